@@ -1,0 +1,274 @@
+/*
+ * rpq.h -- C ABI of the MI355X regular-path-query library (librpq.so).
+ *
+ * What the library computes (cuRPQ paper, arXiv 2602.20748):
+ *
+ *   RPQ (Section 2.1, Definition 1): for a labelled directed graph G and a
+ *   regular expression rho over its edge labels, the set of distinct vertex
+ *   pairs (x, y) joined by a walk x -> ... -> y whose label word is in L(rho).
+ *   Walks of any length count, including the zero-length walk (x, x) when the
+ *   empty word is in L(rho).  Evaluation follows the automata-based approach
+ *   of Section 2.2: a search over the product of G and an automaton for rho,
+ *   keeping one visited set of (vertex, state) pairs per source vertex; a pair
+ *   is emitted when a final state is reached.
+ *
+ *   CRPQ (Section 2.1, Definition 2): all homomorphisms f from the query
+ *   variables to vertices such that labelled variables map to vertices with
+ *   that label and every atom x -rho-> y holds for (f(x), f(y)); the atom
+ *   results are computed first and then joined (Section 6.2).
+ *
+ * Conventions for every entry point:
+ *   - Return value: RPQ_OK (0) or a negative rpq_status.  rpq_last_error()
+ *     returns a thread-local message for the last failing call.  No C++
+ *     exception crosses this boundary.
+ *   - "device" pointers are HIP device memory of the current device (for
+ *     example torch tensors); "host" pointers are ordinary host memory.  The
+ *     library never frees memory it did not allocate.
+ *   - Every call that launches work takes the hipStream_t it runs on.
+ *     Calls that return values in host structs synchronise that stream
+ *     before returning.
+ *   - Inputs are validated before any traversal kernel runs; invalid input
+ *     yields RPQ_EINVAL and leaves outputs untouched.
+ *   - A graph handle may be used from one host thread at a time.
+ */
+#ifndef RPQ_H
+#define RPQ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RPQ_ABI_VERSION 1
+
+/* Automata are epsilon-free NFAs with at most this many states, over at most
+ * this many edge labels (labels are uint8 ids below n_labels). */
+#define RPQ_MAX_STATES 32
+#define RPQ_MAX_LABELS 64
+
+typedef enum {
+    RPQ_OK = 0,
+    RPQ_EINVAL = -1,       /* bad argument: label >= n_labels, vertex >= n_vertices, unsorted sources ... */
+    RPQ_ENOMEM = -2,       /* workspace too small, or a device allocation failed */
+    RPQ_EOVERFLOW = -3,    /* output capacity too small; see rpq_result */
+    RPQ_EDEVICE = -4,      /* a HIP call failed; the message carries the HIP error string */
+    RPQ_EUNSUPPORTED = -5  /* valid request the library does not support (e.g. > 32 states) */
+} rpq_status;
+
+/* Thread-local message describing the last failure on this thread ("" if none). */
+const char* rpq_last_error(void);
+
+/* RPQ_ABI_VERSION of the loaded library. */
+int rpq_abi_version(void);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Graph                                                                                      */
+/* ------------------------------------------------------------------------------------------ */
+
+/* rpq_graph_create flags */
+#define RPQ_BUILD_IN_CSR 1u    /* also build the in-edge CSR (reverse traversal, CRPQ atoms
+                                  whose target is fixed) */
+
+typedef struct rpq_graph* rpq_graph_t;   /* opaque; owned by the library */
+
+typedef struct {
+    uint32_t n_vertices;
+    uint32_t n_labels;
+    uint64_t n_edges_in;                         /* edges passed to rpq_graph_create */
+    uint64_t n_edges;                            /* distinct (src, label, dst) triples kept */
+    uint64_t edges_per_label[RPQ_MAX_LABELS];
+    uint64_t nonempty_rows;                      /* (vertex, label) pairs with >= 1 out-edge */
+    uint64_t device_bytes;                       /* device memory held by the graph */
+    uint32_t has_in_csr;
+    uint32_t has_vertex_labels;
+} rpq_graph_info;
+
+/*
+ * Build the label-partitioned CSR of a graph (the per-label adjacency of the
+ * paper's Labeled Grid Format, Section 2.4, kept as one CSR whose rows are
+ * (vertex, label) pairs).
+ *
+ * src, label, dst: device arrays of n_edges entries (uint32 vertex ids below
+ *   n_vertices, uint8 label ids below n_labels).  Identical triples are
+ *   collapsed (the edge relation is a set); self-loops are kept.
+ * vertex_label: device array of n_vertices uint8 vertex labels, or NULL.
+ * n_vertices: 1 .. 2^31; n_labels: 1 .. RPQ_MAX_LABELS;
+ *   n_vertices * n_labels must stay below 2^32 and distinct edges below 2^32.
+ * flags: RPQ_BUILD_IN_CSR or 0.
+ * On success *out receives a handle that owns its device memory until
+ * rpq_graph_destroy.  The input arrays are not retained.  Allocates device
+ * memory (the only entry point besides rpq_batch_create that does).
+ * Errors: RPQ_EINVAL for out-of-range ids or sizes, RPQ_ENOMEM, RPQ_EDEVICE.
+ */
+int rpq_graph_create(const uint32_t* src, const uint8_t* label, const uint32_t* dst,
+                     uint64_t n_edges, uint32_t n_vertices, uint32_t n_labels,
+                     const uint8_t* vertex_label, uint32_t flags, hipStream_t stream,
+                     rpq_graph_t* out);
+
+/* Release a graph and its device memory (synchronises the device). */
+int rpq_graph_destroy(rpq_graph_t g);
+
+/* Sizes of a graph (host struct). */
+int rpq_graph_info_get(rpq_graph_t g, rpq_graph_info* out);
+
+/*
+ * Copy the CSR out (device buffers supplied by the caller; any may be NULL):
+ *   row_ptr[n_vertices * n_labels + 1] (uint32): edges of vertex v with label l
+ *     are dst[row_ptr[v * n_labels + l] .. row_ptr[v * n_labels + l + 1]),
+ *     ascending;
+ *   dst[n_edges] (uint32).
+ * reverse != 0 copies the in-edge CSR (row = (dst, label), entries = src).
+ */
+int rpq_graph_export_csr(rpq_graph_t g, int reverse, uint32_t* row_ptr, uint32_t* dst,
+                         hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Automaton                                                                                  */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * An epsilon-free NFA.  delta[q * RPQ_MAX_LABELS + l] is the bitmask of
+ * states reachable from state q on label l; entries for q >= n_states or
+ * l >= n_labels must be 0.  initial_mask and final_mask are state bitmasks.
+ * Host memory.  This plays the role of the paper's automata plan
+ * (Section 2.2, Figure 2(a)).
+ */
+typedef struct {
+    uint32_t n_states;
+    uint32_t n_labels;
+    uint32_t initial_mask;
+    uint32_t final_mask;
+    uint32_t delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];
+} rpq_nfa;
+
+/*
+ * Compile a query string into the Glushkov position automaton: state 0 plus
+ * one state per label occurrence, so a.b.c* has 4 states.  Syntax:
+ *   alt := cat ('|' cat)*        (the paper writes alternation as infix '+')
+ *   cat := post (('.' | U+00B7)? post)*
+ *   post := atom ('*' | '+' | '?')*       ('+' = one or more, '?' = optional)
+ *   atom := LABEL | '(' alt ')'
+ * Labels are matched longest-first against label_names[0..n_labels), so
+ * "abc*" over names {a, b, c} is a.b.c*.
+ * regex, label_names: host NUL-terminated strings.  out: host.
+ * Errors: RPQ_EINVAL (syntax, unknown label), RPQ_EUNSUPPORTED (> 31 label
+ * occurrences).
+ */
+int rpq_nfa_compile(const char* regex, const char* const* label_names, uint32_t n_labels,
+                    rpq_nfa* out);
+
+/* The automaton of the reversed language: transitions flipped, initial and
+ * final masks swapped (WavePlan's reverse plan, Section 2.3).  Host. */
+int rpq_nfa_reverse(const rpq_nfa* in, rpq_nfa* out);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Plain evaluation: one query, one source set                                                */
+/* ------------------------------------------------------------------------------------------ */
+
+/* rpq_eval flags */
+#define RPQ_PAIRS        1u   /* write result keys (src << 32) | dst, ascending */
+#define RPQ_PER_SOURCE   2u   /* write per-source {count, hash} */
+#define RPQ_ALL_SOURCES  4u   /* sources == NULL: every vertex 0 .. n_vertices-1 */
+#define RPQ_REVERSE      8u   /* walk in-edges with the reversed automaton: for each given
+                                 vertex y, the x with (x, y) in R(rho); keys are (y << 32) | x */
+
+/* Tuning knobs; zero fields take defaults (the autotuner's choice when one is cached). */
+typedef struct {
+    uint32_t batch_width;    /* sources per unit, one of 64, 128, 256, 512, 1024 */
+    uint32_t concurrency;    /* units advanced together */
+    uint32_t sync_every;     /* levels launched between host checks for the fixpoint */
+    uint32_t chunk_edges;    /* edges per expansion work item */
+} rpq_eval_opts;
+
+/*
+ * Result of rpq_eval (host struct).
+ *   pairs, capacity: device buffer for keys, or NULL for counts only.  Keys
+ *     with global index in [pair_offset, pair_offset + capacity) are written
+ *     to pairs[index - pair_offset]; keys are sorted ascending by
+ *     (source position, dst).
+ *   per_source: device uint64 [n_sources][2] = {count, hash}, or NULL.
+ * Out fields: written (keys stored), count (= |R|), hash (sum over keys of
+ *   SplitMix64-output(key) mod 2^64), product_edges (sum over reached
+ *   (vertex, state) pairs of sum_l deg_l(v) * |delta(q, l)|, summed over
+ *   sources), levels (expansion rounds run), max_depth (longest first-reach
+ *   distance in the product graph).
+ * If count > pair_offset + capacity and pairs != NULL the call returns
+ * RPQ_EOVERFLOW after filling the buffer; calling again with pair_offset
+ * advanced by capacity continues the same sorted sequence.
+ */
+typedef struct {
+    uint64_t* pairs;
+    uint64_t capacity;
+    uint64_t* per_source;
+    uint64_t pair_offset;
+    uint64_t written;
+    uint64_t count;
+    uint64_t hash;
+    uint64_t product_edges;
+    uint64_t levels;
+    uint64_t max_depth;
+} rpq_result;
+
+/* Device workspace bytes rpq_eval needs for this query shape. */
+int rpq_eval_workspace_size(rpq_graph_t g, const rpq_nfa* nfa, uint64_t n_sources,
+                            uint32_t flags, const rpq_eval_opts* opts, uint64_t* bytes);
+
+/*
+ * Evaluate one RPQ from a source set (all-pairs when RPQ_ALL_SOURCES, a slice
+ * or a single vertex otherwise; Section 1 distinguishes the all-pairs and
+ * single-source forms).
+ *
+ * sources: device uint32 [n_sources], strictly ascending, each < n_vertices;
+ *   NULL with RPQ_ALL_SOURCES (then n_sources must equal n_vertices).
+ * workspace: device memory of at least rpq_eval_workspace_size bytes, 256-byte
+ *   aligned, owned by the caller; its contents on entry do not matter.
+ * Sources are processed in units of batch_width sources, concurrency units at a
+ * time; every unit runs its level-synchronous search to the fixpoint (no hop
+ * bound).  Synchronises the stream before returning.
+ * Errors: RPQ_EINVAL, RPQ_ENOMEM (workspace too small), RPQ_EOVERFLOW,
+ * RPQ_EUNSUPPORTED (RPQ_REVERSE on a graph without in-CSR), RPQ_EDEVICE.
+ */
+int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources,
+             uint32_t flags, const rpq_eval_opts* opts, void* workspace, uint64_t workspace_bytes,
+             rpq_result* result, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Profiling of the traversal kernels                                                         */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * Process-wide counters of the level kernels, accumulated over rpq_eval
+ * calls while enabled (host struct).  Durations come from HIP events
+ * recorded on the caller's stream around each launch; the work counts are
+ * exact device-side tallies of the expansion kernel:
+ *   edge_items    (entry, edge) pairs expanded (each reads one 4-byte neighbour id)
+ *   descriptors   16-byte work descriptors read
+ *   row_words     8-byte frontier words read (one per descriptor and word)
+ *   word_reads    8-byte visited words read (frontier word != 0, per successor state)
+ *   word_updates  8-byte atomic ORs into the next-frontier bitmap
+ */
+typedef struct {
+    uint64_t expand_launches;
+    double expand_ms;
+    uint64_t finalize_launches;
+    double finalize_ms;
+    uint64_t edge_items;
+    uint64_t descriptors;
+    uint64_t row_words;
+    uint64_t word_reads;
+    uint64_t word_updates;
+} rpq_profile;
+
+/* Turn event timing of the level kernels on (1) or off (0).  Process-wide. */
+int rpq_profile_enable(int on);
+
+/* Copy the accumulated counters to *out (host); reset them when reset != 0. */
+int rpq_profile_read(rpq_profile* out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPQ_H */

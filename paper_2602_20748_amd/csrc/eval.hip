@@ -1,0 +1,983 @@
+// Plain RPQ evaluation: multi-source, level-synchronous search of the product
+// of the graph and an epsilon-free NFA, to the fixpoint.
+//
+// Semantics (Definition 1 with the automata-based evaluation of Section 2.2):
+// from each source s the search reaches product vertices (v, q); reaching a
+// final q at v puts (s, v) in the result.  A visited set of (vertex, state)
+// pairs per source keeps every product vertex expanded once per source.
+//
+// Bit-parallel layout.  Sources are taken W = 64*K at a time (a "unit", the
+// counterpart of the paper's start-vertex batch, Section 4.1).  For a unit,
+// every product vertex (q, v) owns a row of K 64-bit words; bit i of word k
+// stands for source 64*k + i.  Per unit:
+//   Vis [Q][V][K]  bits already reached (the per-source visited sets)
+//   Next[Q][V][K]  bits reached in the level being expanded
+//   Touch[Q][V]    1 while (q, v) already sits on the next frontier list
+//   Ans [V][K]     bits of result pairs (s_i, v)
+// G units advance together; their rows are tagged by a slot id.
+//
+// One level = two kernels:
+//   expand    reads work descriptors (entry, label, edge range), and for each
+//             edge v -l-> w and successor q' in delta(q, l) ORs the entry's
+//             frontier bits that are new for (q', w) into Next; the first
+//             writer of a row appends (slot, q', w) to the next list.
+//   finalize  for each new entry moves Next into a compact frontier row,
+//             ORs it into Vis (and into Ans when q' is final), counts the
+//             product edges it will examine, and cuts its out-edges per label
+//             into work descriptors of at most H edges (edge-balanced work
+//             for the next expand, whatever the degree skew).
+// The fixpoint is reached when a level appends nothing; the host checks the
+// list counter every few levels (no hop bound).
+//
+// Extraction walks Ans: per source its count and checksum, and optionally the
+// result keys (s << 32) | v written source-major with ascending v, so the
+// output is sorted and distinct by construction.
+#include "internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+// counters[] slots (uint64)
+constexpr int C_LIST = 0;       // [0..1] list length per parity
+constexpr int C_DESC = 2;       // [2..3] descriptor count per parity
+constexpr int C_EPROD = 4;      // product edges examined
+constexpr int C_LEVELS = 5;     // non-empty frontier generations
+constexpr int C_ERR = 6;        // capacity / validation error flags
+constexpr int C_PAIRBASE = 7;   // global key index where the current group starts
+constexpr int C_COUNT = 8;
+constexpr int C_HASH = 9;
+constexpr int C_ITEMS = 10;     // expansion work tallies (profiling)
+constexpr int C_DESCS = 11;
+constexpr int C_ROWW = 12;
+constexpr int C_WREAD = 13;
+constexpr int C_WUPD = 14;
+constexpr int C_NCOUNTERS = 16;
+
+constexpr uint64_t ERR_LIST = 1, ERR_DESC = 2, ERR_SOURCES = 4;
+
+struct Desc {
+    uint32_t entry, beg, len, label;
+};
+
+struct DevNfa {
+    uint32_t Q, L, init, final;
+    uint64_t qlab[RPQ_MAX_STATES];                   // labels with a transition out of q
+    uint32_t delta[RPQ_MAX_STATES * RPQ_MAX_LABELS]; // compact [q * L + l]
+};
+
+struct Args {
+    const uint32_t* row_ptr;
+    const uint32_t* dst;
+    const uint64_t* lmask;
+    const DevNfa* nfa;
+    uint64_t* vis;
+    uint64_t* next;
+    uint32_t* touch;
+    uint64_t* ans;
+    uint64_t* idx0;
+    uint64_t* idx1;
+    uint64_t* rows0;
+    uint64_t* rows1;
+    Desc* desc0;
+    Desc* desc1;
+    unsigned long long* counters;
+    uint32_t V, L, Q, H;
+    uint64_t list_cap, desc_cap;
+};
+
+__device__ __forceinline__ uint64_t* idx_of(const Args& a, int p) { return p ? a.idx1 : a.idx0; }
+__device__ __forceinline__ uint64_t* rows_of(const Args& a, int p) { return p ? a.rows1 : a.rows0; }
+__device__ __forceinline__ Desc* desc_of(const Args& a, int p) { return p ? a.desc1 : a.desc0; }
+
+__device__ __forceinline__ uint64_t pack_entry(uint32_t slot, uint32_t q, uint32_t v) {
+    return ((uint64_t)slot << 40) | ((uint64_t)q << 32) | v;
+}
+
+__device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint64_t* s_qlab, uint32_t* s_final) {
+    const uint32_t QL = a.Q * a.L;
+    for (uint32_t i = threadIdx.x; i < QL; i += kBlock) s_delta[i] = a.nfa->delta[i];
+    if (s_qlab)
+        for (uint32_t i = threadIdx.x; i < a.Q; i += kBlock) s_qlab[i] = a.nfa->qlab[i];
+    if (s_final && threadIdx.x == 0) *s_final = a.nfa->final;
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------------------
+// level expansion
+// ------------------------------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
+    __shared__ uint32_t s_delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];
+    load_nfa(a, s_delta, nullptr, nullptr);
+    const uint64_t n_desc = min((uint64_t)a.counters[C_DESC + p], a.desc_cap);
+    if (n_desc == 0) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
+    const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const uint64_t n_batches = (n_desc + 63) / 64;
+    const Desc* desc = desc_of(a, p);
+    const uint64_t* idx = idx_of(a, p);
+    const uint64_t* rows = rows_of(a, p);
+    uint64_t* out_idx = idx_of(a, p ^ 1);
+    unsigned long long* out_cnt = &a.counters[C_LIST + (p ^ 1)];
+    const uint32_t L = a.L, Q = a.Q, V = a.V;
+    uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0;
+
+    for (uint64_t b = wave; b < n_batches; b += n_waves) {
+        const uint64_t di = b * 64 + lane;
+        uint32_t len = 0, ent = 0, beg = 0, lab = 0;
+        if (di < n_desc) {
+            const Desc d = desc[di];
+            len = d.len;
+            ent = d.entry;
+            beg = d.beg;
+            lab = d.label;
+        }
+        const uint32_t incl = rpqd::wave_incl_scan_u32(len);
+        const uint32_t excl = incl - len;
+        const uint32_t total = __shfl(incl, 63, 64);
+        const uint32_t tasks = total * K;
+        if (lane == 0) {
+            t_items += total;
+            t_descs += (uint64_t)min<uint64_t>(64, n_desc - b * 64);
+        }
+        for (uint32_t base = 0; base < tasks; base += 64) {
+            const uint32_t t = base + lane;
+            const bool active = t < tasks;
+            const uint32_t item = t / K;
+            const uint32_t k = t % K;
+            int c = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int cand = c + step;
+                const uint32_t e = __shfl(excl, cand, 64);
+                if (e <= item) c = cand;
+            }
+            const uint32_t c_ent = __shfl(ent, c, 64);
+            const uint32_t c_beg = __shfl(beg, c, 64);
+            const uint32_t c_lab = __shfl(lab, c, 64);
+            const uint32_t c_ex = __shfl(excl, c, 64);
+            uint32_t app = 0, slot = 0, w = 0;
+            if (active) {
+                w = a.dst[c_beg + (item - c_ex)];
+                const uint64_t pk = idx[c_ent];
+                slot = (uint32_t)(pk >> 40);
+                const uint32_t q = (uint32_t)(pk >> 32) & 0xFF;
+                const uint64_t f = rows[(uint64_t)c_ent * K + k];
+                if (f) {
+                    uint32_t succ = s_delta[q * L + c_lab];
+                    while (succ) {
+                        const uint32_t q2 = __ffs(succ) - 1;
+                        succ &= succ - 1;
+                        const uint64_t row = ((uint64_t)slot * Q + q2) * V + w;
+                        const uint64_t addr = row * K + k;
+                        const uint64_t nb = f & ~a.vis[addr];
+                        ++t_wread;
+                        if (nb) {
+                            ++t_wupd;
+                            const uint64_t old =
+                                atomicOr((unsigned long long*)&a.next[addr], (unsigned long long)nb);
+                            if (old == 0) {
+                                const uint32_t tw = atomicOr(&a.touch[row], 1u);
+                                if (tw == 0) app |= 1u << q2;
+                            }
+                        }
+                    }
+                }
+            }
+            // append first-touched rows to the next list, one counter update per wave round
+            for (;;) {
+                const uint64_t m = __ballot(app != 0);
+                if (m == 0) break;
+                const bool has = app != 0;
+                uint32_t q2 = 0;
+                if (has) {
+                    q2 = __ffs(app) - 1;
+                    app &= app - 1;
+                }
+                const int leader = __ffsll((long long)m) - 1;
+                unsigned long long pos0 = 0;
+                if (lane == leader) pos0 = atomicAdd(out_cnt, (unsigned long long)__popcll(m));
+                pos0 = __shfl(pos0, leader, 64);
+                if (has) {
+                    const uint64_t pos = pos0 + __popcll(m & rpqd::lanemask_lt());
+                    if (pos < a.list_cap) out_idx[pos] = pack_entry(slot, q2, w);
+                    else atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_LIST);
+                }
+            }
+        }
+    }
+    t_items = rpqd::wave_sum_u64(t_items);
+    t_descs = rpqd::wave_sum_u64(t_descs);
+    t_wread = rpqd::wave_sum_u64(t_wread);
+    t_wupd = rpqd::wave_sum_u64(t_wupd);
+    if (lane == 0 && t_items) {
+        atomicAdd(&a.counters[C_ITEMS], (unsigned long long)t_items);
+        atomicAdd(&a.counters[C_DESCS], (unsigned long long)t_descs);
+        atomicAdd(&a.counters[C_ROWW], (unsigned long long)(t_descs * K));
+        atomicAdd(&a.counters[C_WREAD], (unsigned long long)t_wread);
+        atomicAdd(&a.counters[C_WUPD], (unsigned long long)t_wupd);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// finalize the list appended by the last expansion (or by seeding)
+// ------------------------------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
+    __shared__ uint32_t s_delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];
+    __shared__ uint64_t s_qlab[RPQ_MAX_STATES];
+    __shared__ uint32_t s_final;
+    load_nfa(a, s_delta, s_qlab, &s_final);
+    const int np = p ^ 1;
+    const uint64_t n = min((uint64_t)a.counters[C_LIST + np], a.list_cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.counters[C_LIST + p] = 0;
+        a.counters[C_DESC + p] = 0;
+        if (n) atomicAdd(&a.counters[C_LEVELS], 1ull);
+    }
+    if (n == 0) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t* idx = idx_of(a, np);
+    uint64_t* rows = rows_of(a, np);
+    Desc* dout = desc_of(a, np);
+    unsigned long long* dcnt = &a.counters[C_DESC + np];
+    const uint32_t H = a.H, L = a.L, Q = a.Q, V = a.V;
+    const uint32_t fin = s_final;
+    uint64_t eprod = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); e0 < n; e0 += stride) {
+        const uint64_t e = e0 + lane;
+        const bool active = e < n;
+        uint32_t v = 0, q = 0, ndesc = 0;
+        uint64_t m = 0;
+        if (active) {
+            const uint64_t pk = idx[e];
+            const uint32_t slot = (uint32_t)(pk >> 40);
+            q = (uint32_t)(pk >> 32) & 0xFF;
+            v = (uint32_t)pk;
+            const uint64_t row = ((uint64_t)slot * Q + q) * V + v;
+            uint64_t* nx = a.next + row * K;
+            uint64_t* vs = a.vis + row * K;
+            uint64_t* rw = rows + e * K;
+            uint64_t* an = a.ans + ((uint64_t)slot * V + v) * K;
+            const bool is_final = (fin >> q) & 1;
+            uint32_t pc = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint64_t nk = nx[k];
+                rw[k] = nk;
+                if (nk) {
+                    nx[k] = 0;
+                    vs[k] |= nk;
+                    pc += (uint32_t)__popcll(nk);
+                    if (is_final) atomicOr((unsigned long long*)&an[k], (unsigned long long)nk);
+                }
+            }
+            a.touch[row] = 0;
+            m = a.lmask[v] & s_qlab[q];
+            uint64_t wsum = 0;
+            uint64_t mm = m;
+            while (mm) {
+                const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
+                mm &= mm - 1;
+                const uint32_t r = v * L + l;
+                const uint32_t d = a.row_ptr[r + 1] - a.row_ptr[r];
+                wsum += (uint64_t)d * (uint32_t)__popc(s_delta[q * L + l]);
+                ndesc += (d + H - 1) / H;
+            }
+            eprod += (uint64_t)pc * wsum;
+        }
+        const uint32_t incl = rpqd::wave_incl_scan_u32(ndesc);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        if (tot) {
+            unsigned long long dbase = 0;
+            if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)tot);
+            dbase = __shfl(dbase, 0, 64);
+            if (active && ndesc) {
+                uint64_t pos = dbase + incl - ndesc;
+                uint64_t mm = m;
+                while (mm) {
+                    const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
+                    mm &= mm - 1;
+                    const uint32_t r = v * L + l;
+                    const uint32_t b = a.row_ptr[r], d = a.row_ptr[r + 1] - b;
+                    for (uint32_t o = 0; o < d; o += H, ++pos) {
+                        if (pos < a.desc_cap) {
+                            Desc dd;
+                            dd.entry = (uint32_t)e;
+                            dd.beg = b + o;
+                            dd.len = min(H, d - o);
+                            dd.label = l;
+                            dout[pos] = dd;
+                        } else {
+                            atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_DESC);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    eprod = rpqd::wave_sum_u64(eprod);
+    if (lane == 0 && eprod) atomicAdd(&a.counters[C_EPROD], (unsigned long long)eprod);
+}
+
+// ------------------------------------------------------------------------------------------------
+// seeding: (q0, s_i) for every initial state q0 and every source of the group
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_seed(Args a, const uint32_t* __restrict__ sources,
+                                                 uint64_t n_sources, uint64_t group_base, uint32_t G,
+                                                 uint32_t W, uint32_t K) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (uint64_t)G * W) return;
+    const uint64_t gi = group_base + i;
+    if (gi >= n_sources) return;
+    const uint32_t slot = (uint32_t)(i / W), j = (uint32_t)(i % W);
+    const uint32_t s = sources ? sources[gi] : (uint32_t)gi;
+    const uint32_t k = j >> 6;
+    const uint64_t bit = 1ull << (j & 63);
+    uint32_t init = a.nfa->init;
+    while (init) {
+        const uint32_t q = __ffs(init) - 1;
+        init &= init - 1;
+        const uint64_t row = ((uint64_t)slot * a.Q + q) * a.V + s;
+        atomicOr((unsigned long long*)&a.next[row * K + k], (unsigned long long)bit);
+        if (atomicOr(&a.touch[row], 1u) == 0) {
+            const unsigned long long pos = atomicAdd(&a.counters[C_LIST + 1], 1ull);
+            if (pos < a.list_cap) a.idx1[pos] = pack_entry(slot, q, s);
+            else atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_LIST);
+        }
+    }
+}
+
+__global__ void k_check_sources(const uint32_t* __restrict__ s, uint64_t n, uint32_t V,
+                                unsigned long long* __restrict__ counters) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t x = s[i];
+        if (x >= V || (i > 0 && s[i - 1] >= x)) atomicOr(&counters[C_ERR], (unsigned long long)ERR_SOURCES);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// extraction
+// ------------------------------------------------------------------------------------------------
+// One wave per (slot, word k, vertex chunk); lane i owns source 64k+i of the slot.
+template <int K, bool WRITE>
+__global__ __launch_bounds__(kBlock) void k_extract(Args a, const uint32_t* __restrict__ sources,
+                                                    uint64_t n_sources, uint64_t group_base, uint32_t G,
+                                                    uint32_t W, uint32_t nchunks, uint32_t chunk_v,
+                                                    unsigned long long* __restrict__ acc,
+                                                    uint32_t* __restrict__ partial,
+                                                    const uint64_t* __restrict__ srcbase,
+                                                    uint64_t* __restrict__ pairs, uint64_t pair_off,
+                                                    uint64_t capacity) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
+    const uint64_t total = (uint64_t)G * K * nchunks;
+    const uint32_t V = a.V;
+    for (uint64_t wv = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); wv < total; wv += n_waves) {
+        const uint32_t chunk = (uint32_t)(wv % nchunks);
+        const uint32_t k = (uint32_t)((wv / nchunks) % K);
+        const uint32_t slot = (uint32_t)(wv / ((uint64_t)nchunks * K));
+        const uint32_t j = k * 64 + lane;
+        const uint64_t si = (uint64_t)slot * W + j;
+        const uint64_t gi = group_base + si;
+        const bool valid = gi < n_sources;
+        const uint64_t s = valid ? (sources ? sources[gi] : gi) : 0;
+        const uint32_t vbeg = chunk * chunk_v;
+        const uint32_t vend = min(V, vbeg + chunk_v);
+        uint64_t cnt = 0, h = 0;
+        uint64_t cursor = 0;
+        if (WRITE && valid) cursor = srcbase[si] + partial[si * nchunks + chunk];
+        for (uint32_t v0 = vbeg; v0 < vend; v0 += 64) {
+            const uint32_t vv = v0 + lane;
+            const uint64_t word = vv < vend ? a.ans[((uint64_t)slot * V + vv) * K + k] : 0;
+            uint64_t any = __ballot(word != 0);
+            while (any) {
+                const int jj = __ffsll((long long)any) - 1;
+                any &= any - 1;
+                const uint64_t wj = __shfl(word, jj, 64);
+                if (valid && ((wj >> lane) & 1)) {
+                    const uint64_t key = (s << 32) | (uint64_t)(v0 + jj);
+                    if (WRITE) {
+                        if (cursor >= pair_off && cursor - pair_off < capacity) pairs[cursor - pair_off] = key;
+                        ++cursor;
+                    } else {
+                        ++cnt;
+                        h += rpqd::mix64(key);
+                    }
+                }
+            }
+        }
+        if (!WRITE && valid) {
+            if (partial) partial[si * nchunks + chunk] = (uint32_t)cnt;
+            if (cnt) {
+                atomicAdd(&acc[2 * si], (unsigned long long)cnt);
+                atomicAdd(&acc[2 * si + 1], (unsigned long long)h);
+            }
+        }
+    }
+}
+
+// One block: per-source results of the group, chunk prefixes, source offsets, totals.
+__global__ __launch_bounds__(1024) void k_group_finish(unsigned long long* __restrict__ counters,
+                                                       const unsigned long long* __restrict__ acc,
+                                                       uint32_t* __restrict__ partial, uint64_t* __restrict__ srcbase,
+                                                       uint64_t* __restrict__ per_source, uint64_t n_sources,
+                                                       uint64_t group_base, uint64_t n_group, uint32_t nchunks) {
+    __shared__ uint64_t s_w[16];
+    __shared__ uint64_t s_carry;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    if (t == 0) s_carry = counters[C_PAIRBASE];
+    uint64_t csum = 0, hsum = 0;
+    __syncthreads();
+    for (uint64_t b0 = 0; b0 < n_group; b0 += 1024) {
+        const uint64_t i = b0 + t;
+        const bool valid = i < n_group && group_base + i < n_sources;
+        const uint64_t c = valid ? acc[2 * i] : 0;
+        const uint64_t h = valid ? acc[2 * i + 1] : 0;
+        csum += c;
+        hsum += h;
+        if (valid && per_source) {
+            per_source[2 * (group_base + i)] = c;
+            per_source[2 * (group_base + i) + 1] = h;
+        }
+        if (srcbase) {
+            if (valid) {
+                uint32_t run = 0;
+                uint32_t* pp = partial + i * nchunks;
+                for (uint32_t ch = 0; ch < nchunks; ++ch) {
+                    const uint32_t x = pp[ch];
+                    pp[ch] = run;
+                    run += x;
+                }
+            }
+            const uint64_t incl = rpqd::wave_incl_scan_u64(c);
+            if (lane == 63) s_w[wv] = incl;
+            __syncthreads();
+            uint64_t pre = s_carry;
+            for (int w = 0; w < wv; ++w) pre += s_w[w];
+            if (valid) srcbase[i] = pre + incl - c;
+            __syncthreads();
+            if (t == 0) {
+                uint64_t tot = 0;
+                for (int w = 0; w < 16; ++w) tot += s_w[w];
+                s_carry += tot;
+            }
+            __syncthreads();
+        }
+    }
+    csum = rpqd::wave_sum_u64(csum);
+    hsum = rpqd::wave_sum_u64(hsum);
+    if (lane == 0) {
+        atomicAdd(&counters[C_COUNT], (unsigned long long)csum);
+        atomicAdd(&counters[C_HASH], (unsigned long long)hsum);
+    }
+    if (srcbase && t == 0) counters[C_PAIRBASE] = s_carry;
+}
+
+// ------------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------------
+struct Layout {
+    uint32_t K, W, G, Q, L, V, H, nchunks, chunk_v, sync_every;
+    uint64_t list_cap, desc_cap;
+    uint64_t off_counters, off_nfa, off_vis, off_next, off_touch, off_ans, off_idx[2], off_rows[2], off_desc[2],
+        off_acc, off_partial, off_srcbase, total;
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+int popc64(uint64_t x) { return __builtin_popcountll(x); }
+
+int validate_nfa(const rpq_graph* g, const rpq_nfa* nfa) {
+    if (!nfa) {
+        rpq::set_error("automaton is NULL");
+        return RPQ_EINVAL;
+    }
+    if (nfa->n_states == 0 || nfa->n_states > RPQ_MAX_STATES) {
+        rpq::set_error("automaton has %u states; 1..%d supported", nfa->n_states, RPQ_MAX_STATES);
+        return nfa->n_states == 0 ? RPQ_EINVAL : RPQ_EUNSUPPORTED;
+    }
+    if (nfa->n_labels == 0 || nfa->n_labels > g->L) {
+        rpq::set_error("automaton has %u labels; the graph has %u", nfa->n_labels, g->L);
+        return RPQ_EINVAL;
+    }
+    const uint32_t smask = nfa->n_states == 32 ? 0xFFFFFFFFu : ((1u << nfa->n_states) - 1);
+    if ((nfa->initial_mask & ~smask) || (nfa->final_mask & ~smask)) {
+        rpq::set_error("initial/final mask names states >= n_states");
+        return RPQ_EINVAL;
+    }
+    for (uint32_t q = 0; q < RPQ_MAX_STATES; ++q)
+        for (uint32_t l = 0; l < RPQ_MAX_LABELS; ++l) {
+            const uint32_t d = nfa->delta[q * RPQ_MAX_LABELS + l];
+            if (!d) continue;
+            if (q >= nfa->n_states || l >= nfa->n_labels || (d & ~smask)) {
+                rpq::set_error("delta[%u][%u] is outside the automaton", q, l);
+                return RPQ_EINVAL;
+            }
+        }
+    return RPQ_OK;
+}
+
+void to_dev_nfa(const rpq_nfa* nfa, uint32_t L, DevNfa* d) {
+    std::memset(d, 0, sizeof *d);
+    d->Q = nfa->n_states;
+    d->L = L;
+    d->init = nfa->initial_mask;
+    d->final = nfa->final_mask;
+    for (uint32_t q = 0; q < nfa->n_states; ++q)
+        for (uint32_t l = 0; l < L; ++l) {
+            const uint32_t m = l < nfa->n_labels ? nfa->delta[q * RPQ_MAX_LABELS + l] : 0;
+            d->delta[q * L + l] = m;
+            if (m) d->qlab[q] |= 1ull << l;
+        }
+}
+
+uint32_t default_width(uint64_t n_sources) {
+    if (n_sources <= 64) return 64;
+    if (n_sources <= 128) return 128;
+    if (n_sources <= 256) return 256;
+    return 512;
+}
+
+int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32_t flags,
+                const rpq_eval_opts* o, Layout* Lo) {
+    const rpq::Csr& csr = (flags & RPQ_REVERSE) ? g->in : g->out;
+    Layout x;
+    std::memset(&x, 0, sizeof x);
+    x.Q = dn.Q;
+    x.L = g->L;
+    x.V = g->V;
+    x.W = (o && o->batch_width) ? o->batch_width : default_width(n_sources);
+    if (x.W != 64 && x.W != 128 && x.W != 256 && x.W != 512 && x.W != 1024) {
+        rpq::set_error("batch_width must be 64, 128, 256, 512 or 1024");
+        return RPQ_EINVAL;
+    }
+    x.K = x.W / 64;
+    x.H = (o && o->chunk_edges) ? o->chunk_edges : 64;
+    if (x.H > 65535) {
+        rpq::set_error("chunk_edges must be <= 65535");
+        return RPQ_EINVAL;
+    }
+    x.sync_every = (o && o->sync_every) ? o->sync_every : 4;
+    const uint64_t units = std::max<uint64_t>(1, (n_sources + x.W - 1) / x.W);
+    const uint64_t QV = (uint64_t)x.Q * x.V;
+    const uint64_t bitmap_bytes = QV * x.K * 8;
+    uint64_t G = (o && o->concurrency) ? o->concurrency : 0;
+    if (!G) {
+        // keep the two per-unit bitmaps of a group within ~512 MB (cache-sized
+        // working sets on small graphs), at least one unit
+        G = std::max<uint64_t>(1, (512ull << 20) / std::max<uint64_t>(1, 2 * bitmap_bytes));
+        G = std::min<uint64_t>(G, 64);
+    }
+    G = std::min<uint64_t>(G, units);
+    if (G > (1u << 23)) G = 1u << 23;
+    x.G = (uint32_t)G;
+    x.list_cap = G * QV;
+    if (x.list_cap >= 0xFFFFFFFFull) {
+        rpq::set_error("concurrency * states * vertices must stay below 2^32; lower concurrency");
+        return RPQ_EUNSUPPORTED;
+    }
+    uint64_t dper = 0;
+    for (uint32_t q = 0; q < x.Q; ++q) {
+        const uint64_t rows_q = std::min<uint64_t>((uint64_t)x.V * popc64(dn.qlab[q]), csr.nonempty_rows);
+        dper += rows_q + (g->E + x.H - 1) / x.H + 1;
+    }
+    x.desc_cap = G * dper;
+    x.chunk_v = 4096;
+    x.nchunks = (uint32_t)((x.V + x.chunk_v - 1) / x.chunk_v);
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o2 = off;
+        off = align256(off + bytes);
+        return o2;
+    };
+    x.off_counters = take(C_NCOUNTERS * 8);
+    x.off_nfa = take(sizeof(DevNfa));
+    x.off_vis = take(G * bitmap_bytes);
+    x.off_next = take(G * bitmap_bytes);
+    x.off_touch = take(G * QV * 4);
+    x.off_ans = take(G * (uint64_t)x.V * x.K * 8);
+    for (int p = 0; p < 2; ++p) {
+        x.off_idx[p] = take(x.list_cap * 8);
+        x.off_rows[p] = take(x.list_cap * x.K * 8);
+        x.off_desc[p] = take(x.desc_cap * sizeof(Desc));
+    }
+    x.off_acc = take(G * x.W * 16);
+    const bool want_pairs = (flags & RPQ_PAIRS) != 0;
+    x.off_partial = take(want_pairs ? G * x.W * (uint64_t)x.nchunks * 4 : 0);
+    x.off_srcbase = take(want_pairs ? G * x.W * 8 : 0);
+    x.total = off;
+    *Lo = x;
+    return RPQ_OK;
+}
+
+Args make_args(const rpq_graph* g, uint32_t flags, const Layout& x, char* ws) {
+    const rpq::Csr& csr = (flags & RPQ_REVERSE) ? g->in : g->out;
+    Args a;
+    a.row_ptr = csr.row_ptr;
+    a.dst = csr.dst;
+    a.lmask = csr.lmask;
+    a.nfa = reinterpret_cast<const DevNfa*>(ws + x.off_nfa);
+    a.vis = reinterpret_cast<uint64_t*>(ws + x.off_vis);
+    a.next = reinterpret_cast<uint64_t*>(ws + x.off_next);
+    a.touch = reinterpret_cast<uint32_t*>(ws + x.off_touch);
+    a.ans = reinterpret_cast<uint64_t*>(ws + x.off_ans);
+    a.idx0 = reinterpret_cast<uint64_t*>(ws + x.off_idx[0]);
+    a.idx1 = reinterpret_cast<uint64_t*>(ws + x.off_idx[1]);
+    a.rows0 = reinterpret_cast<uint64_t*>(ws + x.off_rows[0]);
+    a.rows1 = reinterpret_cast<uint64_t*>(ws + x.off_rows[1]);
+    a.desc0 = reinterpret_cast<Desc*>(ws + x.off_desc[0]);
+    a.desc1 = reinterpret_cast<Desc*>(ws + x.off_desc[1]);
+    a.counters = reinterpret_cast<unsigned long long*>(ws + x.off_counters);
+    a.V = x.V;
+    a.L = x.L;
+    a.Q = x.Q;
+    a.H = x.H;
+    a.list_cap = x.list_cap;
+    a.desc_cap = x.desc_cap;
+    return a;
+}
+
+constexpr unsigned kLevelGrid = 2048;
+
+// Process-wide profiling state: event pairs around level kernels, resolved at
+// the host synchronisation points of rpq_eval.
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    rpq_profile acc{};
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pend_expand, pend_finalize;
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // caller holds mu and has synchronised the stream the events were recorded on
+    void resolve() {
+        for (int which = 0; which < 2; ++which) {
+            auto& v = which ? pend_finalize : pend_expand;
+            for (auto& pr : v) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+                    if (which) {
+                        acc.finalize_ms += ms;
+                        acc.finalize_launches++;
+                    } else {
+                        acc.expand_ms += ms;
+                        acc.expand_launches++;
+                    }
+                }
+                pool.push_back(pr.first);
+                pool.push_back(pr.second);
+            }
+            v.clear();
+        }
+    }
+};
+
+Profiler& profiler() {
+    static Profiler* p = new Profiler();
+    return *p;
+}
+
+template <int K>
+int launch_level(const Args& a, int p, hipStream_t s) {
+    Profiler& pr = profiler();
+    const bool on = pr.on;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (on) {
+        std::lock_guard<std::mutex> lk(pr.mu);
+        e0 = pr.get();
+        e1 = pr.get();
+        e2 = pr.get();
+    }
+    if (e0) RPQ_HIP(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(k_expand<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
+    RPQ_LAUNCH_CHECK();
+    if (e1) RPQ_HIP(hipEventRecord(e1, s));
+    hipLaunchKernelGGL(k_finalize<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
+    RPQ_LAUNCH_CHECK();
+    if (e2) RPQ_HIP(hipEventRecord(e2, s));
+    if (on && e0 && e1 && e2) {
+        std::lock_guard<std::mutex> lk(pr.mu);
+        pr.pend_expand.emplace_back(e0, e1);
+        pr.pend_finalize.emplace_back(e1, e2);
+    }
+    return RPQ_OK;
+}
+
+void profile_resolve() {
+    Profiler& pr = profiler();
+    std::lock_guard<std::mutex> lk(pr.mu);
+    pr.resolve();
+}
+
+template <int K>
+int launch_finalize(const Args& a, int p, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
+    RPQ_LAUNCH_CHECK();
+    return RPQ_OK;
+}
+
+template <int K>
+int launch_extract(const Args& a, bool write, const uint32_t* sources, uint64_t n_sources, uint64_t group_base,
+                   uint32_t G, uint32_t W, uint32_t nchunks, uint32_t chunk_v, unsigned long long* acc,
+                   uint32_t* partial, const uint64_t* srcbase, uint64_t* pairs, uint64_t off, uint64_t cap,
+                   hipStream_t s) {
+    const uint64_t waves = (uint64_t)G * K * nchunks;
+    const unsigned grid = (unsigned)std::min<uint64_t>((waves + kWaves - 1) / kWaves, 16384);
+    if (write)
+        hipLaunchKernelGGL((k_extract<K, true>), dim3(grid), dim3(kBlock), 0, s, a, sources, n_sources, group_base, G,
+                           W, nchunks, chunk_v, acc, partial, srcbase, pairs, off, cap);
+    else
+        hipLaunchKernelGGL((k_extract<K, false>), dim3(grid), dim3(kBlock), 0, s, a, sources, n_sources, group_base,
+                           G, W, nchunks, chunk_v, acc, partial, srcbase, pairs, off, cap);
+    RPQ_LAUNCH_CHECK();
+    return RPQ_OK;
+}
+
+#define RPQ_DISPATCH_K(K, CALL)                                      \
+    switch (K) {                                                     \
+        case 1: { constexpr int KK = 1; CALL; } break;               \
+        case 2: { constexpr int KK = 2; CALL; } break;               \
+        case 4: { constexpr int KK = 4; CALL; } break;               \
+        case 8: { constexpr int KK = 8; CALL; } break;               \
+        case 16: { constexpr int KK = 16; CALL; } break;             \
+        default: rpq::set_error("bad batch width"); return RPQ_EINVAL; \
+    }
+
+int prepare(rpq_graph_t g, const rpq_nfa* nfa_in, uint64_t n_sources, uint32_t flags, const rpq_eval_opts* opts,
+            rpq_nfa* eff, DevNfa* dn, Layout* lay) {
+    if (!g) {
+        rpq::set_error("graph is NULL");
+        return RPQ_EINVAL;
+    }
+    if (flags & ~(RPQ_PAIRS | RPQ_PER_SOURCE | RPQ_ALL_SOURCES | RPQ_REVERSE)) {
+        rpq::set_error("unknown flags 0x%x", flags);
+        return RPQ_EINVAL;
+    }
+    RPQ_TRY(validate_nfa(g, nfa_in));
+    if ((flags & RPQ_REVERSE) && !g->has_in) {
+        rpq::set_error("RPQ_REVERSE needs a graph built with RPQ_BUILD_IN_CSR");
+        return RPQ_EUNSUPPORTED;
+    }
+    if (flags & RPQ_REVERSE) RPQ_TRY(rpq_nfa_reverse(nfa_in, eff));
+    else *eff = *nfa_in;
+    to_dev_nfa(eff, g->L, dn);
+    return make_layout(g, *dn, n_sources, flags, opts, lay);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpq_eval_workspace_size(rpq_graph_t g, const rpq_nfa* nfa, uint64_t n_sources, uint32_t flags,
+                            const rpq_eval_opts* opts, uint64_t* bytes) {
+    rpq::clear_error();
+    if (!bytes) {
+        rpq::set_error("bytes is NULL");
+        return RPQ_EINVAL;
+    }
+    if (g && (flags & RPQ_ALL_SOURCES) && n_sources == 0) n_sources = g->V;
+    rpq_nfa eff;
+    DevNfa dn;
+    Layout lay;
+    RPQ_TRY(prepare(g, nfa, n_sources, flags, opts, &eff, &dn, &lay));
+    *bytes = lay.total;
+    return RPQ_OK;
+}
+
+int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
+             const rpq_eval_opts* opts, void* workspace, uint64_t workspace_bytes, rpq_result* res,
+             hipStream_t stream) {
+    rpq::clear_error();
+    if (!res) {
+        rpq::set_error("result is NULL");
+        return RPQ_EINVAL;
+    }
+    if (g && (flags & RPQ_ALL_SOURCES)) {
+        if (sources) {
+            rpq::set_error("RPQ_ALL_SOURCES requires sources == NULL");
+            return RPQ_EINVAL;
+        }
+        if (n_sources == 0) n_sources = g->V;
+        if (n_sources != g->V) {
+            rpq::set_error("RPQ_ALL_SOURCES requires n_sources == n_vertices");
+            return RPQ_EINVAL;
+        }
+    } else if (n_sources && !sources) {
+        rpq::set_error("sources is NULL");
+        return RPQ_EINVAL;
+    }
+    if ((flags & RPQ_PAIRS) && res->capacity && !res->pairs) {
+        rpq::set_error("RPQ_PAIRS with a NULL pair buffer");
+        return RPQ_EINVAL;
+    }
+    if ((flags & RPQ_PER_SOURCE) && n_sources && !res->per_source) {
+        rpq::set_error("RPQ_PER_SOURCE with a NULL per_source buffer");
+        return RPQ_EINVAL;
+    }
+    rpq_nfa eff;
+    DevNfa dn;
+    Layout x;
+    RPQ_TRY(prepare(g, nfa, n_sources, flags, opts, &eff, &dn, &x));
+    if (!workspace || workspace_bytes < x.total) {
+        rpq::set_error("workspace of %llu bytes is smaller than the %llu bytes needed",
+                       (unsigned long long)workspace_bytes, (unsigned long long)x.total);
+        return RPQ_ENOMEM;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) {
+        rpq::set_error("workspace must be 256-byte aligned");
+        return RPQ_EINVAL;
+    }
+    const bool want_pairs = (flags & RPQ_PAIRS) && res->pairs != nullptr;
+    res->written = res->count = res->hash = res->product_edges = res->levels = res->max_depth = 0;
+    if (n_sources == 0) return RPQ_OK;
+
+    char* ws = reinterpret_cast<char*>(workspace);
+    Args a = make_args(g, flags, x, ws);
+    uint64_t* stage = g->h_stage;
+    RPQ_HIP(hipMemcpyAsync(ws + x.off_nfa, &dn, sizeof dn, hipMemcpyHostToDevice, stream));
+    RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(a.counters), C_NCOUNTERS, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.next, (uint64_t)x.G * x.Q * x.V * x.K, 0, stream));
+    RPQ_TRY(rpq::fill_u32(a.touch, (uint64_t)x.G * x.Q * x.V, 0, stream));
+    if (sources) {
+        hipLaunchKernelGGL(k_check_sources, dim3((unsigned)std::min<uint64_t>((n_sources + 255) / 256, 4096)),
+                           dim3(256), 0, stream, sources, n_sources, x.V, a.counters);
+        RPQ_LAUNCH_CHECK();
+    }
+    RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
+    RPQ_HIP(hipStreamSynchronize(stream));
+    if (stage[C_ERR] & ERR_SOURCES) {
+        rpq::set_error("sources must be strictly ascending vertex ids below n_vertices");
+        return RPQ_EINVAL;
+    }
+
+    const uint64_t per_group = (uint64_t)x.G * x.W;
+    const uint64_t n_groups = (n_sources + per_group - 1) / per_group;
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws + x.off_acc);
+    uint32_t* partial = want_pairs ? reinterpret_cast<uint32_t*>(ws + x.off_partial) : nullptr;
+    uint64_t* srcbase = want_pairs ? reinterpret_cast<uint64_t*>(ws + x.off_srcbase) : nullptr;
+    uint64_t levels_before = 0, max_depth = 0;
+    for (uint64_t grp = 0; grp < n_groups; ++grp) {
+        const uint64_t gbase = grp * per_group;
+        const uint64_t n_here = std::min<uint64_t>(per_group, n_sources - gbase);
+        const uint32_t G_eff = (uint32_t)((n_here + x.W - 1) / x.W);
+        RPQ_TRY(rpq::fill_u64(a.vis, (uint64_t)G_eff * x.Q * x.V * x.K, 0, stream));
+        RPQ_TRY(rpq::fill_u64(a.ans, (uint64_t)G_eff * x.V * x.K, 0, stream));
+        RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(acc), (uint64_t)G_eff * x.W * 2, 0, stream));
+        hipLaunchKernelGGL(k_seed, dim3((unsigned)(((uint64_t)G_eff * x.W + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           stream, a, sources, n_sources, gbase, G_eff, x.W, x.K);
+        RPQ_LAUNCH_CHECK();
+        RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_finalize<KK>(a, 0, stream)));
+        int p = 1;
+        // a first-reach distance in the product graph is below Q * V, so the
+        // fixpoint arrives within Q * V + 1 levels; more means a defect
+        const uint64_t level_bound = (uint64_t)x.Q * x.V + 2;
+        uint64_t launched = 0;
+        for (;;) {
+            for (uint32_t s = 0; s < x.sync_every; ++s) {
+                RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_level<KK>(a, p, stream)));
+                p ^= 1;
+            }
+            launched += x.sync_every;
+            RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
+            RPQ_HIP(hipStreamSynchronize(stream));
+            if (profiler().on) profile_resolve();
+            if (stage[C_ERR] & (ERR_LIST | ERR_DESC)) {
+                rpq::set_error("internal capacity exceeded (flags 0x%llx)", (unsigned long long)stage[C_ERR]);
+                return RPQ_EDEVICE;
+            }
+            if (stage[C_LIST + p] == 0) break;   // the last finalize produced no new entries
+            if (launched > level_bound) {
+                rpq::set_error("no fixpoint after %llu levels", (unsigned long long)launched);
+                return RPQ_EDEVICE;
+            }
+        }
+        const uint64_t lv = stage[C_LEVELS] - levels_before;
+        levels_before = stage[C_LEVELS];
+        if (lv > 0 && lv - 1 > max_depth) max_depth = lv - 1;
+        RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_extract<KK>(a, false, sources, n_sources, gbase, G_eff, x.W, x.nchunks,
+                                                       x.chunk_v, acc, partial, nullptr, nullptr, 0, 0, stream)));
+        hipLaunchKernelGGL(k_group_finish, dim3(1), dim3(1024), 0, stream, a.counters, acc, partial, srcbase,
+                           (flags & RPQ_PER_SOURCE) ? res->per_source : nullptr, n_sources, gbase,
+                           (uint64_t)G_eff * x.W, x.nchunks);
+        RPQ_LAUNCH_CHECK();
+        if (want_pairs) {
+            RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_extract<KK>(a, true, sources, n_sources, gbase, G_eff, x.W, x.nchunks,
+                                                           x.chunk_v, acc, partial, srcbase, res->pairs,
+                                                           res->pair_offset, res->capacity, stream)));
+        }
+    }
+    RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
+    RPQ_HIP(hipStreamSynchronize(stream));
+    {
+        Profiler& pr = profiler();
+        std::lock_guard<std::mutex> lk(pr.mu);
+        if (pr.on) {
+            pr.resolve();
+            pr.acc.edge_items += stage[C_ITEMS];
+            pr.acc.descriptors += stage[C_DESCS];
+            pr.acc.row_words += stage[C_ROWW];
+            pr.acc.word_reads += stage[C_WREAD];
+            pr.acc.word_updates += stage[C_WUPD];
+        }
+    }
+    res->count = stage[C_COUNT];
+    res->hash = stage[C_HASH];
+    res->product_edges = stage[C_EPROD];
+    res->levels = stage[C_LEVELS];
+    res->max_depth = max_depth;
+    if (want_pairs) {
+        const uint64_t avail = res->count > res->pair_offset ? res->count - res->pair_offset : 0;
+        res->written = std::min<uint64_t>(avail, res->capacity);
+        if (avail > res->capacity) {
+            rpq::set_error("result has %llu keys past offset %llu; capacity is %llu",
+                           (unsigned long long)avail, (unsigned long long)res->pair_offset,
+                           (unsigned long long)res->capacity);
+            return RPQ_EOVERFLOW;
+        }
+    }
+    return RPQ_OK;
+}
+
+int rpq_profile_enable(int on) {
+    Profiler& pr = profiler();
+    std::lock_guard<std::mutex> lk(pr.mu);
+    pr.on = on != 0;
+    return RPQ_OK;
+}
+
+int rpq_profile_read(rpq_profile* out, int reset) {
+    rpq::clear_error();
+    if (!out) {
+        rpq::set_error("out is NULL");
+        return RPQ_EINVAL;
+    }
+    Profiler& pr = profiler();
+    std::lock_guard<std::mutex> lk(pr.mu);
+    *out = pr.acc;
+    if (reset) pr.acc = rpq_profile{};
+    return RPQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal declarations of librpq: error plumbing, the graph object, device
+// primitives (fill, scan, radix sort) and wave64 helpers for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/rpq.h"
+
+namespace rpq {
+
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+#define RPQ_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            ::rpq::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),        \
+                             __FILE__, __LINE__);                                          \
+            return RPQ_EDEVICE;                                                            \
+        }                                                                                  \
+    } while (0)
+
+#define RPQ_TRY(expr)                 \
+    do {                              \
+        int rc_ = (expr);             \
+        if (rc_ != RPQ_OK) return rc_; \
+    } while (0)
+
+#define RPQ_LAUNCH_CHECK() RPQ_HIP(hipGetLastError())
+
+// One direction of the label-partitioned CSR.  Row r = v * n_labels + l holds
+// the neighbours of v over label l in dst[row_ptr[r] .. row_ptr[r + 1]),
+// ascending.  lmask[v] has bit l set when row (v, l) is non-empty.
+struct Csr {
+    uint32_t* row_ptr = nullptr;   // [V * L + 1]
+    uint32_t* dst = nullptr;       // [E]
+    uint64_t* lmask = nullptr;     // [V]
+    uint64_t nonempty_rows = 0;
+};
+
+}  // namespace rpq
+
+struct rpq_graph {
+    uint32_t V = 0, L = 0;
+    uint64_t E_in = 0, E = 0;
+    uint64_t per_label[RPQ_MAX_LABELS] = {};
+    rpq::Csr out, in;
+    bool has_in = false;
+    uint8_t* vlabel = nullptr;          // [V] or null
+    uint64_t device_bytes = 0;
+    int device = 0;
+    uint64_t* h_stage = nullptr;        // pinned host staging for small device->host reads
+};
+
+namespace rpq {
+
+// ---- device primitives (prims.hip) ----
+int fill_u64(uint64_t* p, uint64_t n, uint64_t value, hipStream_t s);
+int fill_u32(uint32_t* p, uint64_t n, uint32_t value, hipStream_t s);
+
+// Temporary uint64 elements needed by exclusive_scan_u64 for n inputs.
+uint64_t scan_temp_elems(uint64_t n);
+// out[i] = sum of in[0..i); out may alias in.  If total != nullptr the grand
+// total is written to *total (device).
+int exclusive_scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* temp,
+                       uint64_t* total, hipStream_t s);
+
+// Temporary bytes needed by radix_sort_u64 for n keys.
+uint64_t radix_temp_bytes(uint64_t n);
+// Stable LSD radix sort of n uint64 keys on bits [0, lo_bits) and [32, 32 + hi_bits)
+// (bits outside are assumed zero).  keys and alt are two buffers of n keys;
+// *sorted receives whichever holds the result.
+int radix_sort_u64(uint64_t* keys, uint64_t* alt, uint64_t n, int lo_bits, int hi_bits,
+                   void* temp, hipStream_t s, uint64_t** sorted);
+
+inline int bits_for(uint64_t max_value) {   // bits needed to represent values <= max_value
+    int b = 0;
+    while (b < 64 && (max_value >> b) != 0) ++b;
+    return b;
+}
+
+}  // namespace rpq
+
+// ---- wave64 helpers (device) ----
+namespace rpqd {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = __lane_id();
+    return l == 0 ? 0ull : ((~0ull) >> (64 - l));
+}
+
+// One SplitMix64 output for state x: the per-key checksum.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    const int l = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+    const int l = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t t = __shfl_up(v, o, 64);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        uint32_t t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+}  // namespace rpqd

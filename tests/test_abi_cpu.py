@@ -1,0 +1,116 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+symbol, and its host-side query compiler agrees with the oracle's own
+Glushkov construction (same language, same state count, same transitions).
+No GPU compute is called here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2602_20748_amd as rpq
+from oracle.automata import glushkov, parse
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "rpq.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rpq_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    path = rpq.library_path()
+    if not os.path.exists(path):
+        from paper_2602_20748_amd import build
+        build.build()
+    return rpq.load_library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    declared = header_functions()
+    assert declared, "no declarations parsed"
+    assert sorted(rpq.EXPORTED_SYMBOLS) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert rpq.rpq_abi_version() == 1
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(rpq.Nfa) == 16 + 4 * 32 * 64
+    assert ctypes.sizeof(rpq.EvalOpts) == 16
+
+
+def nfa_as_oracle_shape(nfa):
+    trans = {}
+    for q in range(nfa.n_states):
+        for l in range(nfa.n_labels):
+            m = nfa.successors(q, l)
+            for p in range(32):
+                if m >> p & 1:
+                    trans.setdefault(q, set()).add((l, p))
+    finals = {q for q in range(32) if nfa.final_mask >> q & 1}
+    return nfa.n_states, trans, finals
+
+
+def test_compiler_matches_oracle_glushkov(lib):
+    names = ["a", "b", "c", "d"]
+    rng = np.random.default_rng(123)
+    queries = ["a.b.c*", "a*", "a.b*", "(a|b).c*", "a.b*.c", "(a.b)*", "a?b*", "abcd", "abc*", "(a|b)*"]
+    for _ in range(200):
+        queries.append(synth.random_regex(rng, names))
+    for q in queries:
+        nfa = rpq.rpq_nfa_compile(q, names)
+        g = glushkov(parse(q, names))
+        n, trans, finals = nfa_as_oracle_shape(nfa)
+        assert n == g.n_states, q
+        want = {qq: set(ts) for qq, ts in enumerate(g.trans) if ts}
+        assert trans == want, q
+        assert finals == g.finals, q
+        assert nfa.initial_mask == 1
+
+
+def test_compiler_state_count_abc_star(lib):
+    assert rpq.rpq_nfa_compile("a.b.c*", ["a", "b", "c", "d"]).n_states == 4
+
+
+def test_compiler_multichar_names_and_middle_dot(lib):
+    names = ["knows", "hasCreator", "replyOf", "hasTag"]
+    n1 = rpq.rpq_nfa_compile("knows.knows*", names)
+    n2 = rpq.rpq_nfa_compile("knows·knows*", names)
+    n3 = rpq.rpq_nfa_compile("knows knows*", names)
+    for n in (n2, n3):
+        assert bytes(n) == bytes(n1)
+    assert n1.n_states == 3
+
+
+@pytest.mark.parametrize("bad,code", [("", rpq.RPQ_EINVAL), ("a.(b", rpq.RPQ_EINVAL), ("x", rpq.RPQ_EINVAL),
+                                      ("a|", rpq.RPQ_EINVAL), ("a" * 32, rpq.RPQ_EUNSUPPORTED)])
+def test_compiler_errors(lib, bad, code):
+    with pytest.raises(rpq.RpqError) as ei:
+        rpq.rpq_nfa_compile(bad, ["a", "b"])
+    assert ei.value.code == code
+    assert rpq.rpq_last_error()
+
+
+def test_reverse_automaton(lib):
+    names = ["a", "b", "c"]
+    nfa = rpq.rpq_nfa_compile("a.b*.c", names)
+    r = rpq.rpq_nfa_reverse(nfa)
+    assert r.initial_mask == nfa.final_mask and r.final_mask == nfa.initial_mask
+    for q in range(nfa.n_states):
+        for l in range(3):
+            for p in range(nfa.n_states):
+                assert bool(nfa.successors(q, l) >> p & 1) == bool(r.successors(p, l) >> q & 1)
+    assert bytes(rpq.rpq_nfa_reverse(r)) == bytes(nfa)
+
+
+def test_workspace_size_rejects_null_graph(lib):
+    nfa = rpq.rpq_nfa_compile("a*", ["a"])
+    n = ctypes.c_uint64()
+    rc = lib.rpq_eval_workspace_size(None, ctypes.byref(nfa), 10, 0, None, ctypes.byref(n))
+    assert rc == rpq.RPQ_EINVAL
