@@ -102,17 +102,23 @@ def main():
     per_source = torch.zeros((el.n_vertices, 2), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
 
+    qtimes = {q: 0.0 for q in queries}
+
     def step():
         out = []
         for q in queries:
+            t = time.perf_counter()
             nfa = rpq.rpq_nfa_compile(q, el.names)
             out.append(rpq.rpq_eval(g, nfa, None, opts=opts, per_source=per_source))
+            qtimes[q] += time.perf_counter() - t
         return out
 
     for i in range(args.warmup):
         print("bench: warmup %d" % i, file=sys.stderr, flush=True)
         step()
     torch.cuda.synchronize()
+    for q in queries:
+        qtimes[q] = 0.0
     rpq.rpq_profile_read(reset=True)
     rpq.rpq_profile_enable(True)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -138,6 +144,8 @@ def main():
     prof = rpq.rpq_profile_read(reset=True)
     secs = ev0.elapsed_time(ev1) / 1e3
     ms_per_step = secs * 1e3 / args.steps
+    for q in queries:
+        per_query[q]["ms"] = round(qtimes[q] * 1e3 / max(1, args.steps), 3)
 
     # roofline of the dominant kernel (level expansion): algorithmic bytes per launch
     # = 4 B per edge item + 16 B per descriptor + 8 B per frontier word read
@@ -159,7 +167,9 @@ def main():
                     kernel="k_expand", avg_launch_ms=round(avg_ms, 5), launches=prof["expand_launches"],
                     alg_bytes_per_launch=round(bytes_per_launch, 1),
                     expand_share=round(prof["expand_ms"] / max(1e-9, prof["expand_ms"] + prof["finalize_ms"]), 4),
-                    finalize_avg_ms=round(prof["finalize_ms"] / max(1, prof["finalize_launches"]), 5))
+                    finalize_avg_ms=round(prof["finalize_ms"] / max(1, prof["finalize_launches"]), 5),
+                    counters={k: prof[k] for k in ("edge_items", "descriptors", "row_words", "word_reads",
+                                                   "word_updates", "expand_ms", "finalize_ms")})
     cpu = None
     if args.cpu_baseline_seconds > 0:
         print("bench: cpu baseline", file=sys.stderr, flush=True)

@@ -176,7 +176,7 @@ int rpq_nfa_reverse(const rpq_nfa* in, rpq_nfa* out);
 
 /* Tuning knobs; zero fields take defaults (the autotuner's choice when one is cached). */
 typedef struct {
-    uint32_t batch_width;    /* sources per unit, one of 64, 128, 256, 512, 1024 */
+    uint32_t batch_width;    /* sources per unit: 64, 128, 256, 512, 1024, 2048 or 4096 */
     uint32_t concurrency;    /* units advanced together */
     uint32_t sync_every;     /* levels launched between host checks for the fixpoint */
     uint32_t chunk_edges;    /* edges per expansion work item */

@@ -44,12 +44,12 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kChunk = 8;   // frontier words handled together per edge item
 
 // counters[] slots (uint64)
 constexpr int C_LIST = 0;       // [0..1] list length per parity
 constexpr int C_DESC = 2;       // [2..3] descriptor count per parity
 constexpr int C_EPROD = 4;      // product edges examined
-constexpr int C_LEVELS = 5;     // non-empty frontier generations
 constexpr int C_ERR = 6;        // capacity / validation error flags
 constexpr int C_PAIRBASE = 7;   // global key index where the current group starts
 constexpr int C_COUNT = 8;
@@ -59,12 +59,16 @@ constexpr int C_DESCS = 11;
 constexpr int C_ROWW = 12;
 constexpr int C_WREAD = 13;
 constexpr int C_WUPD = 14;
+constexpr int C_LASTLEVEL = 15; // 1 + highest level index whose finalize appended rows (this group)
 constexpr int C_NCOUNTERS = 16;
 
 constexpr uint64_t ERR_LIST = 1, ERR_DESC = 2, ERR_SOURCES = 4;
 
+// A unit of expansion work: edges [beg, beg + len) of one CSR row (v, label),
+// to be followed from frontier entry `entry` (state q, unit slot).
+// meta = label | q << 8 | slot << 13.
 struct Desc {
-    uint32_t entry, beg, len, label;
+    uint32_t entry, beg, len, meta;
 };
 
 struct DevNfa {
@@ -80,12 +84,12 @@ struct Args {
     const DevNfa* nfa;
     uint64_t* vis;
     uint64_t* next;
-    uint32_t* touch;
+    uint64_t* touch;        // one bit per (slot, q, v) row: row has bits in Next
     uint64_t* ans;
-    uint64_t* idx0;
-    uint64_t* idx1;
     uint64_t* rows0;
     uint64_t* rows1;
+    uint32_t* ids0;         // row ids of the frontier lists (row = (slot * Q + q) * V + v)
+    uint32_t* ids1;
     Desc* desc0;
     Desc* desc1;
     unsigned long long* counters;
@@ -93,12 +97,14 @@ struct Args {
     uint64_t list_cap, desc_cap;
 };
 
-__device__ __forceinline__ uint64_t* idx_of(const Args& a, int p) { return p ? a.idx1 : a.idx0; }
 __device__ __forceinline__ uint64_t* rows_of(const Args& a, int p) { return p ? a.rows1 : a.rows0; }
+__device__ __forceinline__ uint32_t* ids_of(const Args& a, int p) { return p ? a.ids1 : a.ids0; }
 __device__ __forceinline__ Desc* desc_of(const Args& a, int p) { return p ? a.desc1 : a.desc0; }
 
-__device__ __forceinline__ uint64_t pack_entry(uint32_t slot, uint32_t q, uint32_t v) {
-    return ((uint64_t)slot << 40) | ((uint64_t)q << 32) | v;
+// relaxed device-scope OR whose result is unused (no-return atomic)
+__device__ __forceinline__ void or_relaxed(uint64_t* p, uint64_t v) {
+    (void)__hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint64_t* s_qlab, uint32_t* s_final) {
@@ -111,7 +117,7 @@ __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint6
 }
 
 // ------------------------------------------------------------------------------------------------
-// level expansion
+// level expansion: one lane per edge item, each item carrying all K words of its frontier row
 // ------------------------------------------------------------------------------------------------
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
@@ -124,36 +130,30 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
     const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     const uint64_t n_batches = (n_desc + 63) / 64;
     const Desc* desc = desc_of(a, p);
-    const uint64_t* idx = idx_of(a, p);
     const uint64_t* rows = rows_of(a, p);
-    uint64_t* out_idx = idx_of(a, p ^ 1);
-    unsigned long long* out_cnt = &a.counters[C_LIST + (p ^ 1)];
     const uint32_t L = a.L, Q = a.Q, V = a.V;
     uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0;
 
     for (uint64_t b = wave; b < n_batches; b += n_waves) {
         const uint64_t di = b * 64 + lane;
-        uint32_t len = 0, ent = 0, beg = 0, lab = 0;
+        uint32_t len = 0, ent = 0, beg = 0, meta = 0;
         if (di < n_desc) {
             const Desc d = desc[di];
             len = d.len;
             ent = d.entry;
             beg = d.beg;
-            lab = d.label;
+            meta = d.meta;
         }
         const uint32_t incl = rpqd::wave_incl_scan_u32(len);
         const uint32_t excl = incl - len;
         const uint32_t total = __shfl(incl, 63, 64);
-        const uint32_t tasks = total * K;
         if (lane == 0) {
             t_items += total;
             t_descs += (uint64_t)min<uint64_t>(64, n_desc - b * 64);
         }
-        for (uint32_t base = 0; base < tasks; base += 64) {
-            const uint32_t t = base + lane;
-            const bool active = t < tasks;
-            const uint32_t item = t / K;
-            const uint32_t k = t % K;
+        for (uint32_t base = 0; base < total; base += 64) {
+            const uint32_t item = base + lane;
+            // descriptor of this item: the last lane c with excl[c] <= item
             int c = 0;
 #pragma unroll
             for (int step = 32; step >= 1; step >>= 1) {
@@ -163,54 +163,47 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
             }
             const uint32_t c_ent = __shfl(ent, c, 64);
             const uint32_t c_beg = __shfl(beg, c, 64);
-            const uint32_t c_lab = __shfl(lab, c, 64);
+            const uint32_t c_meta = __shfl(meta, c, 64);
             const uint32_t c_ex = __shfl(excl, c, 64);
-            uint32_t app = 0, slot = 0, w = 0;
-            if (active) {
-                w = a.dst[c_beg + (item - c_ex)];
-                const uint64_t pk = idx[c_ent];
-                slot = (uint32_t)(pk >> 40);
-                const uint32_t q = (uint32_t)(pk >> 32) & 0xFF;
-                const uint64_t f = rows[(uint64_t)c_ent * K + k];
-                if (f) {
-                    uint32_t succ = s_delta[q * L + c_lab];
-                    while (succ) {
-                        const uint32_t q2 = __ffs(succ) - 1;
-                        succ &= succ - 1;
-                        const uint64_t row = ((uint64_t)slot * Q + q2) * V + w;
-                        const uint64_t addr = row * K + k;
-                        const uint64_t nb = f & ~a.vis[addr];
-                        ++t_wread;
-                        if (nb) {
-                            ++t_wupd;
-                            const uint64_t old =
-                                atomicOr((unsigned long long*)&a.next[addr], (unsigned long long)nb);
-                            if (old == 0) {
-                                const uint32_t tw = atomicOr(&a.touch[row], 1u);
-                                if (tw == 0) app |= 1u << q2;
+            if (item < total) {
+                const uint32_t w = a.dst[c_beg + (item - c_ex)];
+                const uint32_t lab = c_meta & 0xFF, q = (c_meta >> 8) & 0x1F, slot = c_meta >> 13;
+                uint32_t succ = s_delta[q * L + lab];
+                const uint64_t* fr = rows + (uint64_t)c_ent * K;
+                while (succ) {
+                    const uint32_t q2 = __ffs(succ) - 1;
+                    succ &= succ - 1;
+                    const uint64_t row = ((uint64_t)slot * Q + q2) * V + w;
+                    const uint64_t* vs = a.vis + row * K;
+                    uint64_t* nx = a.next + row * K;
+                    bool any = false;
+                    // frontier and visited words in chunks of up to 8 (registers stay bounded)
+#pragma unroll
+                    for (int k0 = 0; k0 < K; k0 += kChunk) {
+                        uint64_t f[kChunk], vw[kChunk];
+                        uint64_t fany = 0;
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k) {
+                            f[k] = (k0 + k < K) ? fr[k0 + k] : 0;
+                            fany |= f[k];
+                        }
+                        if (!fany) continue;
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k) vw[k] = (k0 + k < K) ? vs[k0 + k] : 0;
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k) {
+                            if (f[k]) {
+                                ++t_wread;
+                                const uint64_t nb = f[k] & ~vw[k];
+                                if (nb) {
+                                    ++t_wupd;
+                                    or_relaxed(&nx[k0 + k], nb);
+                                    any = true;
+                                }
                             }
                         }
                     }
-                }
-            }
-            // append first-touched rows to the next list, one counter update per wave round
-            for (;;) {
-                const uint64_t m = __ballot(app != 0);
-                if (m == 0) break;
-                const bool has = app != 0;
-                uint32_t q2 = 0;
-                if (has) {
-                    q2 = __ffs(app) - 1;
-                    app &= app - 1;
-                }
-                const int leader = __ffsll((long long)m) - 1;
-                unsigned long long pos0 = 0;
-                if (lane == leader) pos0 = atomicAdd(out_cnt, (unsigned long long)__popcll(m));
-                pos0 = __shfl(pos0, leader, 64);
-                if (has) {
-                    const uint64_t pos = pos0 + __popcll(m & rpqd::lanemask_lt());
-                    if (pos < a.list_cap) out_idx[pos] = pack_entry(slot, q2, w);
-                    else atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_LIST);
+                    if (any) or_relaxed(&a.touch[row >> 6], 1ull << (row & 63));
                 }
             }
         }
@@ -229,7 +222,52 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// finalize the list appended by the last expansion (or by seeding)
+// compaction: the rows touched by the last expansion (or by seeding) become the dense list of
+// row ids of the next frontier.  Each wave reads 64 consecutive touch words (one per lane),
+// clears them, and places its rows with one counter update (popcount prefix over the wave).
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_compact(Args a, int p, uint64_t n_rows, uint32_t level) {
+    const int np = p ^ 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the list and descriptors of parity p were consumed by the expansion that just ran
+        a.counters[C_LIST + p] = 0;
+        a.counters[C_DESC + p] = 0;
+    }
+    const int lane = threadIdx.x & 63;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
+    const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const uint64_t n_words = (n_rows + 63) / 64;
+    unsigned long long* lcnt = &a.counters[C_LIST + np];
+    uint32_t* ids = ids_of(a, np);
+    bool appended = false;
+    for (uint64_t w0 = wave * 64; w0 < n_words; w0 += n_waves * 64) {
+        const uint64_t wi = w0 + lane;
+        uint64_t tw = wi < n_words ? a.touch[wi] : 0;
+        if (tw) a.touch[wi] = 0;
+        const uint32_t c = (uint32_t)__popcll(tw);
+        const uint32_t incl = rpqd::wave_incl_scan_u32(c);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        if (tot == 0) continue;
+        appended = true;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(lcnt, (unsigned long long)tot);
+        base = __shfl(base, 0, 64);
+        uint64_t pos = base + incl - c;
+        while (tw) {
+            const int b = __ffsll((long long)tw) - 1;
+            tw &= tw - 1;
+            if (pos < a.list_cap) ids[pos] = (uint32_t)(wi * 64 + b);
+            else atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_LIST);
+            ++pos;
+        }
+    }
+    if (lane == 0 && appended) atomicMax(&a.counters[C_LASTLEVEL], (unsigned long long)level + 1);
+}
+
+// ------------------------------------------------------------------------------------------------
+// finalize: one thread per new frontier row.  Next moves into the compact frontier row, Vis and
+// (for final states) Ans take the new bits, the product edges the row will examine are counted,
+// and its out-edges are cut into descriptors of at most H edges per label.
 // ------------------------------------------------------------------------------------------------
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
@@ -239,32 +277,29 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
     load_nfa(a, s_delta, s_qlab, &s_final);
     const int np = p ^ 1;
     const uint64_t n = min((uint64_t)a.counters[C_LIST + np], a.list_cap);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.counters[C_LIST + p] = 0;
-        a.counters[C_DESC + p] = 0;
-        if (n) atomicAdd(&a.counters[C_LEVELS], 1ull);
-    }
     if (n == 0) return;
     const int lane = threadIdx.x & 63;
-    const uint64_t* idx = idx_of(a, np);
+    const uint32_t* ids = ids_of(a, np);
     uint64_t* rows = rows_of(a, np);
     Desc* dout = desc_of(a, np);
     unsigned long long* dcnt = &a.counters[C_DESC + np];
-    const uint32_t H = a.H, L = a.L, Q = a.Q, V = a.V;
+    const uint32_t H = a.H, L = a.L, V = a.V;
+    const uint32_t QV = a.Q * a.V;
     const uint32_t fin = s_final;
     uint64_t eprod = 0;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t e0 = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); e0 < n; e0 += stride) {
         const uint64_t e = e0 + lane;
         const bool active = e < n;
-        uint32_t v = 0, q = 0, ndesc = 0;
+        uint32_t v = 0, q = 0, slot = 0, ndesc = 0;
         uint64_t m = 0;
         if (active) {
-            const uint64_t pk = idx[e];
-            const uint32_t slot = (uint32_t)(pk >> 40);
-            q = (uint32_t)(pk >> 32) & 0xFF;
-            v = (uint32_t)pk;
-            const uint64_t row = ((uint64_t)slot * Q + q) * V + v;
+            const uint32_t row32 = ids[e];
+            slot = row32 / QV;
+            const uint32_t rem = row32 - slot * QV;
+            q = rem / V;
+            v = rem - q * V;
+            const uint64_t row = row32;
             uint64_t* nx = a.next + row * K;
             uint64_t* vs = a.vis + row * K;
             uint64_t* rw = rows + e * K;
@@ -272,17 +307,24 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
             const bool is_final = (fin >> q) & 1;
             uint32_t pc = 0;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const uint64_t nk = nx[k];
-                rw[k] = nk;
-                if (nk) {
-                    nx[k] = 0;
-                    vs[k] |= nk;
-                    pc += (uint32_t)__popcll(nk);
-                    if (is_final) atomicOr((unsigned long long*)&an[k], (unsigned long long)nk);
+            for (int k0 = 0; k0 < K; k0 += kChunk) {
+                uint64_t nk[kChunk], vk[kChunk];
+#pragma unroll
+                for (int k = 0; k < kChunk; ++k) nk[k] = (k0 + k < K) ? nx[k0 + k] : 0;
+#pragma unroll
+                for (int k = 0; k < kChunk; ++k) vk[k] = (k0 + k < K) ? vs[k0 + k] : 0;
+#pragma unroll
+                for (int k = 0; k < kChunk; ++k) {
+                    if (k0 + k >= K) break;
+                    rw[k0 + k] = nk[k];
+                    if (nk[k]) {
+                        nx[k0 + k] = 0;
+                        vs[k0 + k] = vk[k] | nk[k];
+                        pc += (uint32_t)__popcll(nk[k]);
+                        if (is_final) or_relaxed(&an[k0 + k], nk[k]);
+                    }
                 }
             }
-            a.touch[row] = 0;
             m = a.lmask[v] & s_qlab[q];
             uint64_t wsum = 0;
             uint64_t mm = m;
@@ -305,6 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
             if (active && ndesc) {
                 uint64_t pos = dbase + incl - ndesc;
                 uint64_t mm = m;
+                const uint32_t meta_qs = (q << 8) | (slot << 13);
                 while (mm) {
                     const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
                     mm &= mm - 1;
@@ -316,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
                             dd.entry = (uint32_t)e;
                             dd.beg = b + o;
                             dd.len = min(H, d - o);
-                            dd.label = l;
+                            dd.meta = l | meta_qs;
                             dout[pos] = dd;
                         } else {
                             atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_DESC);
@@ -349,12 +392,8 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args a, const uint32_t* __restr
         const uint32_t q = __ffs(init) - 1;
         init &= init - 1;
         const uint64_t row = ((uint64_t)slot * a.Q + q) * a.V + s;
-        atomicOr((unsigned long long*)&a.next[row * K + k], (unsigned long long)bit);
-        if (atomicOr(&a.touch[row], 1u) == 0) {
-            const unsigned long long pos = atomicAdd(&a.counters[C_LIST + 1], 1ull);
-            if (pos < a.list_cap) a.idx1[pos] = pack_entry(slot, q, s);
-            else atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_LIST);
-        }
+        or_relaxed(&a.next[row * K + k], bit);
+        or_relaxed(&a.touch[row >> 6], 1ull << (row & 63));
     }
 }
 
@@ -492,7 +531,7 @@ __global__ __launch_bounds__(1024) void k_group_finish(unsigned long long* __res
 struct Layout {
     uint32_t K, W, G, Q, L, V, H, nchunks, chunk_v, sync_every;
     uint64_t list_cap, desc_cap;
-    uint64_t off_counters, off_nfa, off_vis, off_next, off_touch, off_ans, off_idx[2], off_rows[2], off_desc[2],
+    uint64_t off_counters, off_nfa, off_vis, off_next, off_touch, off_ans, off_ids[2], off_rows[2], off_desc[2],
         off_acc, off_partial, off_srcbase, total;
 };
 
@@ -560,8 +599,8 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     x.L = g->L;
     x.V = g->V;
     x.W = (o && o->batch_width) ? o->batch_width : default_width(n_sources);
-    if (x.W != 64 && x.W != 128 && x.W != 256 && x.W != 512 && x.W != 1024) {
-        rpq::set_error("batch_width must be 64, 128, 256, 512 or 1024");
+    if (x.W != 64 && x.W != 128 && x.W != 256 && x.W != 512 && x.W != 1024 && x.W != 2048 && x.W != 4096) {
+        rpq::set_error("batch_width must be 64, 128, 256, 512, 1024, 2048 or 4096");
         return RPQ_EINVAL;
     }
     x.K = x.W / 64;
@@ -582,7 +621,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
         G = std::min<uint64_t>(G, 64);
     }
     G = std::min<uint64_t>(G, units);
-    if (G > (1u << 23)) G = 1u << 23;
+    if (G > (1u << 19)) G = 1u << 19;   // slot ids travel in 19 bits of a descriptor
     x.G = (uint32_t)G;
     x.list_cap = G * QV;
     if (x.list_cap >= 0xFFFFFFFFull) {
@@ -607,10 +646,10 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     x.off_nfa = take(sizeof(DevNfa));
     x.off_vis = take(G * bitmap_bytes);
     x.off_next = take(G * bitmap_bytes);
-    x.off_touch = take(G * QV * 4);
+    x.off_touch = take((G * QV + 63) / 64 * 8);
     x.off_ans = take(G * (uint64_t)x.V * x.K * 8);
     for (int p = 0; p < 2; ++p) {
-        x.off_idx[p] = take(x.list_cap * 8);
+        x.off_ids[p] = take(x.list_cap * 4);
         x.off_rows[p] = take(x.list_cap * x.K * 8);
         x.off_desc[p] = take(x.desc_cap * sizeof(Desc));
     }
@@ -632,10 +671,10 @@ Args make_args(const rpq_graph* g, uint32_t flags, const Layout& x, char* ws) {
     a.nfa = reinterpret_cast<const DevNfa*>(ws + x.off_nfa);
     a.vis = reinterpret_cast<uint64_t*>(ws + x.off_vis);
     a.next = reinterpret_cast<uint64_t*>(ws + x.off_next);
-    a.touch = reinterpret_cast<uint32_t*>(ws + x.off_touch);
+    a.touch = reinterpret_cast<uint64_t*>(ws + x.off_touch);
     a.ans = reinterpret_cast<uint64_t*>(ws + x.off_ans);
-    a.idx0 = reinterpret_cast<uint64_t*>(ws + x.off_idx[0]);
-    a.idx1 = reinterpret_cast<uint64_t*>(ws + x.off_idx[1]);
+    a.ids0 = reinterpret_cast<uint32_t*>(ws + x.off_ids[0]);
+    a.ids1 = reinterpret_cast<uint32_t*>(ws + x.off_ids[1]);
     a.rows0 = reinterpret_cast<uint64_t*>(ws + x.off_rows[0]);
     a.rows1 = reinterpret_cast<uint64_t*>(ws + x.off_rows[1]);
     a.desc0 = reinterpret_cast<Desc*>(ws + x.off_desc[0]);
@@ -686,8 +725,14 @@ struct Profiler {
                         acc.expand_launches++;
                     }
                 }
-                pool.push_back(pr.first);
-                pool.push_back(pr.second);
+                // the expansion's end event is also the finalize's start event:
+                // return each event to the pool exactly once
+                if (which) {
+                    pool.push_back(pr.first);
+                    pool.push_back(pr.second);
+                } else {
+                    pool.push_back(pr.first);
+                }
             }
             v.clear();
         }
@@ -700,7 +745,7 @@ Profiler& profiler() {
 }
 
 template <int K>
-int launch_level(const Args& a, int p, hipStream_t s) {
+int launch_level(const Args& a, int p, uint64_t n_rows, uint32_t level, hipStream_t s) {
     Profiler& pr = profiler();
     const bool on = pr.on;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
@@ -714,6 +759,8 @@ int launch_level(const Args& a, int p, hipStream_t s) {
     hipLaunchKernelGGL(k_expand<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
     RPQ_LAUNCH_CHECK();
     if (e1) RPQ_HIP(hipEventRecord(e1, s));
+    hipLaunchKernelGGL(k_compact, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p, n_rows, level);
+    RPQ_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_finalize<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
     RPQ_LAUNCH_CHECK();
     if (e2) RPQ_HIP(hipEventRecord(e2, s));
@@ -732,7 +779,9 @@ void profile_resolve() {
 }
 
 template <int K>
-int launch_finalize(const Args& a, int p, hipStream_t s) {
+int launch_finalize(const Args& a, int p, uint64_t n_rows, uint32_t level, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p, n_rows, level);
+    RPQ_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_finalize<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
     RPQ_LAUNCH_CHECK();
     return RPQ_OK;
@@ -762,6 +811,8 @@ int launch_extract(const Args& a, bool write, const uint32_t* sources, uint64_t 
         case 4: { constexpr int KK = 4; CALL; } break;               \
         case 8: { constexpr int KK = 8; CALL; } break;               \
         case 16: { constexpr int KK = 16; CALL; } break;             \
+        case 32: { constexpr int KK = 32; CALL; } break;             \
+        case 64: { constexpr int KK = 64; CALL; } break;             \
         default: rpq::set_error("bad batch width"); return RPQ_EINVAL; \
     }
 
@@ -859,7 +910,7 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
     RPQ_HIP(hipMemcpyAsync(ws + x.off_nfa, &dn, sizeof dn, hipMemcpyHostToDevice, stream));
     RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(a.counters), C_NCOUNTERS, 0, stream));
     RPQ_TRY(rpq::fill_u64(a.next, (uint64_t)x.G * x.Q * x.V * x.K, 0, stream));
-    RPQ_TRY(rpq::fill_u32(a.touch, (uint64_t)x.G * x.Q * x.V, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.touch, ((uint64_t)x.G * x.Q * x.V + 63) / 64, 0, stream));
     if (sources) {
         hipLaunchKernelGGL(k_check_sources, dim3((unsigned)std::min<uint64_t>((n_sources + 255) / 256, 4096)),
                            dim3(256), 0, stream, sources, n_sources, x.V, a.counters);
@@ -877,7 +928,7 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws + x.off_acc);
     uint32_t* partial = want_pairs ? reinterpret_cast<uint32_t*>(ws + x.off_partial) : nullptr;
     uint64_t* srcbase = want_pairs ? reinterpret_cast<uint64_t*>(ws + x.off_srcbase) : nullptr;
-    uint64_t levels_before = 0, max_depth = 0;
+    uint64_t levels_total = 0, max_depth = 0;
     for (uint64_t grp = 0; grp < n_groups; ++grp) {
         const uint64_t gbase = grp * per_group;
         const uint64_t n_here = std::min<uint64_t>(per_group, n_sources - gbase);
@@ -888,7 +939,10 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
         hipLaunchKernelGGL(k_seed, dim3((unsigned)(((uint64_t)G_eff * x.W + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                            stream, a, sources, n_sources, gbase, G_eff, x.W, x.K);
         RPQ_LAUNCH_CHECK();
-        RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_finalize<KK>(a, 0, stream)));
+        const uint64_t n_rows = (uint64_t)G_eff * x.Q * x.V;
+        RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(a.counters) + C_LASTLEVEL, 1, 0, stream));
+        RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_finalize<KK>(a, 0, n_rows, 0, stream)));
+        uint32_t level = 1;
         int p = 1;
         // a first-reach distance in the product graph is below Q * V, so the
         // fixpoint arrives within Q * V + 1 levels; more means a defect
@@ -896,8 +950,9 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
         uint64_t launched = 0;
         for (;;) {
             for (uint32_t s = 0; s < x.sync_every; ++s) {
-                RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_level<KK>(a, p, stream)));
+                RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_level<KK>(a, p, n_rows, level, stream)));
                 p ^= 1;
+                ++level;
             }
             launched += x.sync_every;
             RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
@@ -913,8 +968,8 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
                 return RPQ_EDEVICE;
             }
         }
-        const uint64_t lv = stage[C_LEVELS] - levels_before;
-        levels_before = stage[C_LEVELS];
+        const uint64_t lv = stage[C_LASTLEVEL];   // levels with a non-empty frontier, seeds included
+        levels_total += lv;
         if (lv > 0 && lv - 1 > max_depth) max_depth = lv - 1;
         RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_extract<KK>(a, false, sources, n_sources, gbase, G_eff, x.W, x.nchunks,
                                                        x.chunk_v, acc, partial, nullptr, nullptr, 0, 0, stream)));
@@ -945,7 +1000,7 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
     res->count = stage[C_COUNT];
     res->hash = stage[C_HASH];
     res->product_edges = stage[C_EPROD];
-    res->levels = stage[C_LEVELS];
+    res->levels = levels_total;
     res->max_depth = max_depth;
     if (want_pairs) {
         const uint64_t avail = res->count > res->pair_offset ? res->count - res->pair_offset : 0;

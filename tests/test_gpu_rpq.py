@@ -79,7 +79,7 @@ def test_uniform_1000_all_pairs_full(rpq):
     g.close()
 
 
-@pytest.mark.parametrize("width", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("width", [64, 128, 256, 512, 1024, 2048, 4096])
 def test_batch_shapes_do_not_change_results(rpq, width):
     el = synth.workload_graph("uniform_v1000_e5000_l4")
     g = gpu_graph(rpq, el)
@@ -111,7 +111,7 @@ def test_random_small_graphs_and_queries(rpq):
         g = rpq.rpq_graph_create(src, lab, dst, n, L, names=names[:L])
         og = oracle.OracleGraph(n, src, lab, dst, L, names[:L])
         sources = None if rng.random() < 0.5 else synth.sample_sources(n, int(rng.integers(1, n + 1)), seed=trial)
-        width = int(rng.choice([64, 128, 256, 512, 1024]))
+        width = int(rng.choice([64, 128, 256, 512, 1024, 2048, 4096]))
         check_against_oracle(rpq, g, og, regex, sources=sources,
                              opts=dict(batch_width=width, concurrency=int(rng.integers(1, 4)),
                                        chunk_edges=int(rng.integers(1, 100))))
