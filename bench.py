@@ -43,7 +43,23 @@ def parse_args():
                     help="target CPU time of the oracle baseline leg (0 disables it)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "expand_rmat18_traffic.json"),
                     help="measured HBM bytes per expand launch (from rocprofv3 --pmc), if present")
+    ap.add_argument("--queries", default="",
+                    help="comma-separated subset of the workload's queries (profiling runs only)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain copy of known size: HBM counters of this kernel scale the traversal's counters."""
+    import torch
+    n = mib << 20
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "repeats": 3}), flush=True)
 
 
 def cpu_baseline(el, queries, budget_s):
@@ -90,9 +106,14 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
     rpq.load_library()
     spec = synth.WORKLOADS[args.workload]
     queries = spec["queries"]
+    if args.queries:
+        queries = [q for q in args.queries.split(",") if q]
     print("bench: generating %s" % args.workload, file=sys.stderr, flush=True)
     el = synth.workload_graph(args.workload)
     g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)

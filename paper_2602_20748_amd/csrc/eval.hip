@@ -583,11 +583,22 @@ void to_dev_nfa(const rpq_nfa* nfa, uint32_t L, DevNfa* d) {
         }
 }
 
-uint32_t default_width(uint64_t n_sources) {
-    if (n_sources <= 64) return 64;
-    if (n_sources <= 128) return 128;
-    if (n_sources <= 256) return 256;
-    return 512;
+// Default shape: aim for about 32K sources in flight (measured on R-MAT scale 18:
+// throughput rises with the sources advanced per level until ~16K-32K), the widest
+// unit that the source count fills, and per-call workspace within ~24 GB.
+constexpr uint64_t kTargetInFlight = 32768;
+constexpr uint64_t kWorkspaceBudget = 24ull << 30;
+
+uint64_t unit_bytes(uint64_t QV, uint32_t W) {
+    // Vis + Next + two frontier lists of rows + row ids
+    return QV * (W / 8) * 4 + QV * 8;
+}
+
+uint32_t default_width(uint64_t n_sources, uint64_t QV) {
+    uint32_t W = 64;
+    while (W < 4096 && (uint64_t)W * 2 <= std::max<uint64_t>(64, n_sources / 8)) W *= 2;
+    while (W > 64 && unit_bytes(QV, W) > kWorkspaceBudget) W /= 2;
+    return W;
 }
 
 int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32_t flags,
@@ -598,7 +609,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     x.Q = dn.Q;
     x.L = g->L;
     x.V = g->V;
-    x.W = (o && o->batch_width) ? o->batch_width : default_width(n_sources);
+    x.W = (o && o->batch_width) ? o->batch_width : default_width(n_sources, (uint64_t)dn.Q * g->V);
     if (x.W != 64 && x.W != 128 && x.W != 256 && x.W != 512 && x.W != 1024 && x.W != 2048 && x.W != 4096) {
         rpq::set_error("batch_width must be 64, 128, 256, 512, 1024, 2048 or 4096");
         return RPQ_EINVAL;
@@ -615,10 +626,8 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     const uint64_t bitmap_bytes = QV * x.K * 8;
     uint64_t G = (o && o->concurrency) ? o->concurrency : 0;
     if (!G) {
-        // keep the two per-unit bitmaps of a group within ~512 MB (cache-sized
-        // working sets on small graphs), at least one unit
-        G = std::max<uint64_t>(1, (512ull << 20) / std::max<uint64_t>(1, 2 * bitmap_bytes));
-        G = std::min<uint64_t>(G, 64);
+        G = std::max<uint64_t>(1, kTargetInFlight / x.W);
+        G = std::min<uint64_t>(G, std::max<uint64_t>(1, kWorkspaceBudget / unit_bytes(QV, x.W)));
     }
     G = std::min<uint64_t>(G, units);
     if (G > (1u << 19)) G = 1u << 19;   // slot ids travel in 19 bits of a descriptor
