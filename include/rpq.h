@@ -235,6 +235,78 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
              rpq_result* result, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Batched evaluation: many queries in one persistent, graph-captured launch                  */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * A batch holds RPQs over one graph -- each with its own automaton, source set
+ * and result mode -- and evaluates all of them with one persistent kernel:
+ * queries are cut into units of at most batch_width sources, `slots` units
+ * advance level by level together, and a slot whose unit reaches its
+ * fixpoint is retired and refilled from the device-side unit queue in the
+ * same iteration (the role of the paper's traversal queue feeding the
+ * exploration kernel, Section 4.2 and Algorithm 1, without host round trips).
+ * The launch sequence is captured once into a hipGraph and replayed by
+ * rpq_batch_run.  Results are identical to rpq_eval of each query alone.
+ */
+typedef struct rpq_batch* rpq_batch_t;
+
+typedef struct {
+    uint32_t batch_width;   /* sources per unit: 64 .. 4096, power of two (0 = 512) */
+    uint32_t slots;         /* units advanced together (0 = sized for ~32K sources in flight, <= 32 GB) */
+    uint32_t chunk_edges;   /* edges per work descriptor (0 = 64) */
+    uint32_t reserved;
+} rpq_batch_opts;
+
+typedef struct {
+    uint32_t n_queries, n_units, slots, batch_width, blocks, reserved;
+    uint64_t workspace_bytes;
+    uint64_t iterations;         /* level iterations of the last run */
+    uint64_t edge_items, word_reads, word_updates;   /* expansion tallies of the last run */
+    double last_run_ms;          /* device time of the last graph launch */
+} rpq_batch_info;
+
+/* Create an empty batch over graph g (host object; no device memory). opts may be NULL. */
+int rpq_batch_create(rpq_graph_t g, const rpq_batch_opts* opts, rpq_batch_t* out);
+
+/* Destroy a batch and its captured graph. */
+int rpq_batch_destroy(rpq_batch_t b);
+
+/*
+ * Add one query.  nfa: host, copied.  sources: device uint32 [n_sources],
+ * strictly ascending (checked on the device at the first run), or NULL with
+ * RPQ_ALL_SOURCES.  flags: RPQ_PAIRS (pairs: device uint64 [capacity]; keys
+ * sorted as in rpq_eval; capacity must hold the whole result, else the query
+ * reports RPQ_EOVERFLOW and the buffer content is unspecified),
+ * RPQ_PER_SOURCE (per_source: device uint64 [n_sources][2]), RPQ_ALL_SOURCES.
+ * Device buffers must stay valid until the last rpq_batch_run.  *query_id
+ * receives the query's index.  Queries cannot be added after the first run.
+ */
+int rpq_batch_add(rpq_batch_t b, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources,
+                  uint32_t flags, uint64_t* pairs, uint64_t capacity, uint64_t* per_source,
+                  uint32_t* query_id);
+
+/* Device workspace bytes the batch needs (fixes the unit/slot plan). */
+int rpq_batch_workspace_size(rpq_batch_t b, uint64_t* bytes);
+
+/*
+ * Run every query of the batch to its fixpoint: one graph launch (reset
+ * kernels, the persistent kernel, the key gather) on `stream`, captured on the
+ * first run with this workspace.  Synchronises the stream.  workspace: device,
+ * 256-byte aligned, >= rpq_batch_workspace_size bytes, caller-owned; reusing
+ * the same workspace replays the captured graph.
+ * Errors: RPQ_EINVAL (bad sources), RPQ_ENOMEM, RPQ_EDEVICE (including a grid
+ * barrier that timed out because the persistent grid was not co-resident).
+ */
+int rpq_batch_run(rpq_batch_t b, void* workspace, uint64_t workspace_bytes, hipStream_t stream);
+
+/* Per-query results of the last run (host struct; counts, checksum, product edges, depth). */
+int rpq_batch_result(rpq_batch_t b, uint32_t query_id, rpq_result* out);
+
+/* Plan and tallies of the batch (host struct). */
+int rpq_batch_stats(rpq_batch_t b, rpq_batch_info* out);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Profiling of the traversal kernels                                                         */
 /* ------------------------------------------------------------------------------------------ */
 

@@ -25,6 +25,8 @@ __all__ = [
     "RPQ_OK", "RPQ_EINVAL", "RPQ_ENOMEM", "RPQ_EOVERFLOW", "RPQ_EDEVICE", "RPQ_EUNSUPPORTED",
     "RPQ_BUILD_IN_CSR", "RPQ_PAIRS", "RPQ_PER_SOURCE", "RPQ_ALL_SOURCES", "RPQ_REVERSE",
     "RPQ_MAX_STATES", "RPQ_MAX_LABELS", "EXPORTED_SYMBOLS", "rpq_profile_enable", "rpq_profile_read",
+    "Batch", "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size",
+    "rpq_batch_run", "rpq_batch_result", "rpq_batch_stats",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -73,6 +75,19 @@ class Profile(ctypes.Structure):
                 ("word_reads", ctypes.c_uint64), ("word_updates", ctypes.c_uint64)]
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("batch_width", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_queries", ctypes.c_uint32), ("n_units", ctypes.c_uint32), ("slots", ctypes.c_uint32),
+                ("batch_width", ctypes.c_uint32), ("blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("workspace_bytes", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
+                ("edge_items", ctypes.c_uint64), ("word_reads", ctypes.c_uint64), ("word_updates", ctypes.c_uint64),
+                ("last_run_ms", ctypes.c_double)]
+
+
 class _Result(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("per_source", ctypes.c_void_p),
                 ("pair_offset", ctypes.c_uint64), ("written", ctypes.c_uint64), ("count", ctypes.c_uint64),
@@ -85,6 +100,8 @@ EXPORTED_SYMBOLS = [
     "rpq_last_error", "rpq_abi_version", "rpq_graph_create", "rpq_graph_destroy", "rpq_graph_info_get",
     "rpq_graph_export_csr", "rpq_nfa_compile", "rpq_nfa_reverse", "rpq_eval_workspace_size", "rpq_eval",
     "rpq_profile_enable", "rpq_profile_read",
+    "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size", "rpq_batch_run",
+    "rpq_batch_result", "rpq_batch_stats",
 ]
 
 _lib = None
@@ -119,6 +136,14 @@ def load_library():
         "rpq_eval": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), vp, u64, u32, ctypes.POINTER(EvalOpts), vp, u64,
                                     ctypes.POINTER(_Result), vp]),
         "rpq_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+        "rpq_batch_create": (ctypes.c_int, [vp, ctypes.POINTER(BatchOpts), ctypes.POINTER(vp)]),
+        "rpq_batch_destroy": (ctypes.c_int, [vp]),
+        "rpq_batch_add": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), vp, u64, u32, vp, u64, vp,
+                                         ctypes.POINTER(u32)]),
+        "rpq_batch_workspace_size": (ctypes.c_int, [vp, ctypes.POINTER(u64)]),
+        "rpq_batch_run": (ctypes.c_int, [vp, vp, u64, vp]),
+        "rpq_batch_result": (ctypes.c_int, [vp, u32, ctypes.POINTER(_Result)]),
+        "rpq_batch_stats": (ctypes.c_int, [vp, ctypes.POINTER(BatchInfo)]),
         "rpq_profile_read": (ctypes.c_int, [ctypes.POINTER(Profile), ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -370,3 +395,120 @@ def rpq_profile_read(reset: bool = False) -> dict:
     p = Profile()
     _check(load_library().rpq_profile_read(ctypes.byref(p), 1 if reset else 0))
     return {name: getattr(p, name) for name, _ in Profile._fields_}
+
+
+# ------------------------------------------------------------------------------------------------
+# batched evaluation
+# ------------------------------------------------------------------------------------------------
+
+class Batch:
+    """Owner of an rpq_batch_t plus the device buffers its queries write into."""
+
+    def __init__(self, handle: int, graph: Graph):
+        self.handle = ctypes.c_void_p(handle)
+        self.graph = graph           # keeps the graph alive
+        self.keep = []               # device tensors the batch reads or writes
+        self.outputs = []            # per query: (pairs tensor or None, per_source tensor or None)
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load_library().rpq_batch_destroy(self.handle)
+        self.handle = None
+
+    def add(self, nfa: Nfa, sources=None, pairs_capacity: Optional[int] = None, per_source: bool = False) -> int:
+        return rpq_batch_add(self, nfa, sources, pairs_capacity, per_source)
+
+    def run(self, stream=None) -> None:
+        rpq_batch_run(self, stream=stream)
+
+    def result(self, qid: int) -> EvalResult:
+        return rpq_batch_result(self, qid)
+
+    def stats(self) -> dict:
+        return rpq_batch_stats(self)
+
+
+def rpq_batch_create(g: Graph, opts=None) -> Batch:
+    o = None
+    if opts:
+        o = BatchOpts()
+        for k, v in dict(opts).items():
+            setattr(o, k, int(v))
+    h = ctypes.c_void_p()
+    _check(load_library().rpq_batch_create(g.handle, ctypes.byref(o) if o is not None else None, ctypes.byref(h)))
+    return Batch(h.value, g)
+
+
+def rpq_batch_destroy(b: Batch) -> None:
+    b.close()
+
+
+def rpq_batch_add(b: Batch, nfa: Nfa, sources=None, pairs_capacity: Optional[int] = None,
+                  per_source: bool = False) -> int:
+    """Add a query; sources=None means every vertex.  Result buffers are allocated here."""
+    torch = _torch()
+    flags = 0
+    if sources is None:
+        flags |= RPQ_ALL_SOURCES
+        src_t = None
+        n = b.graph.info()["n_vertices"]
+    else:
+        src_t = _dev_u32(sources, torch)
+        n = src_t.numel()
+        b.keep.append(src_t)
+    pairs = ps = None
+    if pairs_capacity is not None:
+        flags |= RPQ_PAIRS
+        pairs = torch.empty(max(int(pairs_capacity), 1), dtype=torch.int64, device="cuda")
+        b.keep.append(pairs)
+    if per_source:
+        flags |= RPQ_PER_SOURCE
+        ps = torch.zeros((max(n, 1), 2), dtype=torch.int64, device="cuda")
+        b.keep.append(ps)
+    qid = ctypes.c_uint32()
+    _check(load_library().rpq_batch_add(b.handle, ctypes.byref(nfa),
+                                        src_t.data_ptr() if (src_t is not None and n) else None, n, flags,
+                                        pairs.data_ptr() if pairs is not None else None,
+                                        int(pairs_capacity or 0), ps.data_ptr() if ps is not None else None,
+                                        ctypes.byref(qid)))
+    b.outputs.append((pairs, ps[:n] if ps is not None else None))
+    return int(qid.value)
+
+
+def rpq_batch_workspace_size(b: Batch) -> int:
+    n = ctypes.c_uint64()
+    _check(load_library().rpq_batch_workspace_size(b.handle, ctypes.byref(n)))
+    return int(n.value)
+
+
+def rpq_batch_run(b: Batch, workspace=None, stream=None) -> None:
+    torch = _torch()
+    need = rpq_batch_workspace_size(b)
+    if workspace is None:
+        if b.ws is None or b.ws.numel() < need:
+            b.ws = None
+            b.ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        workspace = b.ws
+    _check(load_library().rpq_batch_run(b.handle, workspace.data_ptr(), workspace.numel(), _stream(stream)))
+
+
+def rpq_batch_result(b: Batch, qid: int) -> EvalResult:
+    res = _Result()
+    rc = load_library().rpq_batch_result(b.handle, qid, ctypes.byref(res))
+    _check(rc, allow=(RPQ_EOVERFLOW,))
+    pairs, ps = b.outputs[qid]
+    return EvalResult(int(res.count), int(res.hash), int(res.product_edges), int(res.levels), int(res.max_depth),
+                      int(res.written), pairs[: res.written] if pairs is not None else None, ps, rc)
+
+
+def rpq_batch_stats(b: Batch) -> dict:
+    info = BatchInfo()
+    _check(load_library().rpq_batch_stats(b.handle, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in BatchInfo._fields_}

@@ -1,0 +1,1292 @@
+// Batched evaluation: many RPQs (different automata, source sets, result
+// modes) advanced together by one persistent kernel, captured in a HIP graph.
+//
+// The queries are cut into units (a query's sources, at most W per unit; a
+// single-source query is one unit).  G slots each own a unit's bitmaps, sized
+// for the largest automaton of the batch: Vis/Next [Qmax][V][K] words, a
+// touch bitmap, Ans [V][K] and a one-bit-per-vertex summary of non-empty Ans
+// rows.  The persistent kernel repeats
+//
+//   expand -> compact -> decide -> (retire) -> refill/seed -> finalize
+//
+// with a grid barrier between phases: the level kernels of the plain form,
+// for every running slot at once, each slot with its own automaton.  A slot
+// whose compaction finds no touched rows has reached its fixpoint (no hop
+// bound); it is retired at once -- per-source count and checksum, keys into
+// per-query staging, then only the rows it visited are cleared (a log of
+// first-visited rows) -- and refilled from the unit queue in the same
+// iteration.  Units of one query may run in any order and any slot; results
+// do not depend on the schedule (every bit enters Vis exactly once and all
+// updates are ORs).
+//
+// This is the counterpart of the paper's traversal queue feeding TGs to the
+// exploration kernel (Section 4.2, Algorithm 1), with the queue held on the
+// device and the loop held in one launch.
+#include "internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kChunk = 8;
+constexpr uint32_t kChunkV = 4096;          // vertices per extraction chunk (64 summary words)
+
+constexpr uint32_t S_IDLE = 0, S_RUN = 1, S_RETIRE = 2;
+
+struct Desc {
+    uint32_t entry, beg;
+    uint32_t lenq;   // len | query << 16
+    uint32_t meta;   // label | q << 8 | slot << 13
+};
+
+struct BNfa {
+    uint32_t Q, L, init, final;
+    uint64_t qlab[RPQ_MAX_STATES];
+    uint32_t delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];   // compact [q * L + l]
+};
+
+struct BQuery {
+    const uint32_t* sources;   // device, ascending; null = implicit ids [0, n)
+    uint64_t n_sources;
+    uint64_t* per_source;      // device [n][2] or null
+    uint64_t* pairs;           // device output or null
+    uint64_t capacity;
+    uint64_t stage_off;        // first staging key of this query
+    uint32_t first_unit, n_units;
+    uint32_t flags, pad;
+};
+
+struct BQueryOut {
+    unsigned long long count, hash, eprod, stage_top, max_depth, overflow, levels, pad;
+};
+
+struct BUnit {
+    uint32_t query, n;
+    uint64_t src_off;
+};
+
+struct BSlot {
+    uint32_t state, unit, query, alive;
+    uint32_t start_iter, pad0;
+    unsigned long long log_n;
+};
+
+struct BCtl {
+    rpqd::GridSync gs;
+    unsigned long long list_cnt[2], desc_cnt[2];
+    unsigned long long queue_head;
+    unsigned long long n_running, n_retiring, n_pairs_retiring;
+    unsigned long long err, iterations;
+    unsigned long long items, descs, wreads, wupds;
+    unsigned long long pad[2];
+};
+
+struct BArgs {
+    const uint32_t* row_ptr;
+    const uint32_t* dst;
+    const uint64_t* lmask;
+    const BNfa* nfas;
+    const BQuery* queries;
+    BQueryOut* qout;
+    const BUnit* units;
+    BSlot* slots;
+    BCtl* ctl;
+    uint64_t* vis;
+    uint64_t* next;
+    uint64_t* touch;
+    uint64_t* ans;
+    uint64_t* summ;          // [G][V/64 rounded up]: bit v set when Ans row v is non-empty
+    uint32_t* ids0;
+    uint32_t* ids1;
+    uint64_t* rows0;
+    uint64_t* rows1;
+    Desc* desc0;
+    Desc* desc1;
+    uint32_t* logs;          // [G][slot_stride] first-visited rows (slot-local row ids)
+    uint32_t* retiring;      // [G] slot ids retiring this iteration
+    uint32_t* partial;       // [G][W][nchunks] pair counts per (source, chunk)
+    uint64_t* srcbase;       // [G][W] first staging index of each source of a retiring unit
+    uint64_t* stage;         // staging keys of all queries
+    uint64_t* unit_total;    // [n_units] keys per unit
+    uint64_t* unit_start;    // [n_units] staging index (query-relative) of each unit's keys
+    uint32_t V, L, Qmax, H, G, W, nchunks, n_units, n_queries, n_blocks;
+    uint64_t slot_stride, summ_words, list_cap, desc_cap, timeout, deadline;
+};
+
+__device__ __forceinline__ unsigned long long ld(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld32(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st32(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st64(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void or_relaxed(uint64_t* p, uint64_t v) {
+    (void)__hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+
+// Loads of data written in an earlier phase of the persistent kernel.
+#ifdef RPQ_COHERENT_LOADS
+__device__ __forceinline__ uint64_t xld(const uint64_t* p) {
+    return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t xld(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+#else
+__device__ __forceinline__ uint64_t xld(const uint64_t* p) { return *p; }
+__device__ __forceinline__ uint32_t xld(const uint32_t* p) { return *p; }
+#endif
+
+__device__ __forceinline__ uint64_t gwave(const BArgs& a) {
+    return (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+}
+__device__ __forceinline__ uint64_t gwaves(const BArgs& a) { return (uint64_t)a.n_blocks * kWaves; }
+
+// ------------------------------------------------------------------------------------------------
+// expand: the level expansion of the plain form, per-slot automata
+// ------------------------------------------------------------------------------------------------
+template <int K>
+__device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t& t_descs, uint64_t& t_wread,
+                             uint64_t& t_wupd) {
+    const uint64_t n_desc = min((uint64_t)ld(&a.ctl->desc_cnt[p]), a.desc_cap);
+    if (n_desc == 0) return;
+    const int lane = threadIdx.x & 63;
+    const Desc* desc = p ? a.desc1 : a.desc0;
+    const uint64_t* rows = p ? a.rows1 : a.rows0;
+    const uint32_t L = a.L, V = a.V;
+    const uint64_t n_batches = (n_desc + 63) / 64;
+    for (uint64_t b = gwave(a); b < n_batches; b += gwaves(a)) {
+        const uint64_t di = b * 64 + lane;
+        uint32_t len = 0, ent = 0, beg = 0, meta = 0, qq = 0;
+        if (di < n_desc) {
+            const uint32_t* dw = reinterpret_cast<const uint32_t*>(desc + di);
+            ent = xld(dw + 0);
+            beg = xld(dw + 1);
+            const uint32_t lq = xld(dw + 2);
+            meta = xld(dw + 3);
+            len = lq & 0xFFFF;
+            qq = lq >> 16;
+        }
+        const uint32_t incl = rpqd::wave_incl_scan_u32(len);
+        const uint32_t excl = incl - len;
+        const uint32_t total = __shfl(incl, 63, 64);
+        if (lane == 0) {
+            t_items += total;
+            t_descs += min<uint64_t>(64, n_desc - b * 64);
+        }
+        for (uint32_t base = 0; base < total; base += 64) {
+            const uint32_t item = base + lane;
+            int c = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int cand = c + step;
+                const uint32_t e = __shfl(excl, cand, 64);
+                if (e <= item) c = cand;
+            }
+            const uint32_t c_ent = __shfl(ent, c, 64);
+            const uint32_t c_beg = __shfl(beg, c, 64);
+            const uint32_t c_meta = __shfl(meta, c, 64);
+            const uint32_t c_ex = __shfl(excl, c, 64);
+            const uint32_t c_q = __shfl(qq, c, 64);
+            if (item < total) {
+                const uint32_t w = a.dst[c_beg + (item - c_ex)];
+                const uint32_t lab = c_meta & 0xFF, q = (c_meta >> 8) & 0x1F, slot = c_meta >> 13;
+                const BNfa* nfa = a.nfas + c_q;
+                uint32_t succ = nfa->delta[q * L + lab];
+                const uint64_t* fr = rows + (uint64_t)c_ent * K;
+                while (succ) {
+                    const uint32_t q2 = __ffs(succ) - 1;
+                    succ &= succ - 1;
+                    const uint64_t row = (uint64_t)slot * a.slot_stride + (uint64_t)q2 * V + w;
+                    const uint64_t* vs = a.vis + row * K;
+                    uint64_t* nx = a.next + row * K;
+                    bool any = false;
+#pragma unroll
+                    for (int k0 = 0; k0 < K; k0 += kChunk) {
+                        uint64_t f[kChunk], vw[kChunk];
+                        uint64_t fany = 0;
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k) {
+                            f[k] = (k0 + k < K) ? xld(fr + k0 + k) : 0;
+                            fany |= f[k];
+                        }
+                        if (!fany) continue;
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k) vw[k] = (k0 + k < K) ? xld(vs + k0 + k) : 0;
+#pragma unroll
+                        for (int k = 0; k < kChunk; ++k) {
+                            if (f[k]) {
+                                ++t_wread;
+                                const uint64_t nb = f[k] & ~vw[k];
+                                if (nb) {
+                                    ++t_wupd;
+                                    or_relaxed(&nx[k0 + k], nb);
+                                    any = true;
+                                }
+                            }
+                        }
+                    }
+                    if (any) or_relaxed(&a.touch[row >> 6], 1ull << (row & 63));
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// compact: touched rows -> row-id list p^1; per-slot liveness
+// ------------------------------------------------------------------------------------------------
+__device__ void phase_compact(const BArgs& a, int p, uint32_t iter) {
+    const int np = p ^ 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st64(&a.ctl->list_cnt[p], 0);
+        st64(&a.ctl->desc_cnt[p], 0);
+    }
+    const int lane = threadIdx.x & 63;
+    const uint64_t n_words = (uint64_t)a.G * a.slot_stride / 64;
+    const uint64_t words_per_slot = a.slot_stride / 64;
+    uint32_t* ids = np ? a.ids1 : a.ids0;
+    for (uint64_t w0 = gwave(a) * 64; w0 < n_words; w0 += gwaves(a) * 64) {
+        const uint64_t wi = w0 + lane;
+        uint64_t tw = wi < n_words ? xld(a.touch + wi) : 0;
+        if (tw) {
+            a.touch[wi] = 0;
+            const uint32_t slot = (uint32_t)(wi / words_per_slot);
+            if (ld32(&a.slots[slot].alive) != iter) st32(&a.slots[slot].alive, iter);
+        }
+        const uint32_t c = (uint32_t)__popcll(tw);
+        const uint32_t incl = rpqd::wave_incl_scan_u32(c);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        if (tot == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&a.ctl->list_cnt[np], (unsigned long long)tot);
+        base = __shfl(base, 0, 64);
+        uint64_t pos = base + incl - c;
+        while (tw) {
+            const int bt = __ffsll((long long)tw) - 1;
+            tw &= tw - 1;
+            if (pos < a.list_cap) ids[pos] = (uint32_t)(wi * 64 + bt);
+            else atomicOr(&a.ctl->err, 1ull);
+            ++pos;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// decide (block 0): running slots that produced no touched rows this iteration retire
+// ------------------------------------------------------------------------------------------------
+__device__ void phase_decide(const BArgs& a, uint32_t iter) {
+    __shared__ uint32_t s_n, s_pairs;
+    if (threadIdx.x == 0) {
+        s_n = 0;
+        s_pairs = 0;
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < a.G; s += kBlock) {
+        if (ld32(&a.slots[s].state) == S_RUN && ld32(&a.slots[s].alive) != iter) {
+            st32(&a.slots[s].state, S_RETIRE);
+            const uint32_t i = atomicAdd(&s_n, 1u);
+            st32(&a.retiring[i], s);
+            const uint32_t qid = ld32(&a.slots[s].query);
+            if (a.queries[qid].pairs) atomicAdd(&s_pairs, 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st64(&a.ctl->n_retiring, s_n);
+        st64(&a.ctl->n_pairs_retiring, s_pairs);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// retire: extraction over the non-empty Ans rows of each retiring slot
+// ------------------------------------------------------------------------------------------------
+template <int K, bool WRITE>
+__device__ void phase_retire_extract(const BArgs& a, uint32_t n_ret) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t total = (uint64_t)n_ret * K * a.nchunks;
+    for (uint64_t wv = gwave(a); wv < total; wv += gwaves(a)) {
+        const uint32_t chunk = (uint32_t)(wv % a.nchunks);
+        const uint32_t k = (uint32_t)((wv / a.nchunks) % K);
+        const uint32_t slot = ld32(&a.retiring[wv / ((uint64_t)a.nchunks * K)]);
+        const uint32_t u = ld32(&a.slots[slot].unit);
+        const BUnit unit = a.units[u];
+        const BQuery& Qy = a.queries[unit.query];
+        if (WRITE && !Qy.pairs) continue;
+        const uint32_t j = k * 64 + lane;
+        const bool valid = j < unit.n;
+        const uint64_t sidx = unit.src_off + j;
+        const uint64_t s = valid ? (Qy.sources ? Qy.sources[sidx] : sidx) : 0;
+        const uint32_t vbeg = chunk * kChunkV;
+        // the chunk's 64 summary words: bit set = Ans row non-empty
+        const uint64_t sw_i = (uint64_t)slot * a.summ_words + vbeg / 64 + lane;
+        const uint64_t sw = (vbeg / 64 + lane < a.summ_words) ? xld(a.summ + sw_i) : 0;
+        uint64_t cnt = 0, h = 0, cursor = 0;
+        const uint64_t pidx = ((uint64_t)slot * a.W + j) * a.nchunks + chunk;
+        if (WRITE && valid) cursor = a.srcbase[(uint64_t)slot * a.W + j] + a.partial[pidx];
+        uint64_t any = __ballot(sw != 0);
+        while (any) {
+            const int wl = __ffsll((long long)any) - 1;
+            any &= any - 1;
+            uint64_t bits = __shfl(sw, wl, 64);
+            while (bits) {
+                const int bb = __ffsll((long long)bits) - 1;
+                bits &= bits - 1;
+                const uint32_t v = vbeg + (uint32_t)wl * 64 + bb;
+                const uint64_t word = xld(a.ans + ((uint64_t)slot * a.V + v) * K + k);
+                if (valid && ((word >> lane) & 1)) {
+                    const uint64_t key = (s << 32) | v;
+                    if (WRITE) {
+                        if (cursor < Qy.capacity) a.stage[Qy.stage_off + cursor] = key;
+                        ++cursor;
+                    } else {
+                        ++cnt;
+                        h += rpqd::mix64(key);
+                    }
+                }
+            }
+        }
+        if (!WRITE) {
+            if (Qy.pairs && valid) a.partial[pidx] = (uint32_t)cnt;
+            if (Qy.per_source && valid && cnt) {
+                atomicAdd((unsigned long long*)&Qy.per_source[2 * sidx], (unsigned long long)cnt);
+                atomicAdd((unsigned long long*)&Qy.per_source[2 * sidx + 1], (unsigned long long)h);
+            }
+            const uint64_t wc = rpqd::wave_sum_u64(cnt), wh = rpqd::wave_sum_u64(h);
+            if (lane == 0 && wc) {
+                atomicAdd(&a.qout[unit.query].count, (unsigned long long)wc);
+                atomicAdd(&a.qout[unit.query].hash, (unsigned long long)wh);
+            }
+        }
+    }
+}
+
+// one block per retiring slot with pairs: chunk prefixes, source offsets, staging allocation
+__device__ void phase_retire_prefix(const BArgs& a, uint32_t n_ret) {
+    __shared__ uint64_t s_w[kWaves];
+    __shared__ uint64_t s_carry, s_base;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (uint32_t r = blockIdx.x; r < n_ret; r += a.n_blocks) {
+        const uint32_t slot = ld32(&a.retiring[r]);
+        const uint32_t u = ld32(&a.slots[slot].unit);
+        const BUnit unit = a.units[u];
+        const BQuery& Qy = a.queries[unit.query];
+        if (!Qy.pairs) continue;   // uniform per block
+        if (t == 0) s_carry = 0;
+        __syncthreads();
+        // source totals and per-source chunk prefixes (pass 1), unit total
+        for (uint32_t j0 = 0; j0 < a.W; j0 += kBlock) {
+            const uint32_t j = j0 + t;
+            uint64_t c = 0;
+            if (j < unit.n) {
+                uint32_t* pp = a.partial + ((uint64_t)slot * a.W + j) * a.nchunks;
+                uint32_t run = 0;
+                for (uint32_t ch = 0; ch < a.nchunks; ++ch) {
+                    const uint32_t x = pp[ch];
+                    pp[ch] = run;
+                    run += x;
+                }
+                c = run;
+            }
+            const uint64_t incl = rpqd::wave_incl_scan_u64(c);
+            if (lane == 63) s_w[wv] = incl;
+            __syncthreads();
+            uint64_t pre = s_carry;
+            for (int w = 0; w < wv; ++w) pre += s_w[w];
+            if (j < unit.n) a.srcbase[(uint64_t)slot * a.W + j] = pre + incl - c;   // unit-relative
+            __syncthreads();
+            if (t == 0) {
+                uint64_t tot = 0;
+                for (int w = 0; w < kWaves; ++w) tot += s_w[w];
+                s_carry += tot;
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            const uint64_t tot = s_carry;
+            const unsigned long long st = atomicAdd(&a.qout[unit.query].stage_top, (unsigned long long)tot);
+            a.unit_total[u] = tot;
+            a.unit_start[u] = st;
+            if (st + tot > Qy.capacity) atomicOr(&a.qout[unit.query].overflow, 1ull);
+            s_base = st;
+        }
+        __syncthreads();
+        for (uint32_t j = t; j < unit.n; j += kBlock) a.srcbase[(uint64_t)slot * a.W + j] += s_base;
+        __syncthreads();
+    }
+}
+
+// clear the rows a retiring unit visited, its Ans rows and summary; the slot becomes idle
+template <int K>
+__device__ void phase_retire_clear(const BArgs& a, uint32_t n_ret) {
+    const int lane = threadIdx.x & 63;
+    // Vis rows from the per-slot log
+    for (uint32_t r = 0; r < n_ret; ++r) {
+        const uint32_t slot = ld32(&a.retiring[r]);
+        const uint64_t n = min((uint64_t)ld(&a.slots[slot].log_n), a.slot_stride);
+        const uint32_t* log = a.logs + (uint64_t)slot * a.slot_stride;
+        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)a.n_blocks * kBlock) {
+            uint64_t* vs = a.vis + ((uint64_t)slot * a.slot_stride + xld(log + i)) * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k) vs[k] = 0;
+        }
+    }
+    // Ans rows flagged in the summary, then the summary itself
+    for (uint32_t r = 0; r < n_ret; ++r) {
+        const uint32_t slot = ld32(&a.retiring[r]);
+        for (uint64_t w0 = gwave(a) * 64; w0 < a.summ_words; w0 += gwaves(a) * 64) {
+            const uint64_t wi = w0 + lane;
+            uint64_t sw = wi < a.summ_words ? xld(a.summ + (uint64_t)slot * a.summ_words + wi) : 0;
+            if (sw) a.summ[(uint64_t)slot * a.summ_words + wi] = 0;
+            while (sw) {
+                const int bb = __ffsll((long long)sw) - 1;
+                sw &= sw - 1;
+                uint64_t* an = a.ans + ((uint64_t)slot * a.V + wi * 64 + bb) * K;
+#pragma unroll
+                for (int k = 0; k < K; ++k) an[k] = 0;
+            }
+        }
+    }
+    // The slot itself (log length, state) is reset in the next phase: other blocks may
+    // still be reading log_n in this one.
+}
+
+// ------------------------------------------------------------------------------------------------
+// refill (block 0 assigns units to idle slots), then every block seeds the new units
+// ------------------------------------------------------------------------------------------------
+__device__ void phase_assign(const BArgs& a, uint32_t iter) {
+    __shared__ uint32_t s_running;
+    if (threadIdx.x == 0) s_running = 0;
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < a.G; s += kBlock) {
+        uint32_t st = ld32(&a.slots[s].state);
+        if (st == S_RETIRE) {
+            // retired in this iteration's earlier phases: account its depth, free the slot
+            const uint32_t qid = a.units[ld32(&a.slots[s].unit)].query;
+            const uint32_t depth = iter - ld32(&a.slots[s].start_iter);
+            atomicMax(&a.qout[qid].max_depth, (unsigned long long)depth);
+            atomicAdd(&a.qout[qid].levels, (unsigned long long)depth);
+            st64(&a.slots[s].log_n, 0);
+            st32(&a.slots[s].state, S_IDLE);
+            st = S_IDLE;
+        }
+        if (st == S_IDLE) {
+            const unsigned long long u = atomicAdd(&a.ctl->queue_head, 1ull);
+            if (u < a.n_units) {
+                st32(&a.slots[s].unit, (uint32_t)u);
+                st32(&a.slots[s].query, a.units[u].query);
+                st32(&a.slots[s].alive, iter);
+                st32(&a.slots[s].start_iter, iter);
+                st32(&a.slots[s].state, S_RUN);
+                // seeding happens in phase_seed for slots whose start_iter == iter
+                st = S_RUN;
+            }
+        }
+        if (st == S_RUN) atomicAdd(&s_running, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) st64(&a.ctl->n_running, s_running);
+}
+
+template <int K>
+__device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
+    const int np = p ^ 1;
+    uint32_t* ids = np ? a.ids1 : a.ids0;
+    const uint64_t total = (uint64_t)a.G * a.W;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (uint64_t)a.n_blocks * kBlock) {
+        const uint32_t slot = (uint32_t)(i / a.W), j = (uint32_t)(i % a.W);
+        if (ld32(&a.slots[slot].state) != S_RUN || ld32(&a.slots[slot].start_iter) != iter) continue;
+        const BUnit unit = a.units[ld32(&a.slots[slot].unit)];
+        if (j >= unit.n) continue;
+        const BQuery& Qy = a.queries[unit.query];
+        const uint64_t sidx = unit.src_off + j;
+        const uint32_t s = Qy.sources ? Qy.sources[sidx] : (uint32_t)sidx;
+        uint32_t init = a.nfas[unit.query].init;
+        while (init) {
+            const uint32_t q = __ffs(init) - 1;
+            init &= init - 1;
+            const uint64_t lrow = (uint64_t)q * a.V + s;
+            const uint64_t row = (uint64_t)slot * a.slot_stride + lrow;
+            or_relaxed(&a.next[row * K + (j >> 6)], 1ull << (j & 63));
+            // one list entry per (slot, q, s): the first source bit of a word is enough since
+            // sources are distinct vertices, every (q, s) row gets exactly one source
+            const unsigned long long pos = atomicAdd(&a.ctl->list_cnt[np], 1ull);
+            if (pos < a.list_cap) ids[pos] = (uint32_t)row;
+            else atomicOr(&a.ctl->err, 1ull);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// finalize: list p^1 -> frontier rows, Vis (with first-visit log), Ans (+ summary), descriptors
+// ------------------------------------------------------------------------------------------------
+template <int K>
+__device__ void phase_finalize(const BArgs& a, int p) {
+    const int np = p ^ 1;
+    const uint64_t n = min((uint64_t)ld(&a.ctl->list_cnt[np]), a.list_cap);
+    if (n == 0) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t* ids = np ? a.ids1 : a.ids0;
+    uint64_t* rows = np ? a.rows1 : a.rows0;
+    Desc* dout = np ? a.desc1 : a.desc0;
+    unsigned long long* dcnt = &a.ctl->desc_cnt[np];
+    const uint32_t H = a.H, L = a.L, V = a.V;
+    const uint64_t stride = (uint64_t)a.n_blocks * kBlock;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); e0 < n; e0 += stride) {
+        const uint64_t e = e0 + lane;
+        const bool active = e < n;
+        uint32_t v = 0, q = 0, slot = 0, ndesc = 0, qid = 0;
+        uint64_t m = 0, eprod = 0;
+        const BNfa* nfa = a.nfas;
+        if (active) {
+            const uint32_t row32 = xld(ids + e);
+            slot = (uint32_t)(row32 / a.slot_stride);
+            const uint32_t lrow = (uint32_t)(row32 - (uint64_t)slot * a.slot_stride);
+            q = lrow / V;
+            v = lrow - q * V;
+            qid = ld32(&a.slots[slot].query);
+            nfa = a.nfas + qid;
+            const uint64_t row = row32;
+            uint64_t* nx = a.next + row * K;
+            uint64_t* vs = a.vis + row * K;
+            uint64_t* rw = rows + e * K;
+            uint64_t* an = a.ans + ((uint64_t)slot * V + v) * K;
+            const bool is_final = (nfa->final >> q) & 1;
+            uint32_t pc = 0;
+            uint64_t vis_any = 0;
+#pragma unroll
+            for (int k0 = 0; k0 < K; k0 += kChunk) {
+                uint64_t nk[kChunk], vk[kChunk];
+#pragma unroll
+                for (int k = 0; k < kChunk; ++k) nk[k] = (k0 + k < K) ? xld(nx + k0 + k) : 0;
+#pragma unroll
+                for (int k = 0; k < kChunk; ++k) vk[k] = (k0 + k < K) ? xld(vs + k0 + k) : 0;
+#pragma unroll
+                for (int k = 0; k < kChunk; ++k) {
+                    if (k0 + k >= K) break;
+                    rw[k0 + k] = nk[k];
+                    vis_any |= vk[k];
+                    if (nk[k]) {
+                        nx[k0 + k] = 0;
+                        vs[k0 + k] = vk[k] | nk[k];
+                        pc += (uint32_t)__popcll(nk[k]);
+                        if (is_final) or_relaxed(&an[k0 + k], nk[k]);
+                    }
+                }
+            }
+            if (is_final && pc) or_relaxed(&a.summ[(uint64_t)slot * a.summ_words + v / 64], 1ull << (v & 63));
+            if (!vis_any && pc) {
+                const unsigned long long li = atomicAdd(&a.slots[slot].log_n, 1ull);
+                if (li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = lrow;
+            }
+            m = a.lmask[v] & nfa->qlab[q];
+            uint64_t wsum = 0;
+            uint64_t mm = m;
+            while (mm) {
+                const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
+                mm &= mm - 1;
+                const uint32_t r = v * L + l;
+                const uint32_t d = a.row_ptr[r + 1] - a.row_ptr[r];
+                wsum += (uint64_t)d * (uint32_t)__popc(nfa->delta[q * L + l]);
+                ndesc += (d + H - 1) / H;
+            }
+            eprod = (uint64_t)pc * wsum;
+        }
+        // product edges per query (one atomic per wave when the wave holds one query)
+        const uint32_t q0 = __shfl(qid, __ffsll((long long)__ballot(active)) - 1, 64);
+        if (__ballot(active && qid != q0) == 0) {
+            const uint64_t ws = rpqd::wave_sum_u64(eprod);
+            if (lane == 0 && ws) atomicAdd(&a.qout[q0].eprod, (unsigned long long)ws);
+        } else if (active && eprod) {
+            atomicAdd(&a.qout[qid].eprod, (unsigned long long)eprod);
+        }
+        const uint32_t incl = rpqd::wave_incl_scan_u32(ndesc);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        if (tot) {
+            unsigned long long dbase = 0;
+            if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)tot);
+            dbase = __shfl(dbase, 0, 64);
+            if (active && ndesc) {
+                uint64_t pos = dbase + incl - ndesc;
+                uint64_t mm = m;
+                const uint32_t meta_qs = (q << 8) | (slot << 13);
+                while (mm) {
+                    const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
+                    mm &= mm - 1;
+                    const uint32_t r = v * L + l;
+                    const uint32_t b = a.row_ptr[r], d = a.row_ptr[r + 1] - b;
+                    for (uint32_t o = 0; o < d; o += H, ++pos) {
+                        if (pos < a.desc_cap) {
+                            Desc dd;
+                            dd.entry = (uint32_t)e;
+                            dd.beg = b + o;
+                            dd.lenq = min(H, d - o) | (qid << 16);
+                            dd.meta = l | meta_qs;
+                            dout[pos] = dd;
+                        } else {
+                            atomicOr(&a.ctl->err, 2ull);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// the persistent kernel
+// ------------------------------------------------------------------------------------------------
+#define BAR()                                                              \
+    do {                                                                   \
+        if (!rpqd::grid_barrier(&a.ctl->gs, a.n_blocks, a.timeout)) return; \
+    } while (0)
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_batch(BArgs a) {
+    uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0;
+    int p = 0;
+    const uint64_t t_start = wall_clock64();
+    for (uint32_t iter = 1;; ++iter) {
+        // whole-kernel deadline: a run that exceeds it is abandoned (every block leaves at its
+        // next barrier) and reported as an error
+        if (blockIdx.x == 0 && threadIdx.x == 0 && wall_clock64() - t_start > a.deadline)
+            __hip_atomic_store(&a.ctl->gs.abort, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        phase_expand<K>(a, p, t_items, t_descs, t_wread, t_wupd);
+        BAR();
+        phase_compact(a, p, iter);
+        BAR();
+        if (blockIdx.x == 0) phase_decide(a, iter);
+        BAR();
+        const uint32_t n_ret = (uint32_t)ld(&a.ctl->n_retiring);
+        if (n_ret) {
+            phase_retire_extract<K, false>(a, n_ret);
+            BAR();
+            if (ld(&a.ctl->n_pairs_retiring)) {
+                phase_retire_prefix(a, n_ret);
+                BAR();
+                phase_retire_extract<K, true>(a, n_ret);
+                BAR();
+            }
+            phase_retire_clear<K>(a, n_ret);
+            BAR();
+        }
+        if (blockIdx.x == 0) phase_assign(a, iter);
+        BAR();
+        if (ld(&a.ctl->n_running) == 0) break;
+        phase_seed<K>(a, p, iter);
+        BAR();
+        phase_finalize<K>(a, p);
+        BAR();
+        p ^= 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) st64(&a.ctl->iterations, iter);
+    }
+    t_items = rpqd::wave_sum_u64(t_items);
+    t_descs = rpqd::wave_sum_u64(t_descs);
+    t_wread = rpqd::wave_sum_u64(t_wread);
+    t_wupd = rpqd::wave_sum_u64(t_wupd);
+    if ((threadIdx.x & 63) == 0 && t_items) {
+        atomicAdd(&a.ctl->items, (unsigned long long)t_items);
+        atomicAdd(&a.ctl->descs, (unsigned long long)t_descs);
+        atomicAdd(&a.ctl->wreads, (unsigned long long)t_wread);
+        atomicAdd(&a.ctl->wupds, (unsigned long long)t_wupd);
+    }
+}
+#undef BAR
+
+__global__ void k_check_sources(const uint32_t* __restrict__ src, uint64_t n, uint32_t V,
+                                unsigned long long* __restrict__ bad) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t x = src[i];
+        if (x >= V || (i > 0 && src[i - 1] >= x)) atomicOr(bad, 1ull);
+    }
+}
+
+// after the persistent kernel: move each query's staged keys into its output in unit order
+__global__ void k_gather_pairs(BArgs a, const uint64_t* __restrict__ unit_prefix) {
+    for (uint32_t u = blockIdx.x; u < a.n_units; u += gridDim.x) {
+        const BUnit unit = a.units[u];
+        const BQuery& Qy = a.queries[unit.query];
+        if (!Qy.pairs) continue;
+        const uint64_t first = unit_prefix[Qy.first_unit];
+        const uint64_t dst0 = unit_prefix[u] - first;       // keys of earlier units of this query
+        const uint64_t src0 = a.unit_start[u];
+        const uint64_t n = a.unit_total[u];
+        for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            if (src0 + i < Qy.capacity && dst0 + i < Qy.capacity)
+                Qy.pairs[dst0 + i] = a.stage[Qy.stage_off + src0 + i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------------
+struct HostQuery {
+    rpq_nfa nfa;
+    const uint32_t* sources;
+    uint64_t n_sources;
+    uint32_t flags;
+    uint64_t* pairs;
+    uint64_t capacity;
+    uint64_t* per_source;
+};
+
+struct Layout {
+    uint32_t K, W, G, Qmax, H, nchunks, n_units;
+    uint64_t slot_stride, summ_words, list_cap, desc_cap, stage_keys;
+    uint64_t off_ctl, off_nfas, off_queries, off_qout, off_units, off_slots, off_vis, off_next, off_touch, off_ans,
+        off_summ, off_ids[2], off_rows[2], off_desc[2], off_logs, off_retiring, off_partial, off_srcbase, off_stage,
+        off_utotal, off_ustart, off_uprefix, off_scan_tmp, total;
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+}  // namespace
+
+struct rpq_batch {
+    rpq_graph* g = nullptr;
+    rpq_batch_opts opts{};
+    std::vector<HostQuery> queries;
+    std::vector<BUnit> units;
+    bool frozen = false;
+    Layout lay{};
+    // graph capture
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    void* ws_captured = nullptr;
+    hipStream_t cap_stream = nullptr;
+    unsigned n_blocks = 0;
+    BQueryOut* h_out = nullptr;      // pinned copy of the per-query outputs
+    BCtl* h_ctl = nullptr;
+    double last_ms = 0;
+};
+
+namespace {
+
+void to_bnfa(const rpq_nfa& n, uint32_t L, BNfa* d) {
+    std::memset(d, 0, sizeof *d);
+    d->Q = n.n_states;
+    d->L = L;
+    d->init = n.initial_mask;
+    d->final = n.final_mask;
+    for (uint32_t q = 0; q < n.n_states; ++q)
+        for (uint32_t l = 0; l < L; ++l) {
+            const uint32_t m = l < n.n_labels ? n.delta[q * RPQ_MAX_LABELS + l] : 0;
+            d->delta[q * L + l] = m;
+            if (m) d->qlab[q] |= 1ull << l;
+        }
+}
+
+int plan(rpq_batch* b) {
+    const rpq_graph* g = b->g;
+    Layout x;
+    std::memset(&x, 0, sizeof x);
+    x.W = b->opts.batch_width ? b->opts.batch_width : 512;
+    if (x.W != 64 && x.W != 128 && x.W != 256 && x.W != 512 && x.W != 1024 && x.W != 2048 && x.W != 4096) {
+        rpq::set_error("batch_width must be 64 .. 4096, a power of two");
+        return RPQ_EINVAL;
+    }
+    x.K = x.W / 64;
+    x.H = b->opts.chunk_edges ? b->opts.chunk_edges : 64;
+    if (x.H > 65535) {
+        rpq::set_error("chunk_edges must be <= 65535");
+        return RPQ_EINVAL;
+    }
+    x.Qmax = 1;
+    for (auto& q : b->queries) x.Qmax = std::max(x.Qmax, q.nfa.n_states);
+    // units
+    b->units.clear();
+    uint32_t qi = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> qunits;
+    for (auto& q : b->queries) {
+        const uint32_t first = (uint32_t)b->units.size();
+        for (uint64_t off = 0; off < q.n_sources; off += x.W) {
+            BUnit u;
+            u.query = qi;
+            u.n = (uint32_t)std::min<uint64_t>(x.W, q.n_sources - off);
+            u.src_off = off;
+            b->units.push_back(u);
+        }
+        qunits.emplace_back(first, (uint32_t)b->units.size() - first);
+        ++qi;
+    }
+    x.n_units = (uint32_t)b->units.size();
+    x.slot_stride = ((uint64_t)x.Qmax * g->V + 63) / 64 * 64;
+    x.summ_words = (g->V + 63) / 64;
+    const uint64_t per_slot = x.slot_stride * x.K * 8 * 2 + x.slot_stride / 8 + (uint64_t)g->V * x.K * 8 +
+                              x.summ_words * 8 + x.slot_stride * 4;
+    uint64_t G = b->opts.slots;
+    if (!G) {
+        const uint64_t budget = 32ull << 30;
+        G = std::max<uint64_t>(1, std::min<uint64_t>(std::max<uint64_t>(1, 32768 / x.W), budget / per_slot));
+    }
+    G = std::min<uint64_t>(G, std::max<uint32_t>(1, x.n_units));
+    G = std::min<uint64_t>(G, 1024);
+    if ((uint64_t)G * x.slot_stride >= 0xFFFFFFFFull || G >= (1u << 19)) {
+        rpq::set_error("slots * states * vertices must stay below 2^32; use fewer slots");
+        return RPQ_EUNSUPPORTED;
+    }
+    x.G = (uint32_t)G;
+    x.nchunks = (uint32_t)((g->V + kChunkV - 1) / kChunkV);
+    // frontier list: worst case every row of every slot in one level
+    x.list_cap = (uint64_t)x.G * x.slot_stride;
+    uint64_t dper = 0;
+    for (uint32_t q = 0; q < x.Qmax; ++q) dper += g->out.nonempty_rows + (g->E + x.H - 1) / x.H + 1;
+    x.desc_cap = (uint64_t)x.G * std::min<uint64_t>(dper, (uint64_t)x.Qmax * g->V * std::min<uint32_t>(g->L, 64) +
+                                                           (uint64_t)x.Qmax * ((g->E + x.H - 1) / x.H + 1));
+    x.stage_keys = 0;
+    for (auto& q : b->queries)
+        if (q.pairs) x.stage_keys += q.capacity;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const uint32_t nq = (uint32_t)b->queries.size();
+    x.off_ctl = take(sizeof(BCtl));
+    x.off_nfas = take(sizeof(BNfa) * nq);
+    x.off_queries = take(sizeof(BQuery) * nq);
+    x.off_qout = take(sizeof(BQueryOut) * nq);
+    x.off_units = take(sizeof(BUnit) * std::max<uint32_t>(1, x.n_units));
+    x.off_slots = take(sizeof(BSlot) * x.G);
+    x.off_vis = take(G * x.slot_stride * x.K * 8);
+    x.off_next = take(G * x.slot_stride * x.K * 8);
+    x.off_touch = take(G * x.slot_stride / 8);
+    x.off_ans = take(G * (uint64_t)g->V * x.K * 8);
+    x.off_summ = take(G * x.summ_words * 8);
+    for (int p = 0; p < 2; ++p) {
+        x.off_ids[p] = take(x.list_cap * 4);
+        x.off_rows[p] = take(x.list_cap * x.K * 8);
+        x.off_desc[p] = take(x.desc_cap * sizeof(Desc));
+    }
+    x.off_logs = take(G * x.slot_stride * 4);
+    x.off_retiring = take(G * 4);
+    x.off_partial = take(G * x.W * (uint64_t)x.nchunks * 4);
+    x.off_srcbase = take(G * x.W * 8);
+    x.off_stage = take(std::max<uint64_t>(1, x.stage_keys) * 8);
+    x.off_utotal = take(std::max<uint32_t>(1, x.n_units) * 8);
+    x.off_ustart = take(std::max<uint32_t>(1, x.n_units) * 8);
+    x.off_uprefix = take((std::max<uint32_t>(1, x.n_units) + 1) * 8);
+    x.off_scan_tmp = take((rpq::scan_temp_elems(std::max<uint32_t>(1, x.n_units)) + 1) * 8);
+    x.total = off;
+    b->lay = x;
+    (void)qunits;
+    return RPQ_OK;
+}
+
+BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
+    const Layout& x = b->lay;
+    const rpq_graph* g = b->g;
+    BArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.row_ptr = g->out.row_ptr;
+    a.dst = g->out.dst;
+    a.lmask = g->out.lmask;
+    a.nfas = reinterpret_cast<const BNfa*>(ws + x.off_nfas);
+    a.queries = reinterpret_cast<const BQuery*>(ws + x.off_queries);
+    a.qout = reinterpret_cast<BQueryOut*>(ws + x.off_qout);
+    a.units = reinterpret_cast<const BUnit*>(ws + x.off_units);
+    a.slots = reinterpret_cast<BSlot*>(ws + x.off_slots);
+    a.ctl = reinterpret_cast<BCtl*>(ws + x.off_ctl);
+    a.vis = reinterpret_cast<uint64_t*>(ws + x.off_vis);
+    a.next = reinterpret_cast<uint64_t*>(ws + x.off_next);
+    a.touch = reinterpret_cast<uint64_t*>(ws + x.off_touch);
+    a.ans = reinterpret_cast<uint64_t*>(ws + x.off_ans);
+    a.summ = reinterpret_cast<uint64_t*>(ws + x.off_summ);
+    a.ids0 = reinterpret_cast<uint32_t*>(ws + x.off_ids[0]);
+    a.ids1 = reinterpret_cast<uint32_t*>(ws + x.off_ids[1]);
+    a.rows0 = reinterpret_cast<uint64_t*>(ws + x.off_rows[0]);
+    a.rows1 = reinterpret_cast<uint64_t*>(ws + x.off_rows[1]);
+    a.desc0 = reinterpret_cast<Desc*>(ws + x.off_desc[0]);
+    a.desc1 = reinterpret_cast<Desc*>(ws + x.off_desc[1]);
+    a.logs = reinterpret_cast<uint32_t*>(ws + x.off_logs);
+    a.retiring = reinterpret_cast<uint32_t*>(ws + x.off_retiring);
+    a.partial = reinterpret_cast<uint32_t*>(ws + x.off_partial);
+    a.srcbase = reinterpret_cast<uint64_t*>(ws + x.off_srcbase);
+    a.stage = reinterpret_cast<uint64_t*>(ws + x.off_stage);
+    a.unit_total = reinterpret_cast<uint64_t*>(ws + x.off_utotal);
+    a.unit_start = reinterpret_cast<uint64_t*>(ws + x.off_ustart);
+    a.V = g->V;
+    a.L = g->L;
+    a.Qmax = x.Qmax;
+    a.H = x.H;
+    a.G = x.G;
+    a.W = x.W;
+    a.nchunks = x.nchunks;
+    a.n_units = x.n_units;
+    a.n_queries = (uint32_t)b->queries.size();
+    a.n_blocks = n_blocks;
+    a.slot_stride = x.slot_stride;
+    a.summ_words = x.summ_words;
+    a.list_cap = x.list_cap;
+    a.desc_cap = x.desc_cap;
+    a.timeout = 100ull * 1000 * 1000 * 30;    // one barrier wait: 30 s of the 100 MHz clock
+    a.deadline = 100ull * 1000 * 1000 * 300;  // whole run: 300 s
+    return a;
+}
+
+#define RPQ_BDISPATCH(K, CALL)                                   \
+    switch (K) {                                                 \
+        case 1: { constexpr int KK = 1; CALL; } break;           \
+        case 2: { constexpr int KK = 2; CALL; } break;           \
+        case 4: { constexpr int KK = 4; CALL; } break;           \
+        case 8: { constexpr int KK = 8; CALL; } break;           \
+        case 16: { constexpr int KK = 16; CALL; } break;         \
+        case 32: { constexpr int KK = 32; CALL; } break;         \
+        case 64: { constexpr int KK = 64; CALL; } break;         \
+        default: rpq::set_error("bad width"); return RPQ_EINVAL; \
+    }
+
+template <int K>
+int co_resident_blocks(unsigned* out) {
+    int per_cu = 0, dev = 0, n_cu = 0;
+    RPQ_HIP(hipGetDevice(&dev));
+    RPQ_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    RPQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch<K>), kBlock, 0));
+    if (per_cu <= 0) {
+        rpq::set_error("persistent kernel does not fit on a compute unit");
+        return RPQ_EUNSUPPORTED;
+    }
+    // up to four 256-thread blocks per CU: enough waves in flight for the level phases
+    // while the grid barrier stays cheap
+    *out = (unsigned)(std::min(per_cu, 4) * n_cu);
+    return RPQ_OK;
+}
+
+template <int K>
+int enqueue_run(rpq_batch* b, char* ws, hipStream_t s) {
+    const Layout& x = b->lay;
+    const unsigned nb = b->n_blocks;   // co-resident grid, sized before capture began
+    BArgs a = make_bargs(b, ws, nb);
+    // reset the mutable state with fill kernels (graph-safe, no memset nodes)
+    RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(ws + x.off_ctl), sizeof(BCtl) / 8, 0, s));
+    RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(ws + x.off_qout), sizeof(BQueryOut) / 8 * b->queries.size(),
+                          0, s));
+    RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(ws + x.off_slots), sizeof(BSlot) / 8 * x.G, 0, s));
+    RPQ_TRY(rpq::fill_u64(a.vis, (uint64_t)x.G * x.slot_stride * x.K, 0, s));
+    RPQ_TRY(rpq::fill_u64(a.next, (uint64_t)x.G * x.slot_stride * x.K, 0, s));
+    RPQ_TRY(rpq::fill_u64(a.touch, (uint64_t)x.G * x.slot_stride / 64, 0, s));
+    RPQ_TRY(rpq::fill_u64(a.ans, (uint64_t)x.G * b->g->V * x.K, 0, s));
+    RPQ_TRY(rpq::fill_u64(a.summ, (uint64_t)x.G * x.summ_words, 0, s));
+    RPQ_TRY(rpq::fill_u64(a.unit_total, std::max<uint32_t>(1, x.n_units), 0, s));
+    for (auto& q : b->queries)
+        if (q.per_source) RPQ_TRY(rpq::fill_u64(q.per_source, q.n_sources * 2, 0, s));
+    hipLaunchKernelGGL(k_batch<K>, dim3(nb), dim3(kBlock), 0, s, a);
+    RPQ_LAUNCH_CHECK();
+    bool any_pairs = false;
+    for (auto& q : b->queries) any_pairs |= q.pairs != nullptr;
+    if (any_pairs) {
+        uint64_t* prefix = reinterpret_cast<uint64_t*>(ws + x.off_uprefix);
+        RPQ_TRY(rpq::exclusive_scan_u64(a.unit_total, prefix, x.n_units, reinterpret_cast<uint64_t*>(ws + x.off_scan_tmp),
+                                        prefix + x.n_units, s));
+        hipLaunchKernelGGL(k_gather_pairs, dim3(std::min<uint32_t>(x.n_units, 4096)), dim3(256), 0, s, a,
+                           (const uint64_t*)prefix);
+        RPQ_LAUNCH_CHECK();
+    }
+    return RPQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpq_batch_create(rpq_graph_t g, const rpq_batch_opts* opts, rpq_batch_t* out) {
+    rpq::clear_error();
+    if (!g || !out) {
+        rpq::set_error("NULL argument");
+        return RPQ_EINVAL;
+    }
+    rpq_batch* b = new (std::nothrow) rpq_batch();
+    if (!b) {
+        rpq::set_error("host allocation failed");
+        return RPQ_ENOMEM;
+    }
+    b->g = g;
+    if (opts) b->opts = *opts;
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->h_ctl), sizeof(BCtl)) != hipSuccess) {
+        delete b;
+        rpq::set_error("pinned allocation failed");
+        return RPQ_ENOMEM;
+    }
+    *out = b;
+    return RPQ_OK;
+}
+
+int rpq_batch_destroy(rpq_batch_t b) {
+    if (!b) return RPQ_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->h_out) (void)hipHostFree(b->h_out);
+    if (b->h_ctl) (void)hipHostFree(b->h_ctl);
+    delete b;
+    return RPQ_OK;
+}
+
+int rpq_batch_add(rpq_batch_t b, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
+                  uint64_t* pairs, uint64_t capacity, uint64_t* per_source, uint32_t* query_id) {
+    rpq::clear_error();
+    if (!b || !nfa) {
+        rpq::set_error("NULL argument");
+        return RPQ_EINVAL;
+    }
+    if (b->frozen) {
+        rpq::set_error("batch already ran; create a new batch to add queries");
+        return RPQ_EINVAL;
+    }
+    if (b->queries.size() >= 65535) {
+        rpq::set_error("a batch holds at most 65535 queries");
+        return RPQ_EUNSUPPORTED;
+    }
+    if (flags & ~(RPQ_PAIRS | RPQ_PER_SOURCE | RPQ_ALL_SOURCES)) {
+        rpq::set_error("unsupported flags 0x%x for a batched query", flags);
+        return RPQ_EINVAL;
+    }
+    if (nfa->n_states == 0 || nfa->n_states > RPQ_MAX_STATES || nfa->n_labels == 0 || nfa->n_labels > b->g->L) {
+        rpq::set_error("invalid automaton for this graph");
+        return RPQ_EINVAL;
+    }
+    const uint32_t smask = nfa->n_states == 32 ? 0xFFFFFFFFu : ((1u << nfa->n_states) - 1);
+    for (uint32_t q = 0; q < RPQ_MAX_STATES; ++q)
+        for (uint32_t l = 0; l < RPQ_MAX_LABELS; ++l) {
+            const uint32_t d = nfa->delta[q * RPQ_MAX_LABELS + l];
+            if (d && (q >= nfa->n_states || l >= nfa->n_labels || (d & ~smask))) {
+                rpq::set_error("delta[%u][%u] is outside the automaton", q, l);
+                return RPQ_EINVAL;
+            }
+        }
+    if ((nfa->initial_mask & ~smask) || (nfa->final_mask & ~smask)) {
+        rpq::set_error("initial/final mask names states >= n_states");
+        return RPQ_EINVAL;
+    }
+    if (flags & RPQ_ALL_SOURCES) {
+        if (sources) {
+            rpq::set_error("RPQ_ALL_SOURCES requires sources == NULL");
+            return RPQ_EINVAL;
+        }
+        n_sources = b->g->V;
+    } else if (n_sources && !sources) {
+        rpq::set_error("sources is NULL");
+        return RPQ_EINVAL;
+    }
+    if ((flags & RPQ_PAIRS) && !pairs) {
+        rpq::set_error("RPQ_PAIRS with a NULL pair buffer");
+        return RPQ_EINVAL;
+    }
+    if ((flags & RPQ_PER_SOURCE) && n_sources && !per_source) {
+        rpq::set_error("RPQ_PER_SOURCE with a NULL per_source buffer");
+        return RPQ_EINVAL;
+    }
+    HostQuery q;
+    q.nfa = *nfa;
+    q.sources = sources;
+    q.n_sources = n_sources;
+    q.flags = flags;
+    q.pairs = (flags & RPQ_PAIRS) ? pairs : nullptr;
+    q.capacity = (flags & RPQ_PAIRS) ? capacity : 0;
+    q.per_source = (flags & RPQ_PER_SOURCE) ? per_source : nullptr;
+    if (query_id) *query_id = (uint32_t)b->queries.size();
+    b->queries.push_back(q);
+    return RPQ_OK;
+}
+
+int rpq_batch_workspace_size(rpq_batch_t b, uint64_t* bytes) {
+    rpq::clear_error();
+    if (!b || !bytes) {
+        rpq::set_error("NULL argument");
+        return RPQ_EINVAL;
+    }
+    if (b->queries.empty()) {
+        *bytes = 256;
+        return RPQ_OK;
+    }
+    RPQ_TRY(plan(b));
+    *bytes = b->lay.total;
+    return RPQ_OK;
+}
+
+int rpq_batch_run(rpq_batch_t b, void* workspace, uint64_t workspace_bytes, hipStream_t stream) {
+    rpq::clear_error();
+    if (!b) {
+        rpq::set_error("NULL batch");
+        return RPQ_EINVAL;
+    }
+    if (b->queries.empty()) return RPQ_OK;
+    if (!b->frozen) {
+        RPQ_TRY(plan(b));
+        b->frozen = true;
+    }
+    const Layout& x = b->lay;
+    if (!workspace || workspace_bytes < x.total || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+        rpq::set_error("workspace must be 256-byte aligned and hold %llu bytes", (unsigned long long)x.total);
+        return RPQ_ENOMEM;
+    }
+    char* ws = reinterpret_cast<char*>(workspace);
+    if (b->ws_captured != workspace) {
+        // sources: strictly ascending and below V, checked on the device before any traversal
+        unsigned long long* bad = reinterpret_cast<unsigned long long*>(ws + x.off_ctl);
+        RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(bad), 1, 0, stream));
+        for (auto& q : b->queries)
+            if (q.sources && q.n_sources) {
+                hipLaunchKernelGGL(k_check_sources, dim3((unsigned)std::min<uint64_t>((q.n_sources + 255) / 256, 4096)),
+                                   dim3(256), 0, stream, q.sources, q.n_sources, b->g->V, bad);
+                RPQ_LAUNCH_CHECK();
+            }
+        unsigned long long hbad = 0;
+        RPQ_HIP(hipMemcpyAsync(&hbad, bad, 8, hipMemcpyDeviceToHost, stream));
+        RPQ_HIP(hipStreamSynchronize(stream));
+        if (hbad) {
+            rpq::set_error("batched sources must be strictly ascending vertex ids below n_vertices");
+            return RPQ_EINVAL;
+        }
+    }
+    const uint32_t nq = (uint32_t)b->queries.size();
+    if (b->ws_captured != workspace) {
+        // static tables: automata, queries, units (host -> device once per workspace)
+        std::vector<BNfa> nf(nq);
+        std::vector<BQuery> qs(nq);
+        uint64_t stage_off = 0;
+        uint32_t ufirst = 0;
+        for (uint32_t i = 0; i < nq; ++i) {
+            const HostQuery& h = b->queries[i];
+            to_bnfa(h.nfa, b->g->L, &nf[i]);
+            BQuery& d = qs[i];
+            std::memset(&d, 0, sizeof d);
+            d.sources = h.sources;
+            d.n_sources = h.n_sources;
+            d.per_source = h.per_source;
+            d.pairs = h.pairs;
+            d.capacity = h.capacity;
+            d.stage_off = stage_off;
+            if (h.pairs) stage_off += h.capacity;
+            d.first_unit = ufirst;
+            d.n_units = (uint32_t)((h.n_sources + x.W - 1) / x.W);
+            ufirst += d.n_units;
+            d.flags = h.flags;
+        }
+        RPQ_HIP(hipMemcpy(ws + x.off_nfas, nf.data(), sizeof(BNfa) * nq, hipMemcpyHostToDevice));
+        RPQ_HIP(hipMemcpy(ws + x.off_queries, qs.data(), sizeof(BQuery) * nq, hipMemcpyHostToDevice));
+        if (!b->units.empty())
+            RPQ_HIP(hipMemcpy(ws + x.off_units, b->units.data(), sizeof(BUnit) * b->units.size(),
+                              hipMemcpyHostToDevice));
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        if (b->graph) {
+            (void)hipGraphDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        b->ws_captured = workspace;
+    }
+    if (!b->cap_stream) RPQ_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    if (!b->exec) {
+        RPQ_BDISPATCH(x.K, RPQ_TRY(co_resident_blocks<KK>(&b->n_blocks)));
+        RPQ_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = RPQ_OK;
+        RPQ_BDISPATCH(x.K, rc = enqueue_run<KK>(b, ws, b->cap_stream));
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(b->cap_stream, &graph);
+        if (rc != RPQ_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        RPQ_HIP(ec);
+        b->graph = graph;
+        RPQ_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    hipEvent_t e0, e1;
+    RPQ_HIP(hipEventCreate(&e0));
+    RPQ_HIP(hipEventCreate(&e1));
+    RPQ_HIP(hipEventRecord(e0, stream));
+    RPQ_HIP(hipGraphLaunch(b->exec, stream));
+    RPQ_HIP(hipEventRecord(e1, stream));
+    RPQ_HIP(hipStreamSynchronize(stream));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->last_ms = ms;
+    RPQ_HIP(hipMemcpy(b->h_ctl, ws + x.off_ctl, sizeof(BCtl), hipMemcpyDeviceToHost));
+    if (b->h_ctl->gs.abort) {
+        rpq::set_error(b->h_ctl->gs.abort == 2 ? "batched run exceeded its deadline and was abandoned"
+                                               : "persistent kernel aborted at a grid barrier (grid not co-resident)");
+        return RPQ_EDEVICE;
+    }
+    if (b->h_ctl->err) {
+        rpq::set_error("internal capacity exceeded in the batched kernel (flags 0x%llx)",
+                       (unsigned long long)b->h_ctl->err);
+        return RPQ_EDEVICE;
+    }
+    return RPQ_OK;
+}
+
+int rpq_batch_result(rpq_batch_t b, uint32_t query_id, rpq_result* out) {
+    rpq::clear_error();
+    if (!b || !out || query_id >= b->queries.size() || !b->frozen || !b->ws_captured) {
+        rpq::set_error("invalid batch, query id, or batch has not run");
+        return RPQ_EINVAL;
+    }
+    BQueryOut o;
+    const char* ws = reinterpret_cast<const char*>(b->ws_captured);
+    RPQ_HIP(hipMemcpy(&o, ws + b->lay.off_qout + sizeof(BQueryOut) * query_id, sizeof o, hipMemcpyDeviceToHost));
+    const HostQuery& h = b->queries[query_id];
+    std::memset(out, 0, sizeof *out);
+    out->pairs = h.pairs;
+    out->capacity = h.capacity;
+    out->per_source = h.per_source;
+    out->count = o.count;
+    out->hash = o.hash;
+    out->product_edges = o.eprod;
+    out->levels = o.levels;
+    out->max_depth = o.max_depth;
+    if (h.pairs) {
+        out->written = std::min<uint64_t>(o.count, h.capacity);
+        if (o.count > h.capacity) {
+            rpq::set_error("query %u has %llu keys; capacity %llu", query_id, (unsigned long long)o.count,
+                           (unsigned long long)h.capacity);
+            return RPQ_EOVERFLOW;
+        }
+    }
+    return RPQ_OK;
+}
+
+int rpq_batch_stats(rpq_batch_t b, rpq_batch_info* out) {
+    rpq::clear_error();
+    if (!b || !out) {
+        rpq::set_error("NULL argument");
+        return RPQ_EINVAL;
+    }
+    std::memset(out, 0, sizeof *out);
+    out->n_queries = (uint32_t)b->queries.size();
+    out->n_units = b->lay.n_units;
+    out->slots = b->lay.G;
+    out->batch_width = b->lay.W;
+    out->blocks = b->n_blocks;
+    out->workspace_bytes = b->lay.total;
+    out->last_run_ms = b->last_ms;
+    if (b->h_ctl) {
+        out->iterations = b->h_ctl->iterations;
+        out->edge_items = b->h_ctl->items;
+        out->word_reads = b->h_ctl->wreads;
+        out->word_updates = b->h_ctl->wupds;
+    }
+    return RPQ_OK;
+}
+
+}  // extern "C"

@@ -139,3 +139,59 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 }
 
 }  // namespace rpqd
+
+// ---- grid-wide barrier for persistent kernels (device) ----
+// Sense-reversing barrier over all workgroups of a co-resident grid.  Waits are
+// bounded by the 100 MHz constant clock: after `timeout_ticks` a waiting
+// workgroup raises *abort and every workgroup returns from the barrier with
+// false, so a grid that is not fully resident can never hang the device.
+namespace rpqd {
+
+struct GridSync {
+    unsigned int count;
+    unsigned int generation;
+    unsigned int abort;
+    unsigned int pad;
+};
+
+__device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned int n_blocks, uint64_t timeout_ticks) {
+    // A fence orders only the memory operations of the wave that executes it, so every
+    // wave releases its own global writes (stores and no-return atomics) before the
+    // workgroup meets, and every wave acquires (drops stale L1 lines) after the grid met.
+    __threadfence();
+    __syncthreads();
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned int gen = __hip_atomic_load(&gs->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned int arrived =
+            __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == n_blocks - 1) {
+            __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&gs->generation, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&gs->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > timeout_ticks) {
+                    __hip_atomic_store(&gs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();
+    return s_ok != 0;
+}
+
+}  // namespace rpqd
