@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the plain RPQ path on one MI355X.
+"""Throughput benchmark of the RPQ hot path on one MI355X.
 
 Workload (default): R-MAT scale 18 (262,144 vertices, 4,194,304 drawn edges,
-8 labels Zipf(1.1), seed 18) with five all-pairs queries, one evaluation each:
-a*, a.b*, (a|b).c*, a.b*.c, (a.b)*.  One step evaluates all five from all
-262,144 sources to the fixpoint, returning count, checksum and per-source
-(count, checksum).  The graph is built (and resident in HBM) before timing;
-query compilation, traversal and extraction are inside the timed region.
+8 labels Zipf(1.1), seed 18) with five all-pairs queries: a*, a.b*, (a|b).c*,
+a.b*.c, (a.b)*.  One step evaluates all five from all 262,144 sources to the
+fixpoint and returns count, checksum and per-source (count, checksum).  The
+graph is built, and resident in HBM, before timing.
 
-Metric: product-graph edges per second (sum over sources of the product
-edges examined, counted on the Glushkov automaton), with distinct result
-pairs per second beside it.
+Two forms of the same step are timed:
+  plain    one rpq_eval per query (query compile, traversal, extraction);
+  batched  the five queries in one rpq_batch: one persistent kernel in one
+           captured graph launch, unit width/slots/chunk chosen by the native
+           autotuner during warm-up.
+`value` is the product-graph edges per second of --form (default plain, the
+one-launch-per-query form this workload is defined on);
+both forms are reported.
 
+Metric: product-graph edges per second (per source, the product edges
+examined, counted on the Glushkov automaton), with distinct pairs per second.
 Prints one JSON line.  --gpus > 1 is not supported by this single-GPU build.
 """
 from __future__ import annotations
@@ -35,16 +41,21 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18_l8")
-    ap.add_argument("--batch-width", type=int, default=0)
+    ap.add_argument("--form", choices=["batched", "plain"], default="plain",
+                    help="which form's throughput is `value` (both are measured)")
+    ap.add_argument("--batch-width", type=int, default=0, help="plain form: unit width (0 = default policy)")
     ap.add_argument("--concurrency", type=int, default=0)
     ap.add_argument("--sync-every", type=int, default=0)
     ap.add_argument("--chunk-edges", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="batched form: keep the default plan")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline leg (0 disables it)")
-    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "expand_rmat18_traffic.json"),
-                    help="measured HBM bytes per expand launch (from rocprofv3 --pmc), if present")
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic_rmat18.json"),
+                    help="measured HBM bytes per launch of the dominant kernels (rocprofv3 --pmc), if present")
     ap.add_argument("--queries", default="",
                     help="comma-separated subset of the workload's queries (profiling runs only)")
+    ap.add_argument("--only", choices=["", "plain", "batched"], default="",
+                    help="time only one form (profiling runs only)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -64,8 +75,6 @@ def copy_calibration(mib):
 
 def cpu_baseline(el, queries, budget_s):
     """The oracle as it stands, on the host cores, over a bounded source sample."""
-    import numpy as np
-
     import oracle
     import synth
     threads = max(1, min(os.cpu_count() or 1, 16))
@@ -83,11 +92,29 @@ def cpu_baseline(el, queries, budget_s):
         dt = time.perf_counter() - t0
         if dt >= budget_s / 2 or n >= el.n_vertices or n >= 8192:
             break
-        n = min(el.n_vertices, n * 2 if dt * 4 < budget_s else n * 2)
+        n = min(el.n_vertices, n * 2)
     return dict(value=eprod / dt, unit="product-graph edges/s", cores=threads, kind="oracle",
                 pairs_per_s=pairs / dt,
                 sample="%d seeded sources (of %d) x %d queries, %.1f s, %d product edges" % (
                     n, el.n_vertices, len(queries), dt, eprod))
+
+
+def load_traffic(path, kernel, source_files):
+    """Measured HBM bytes per launch, valid only for the kernel sources it was taken with."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        h = hashlib.sha256()
+        for f in source_files:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        ent = d.get(kernel)
+        if not ent or ent.get("sources_sha256") != h.hexdigest():
+            return None
+        return ent.get("bytes_per_launch")
+    except Exception:
+        return None
 
 
 def main():
@@ -96,7 +123,6 @@ def main():
         print("bench.py: this build runs on exactly one GPU (one MI355X); --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2602_20748_amd as rpq
@@ -118,106 +144,168 @@ def main():
     el = synth.workload_graph(args.workload)
     g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
     info = g.info()
-    opts = dict(batch_width=args.batch_width, concurrency=args.concurrency, sync_every=args.sync_every,
-                chunk_edges=args.chunk_edges)
-    per_source = torch.zeros((el.n_vertices, 2), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
+    forms = {}
 
-    qtimes = {q: 0.0 for q in queries}
+    # ------------------------------------------------------------------ plain form
+    if args.only in ("", "plain"):
+        opts = dict(batch_width=args.batch_width, concurrency=args.concurrency, sync_every=args.sync_every,
+                    chunk_edges=args.chunk_edges)
+        per_source = torch.zeros((el.n_vertices, 2), dtype=torch.int64, device="cuda")
+        qtimes = {q: 0.0 for q in queries}
 
-    def step():
-        out = []
+        def step():
+            out = []
+            for q in queries:
+                t = time.perf_counter()
+                nfa = rpq.rpq_nfa_compile(q, el.names)
+                out.append(rpq.rpq_eval(g, nfa, None, opts=opts, per_source=per_source))
+                qtimes[q] += time.perf_counter() - t
+            return out
+
+        for i in range(args.warmup):
+            print("bench: plain warmup %d" % i, file=sys.stderr, flush=True)
+            step()
+        torch.cuda.synchronize()
         for q in queries:
-            t = time.perf_counter()
-            nfa = rpq.rpq_nfa_compile(q, el.names)
-            out.append(rpq.rpq_eval(g, nfa, None, opts=opts, per_source=per_source))
-            qtimes[q] += time.perf_counter() - t
-        return out
+            qtimes[q] = 0.0
+        rpq.rpq_profile_read(reset=True)
+        rpq.rpq_profile_enable(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        eprod = pairs = 0
+        per_query = {}
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for i in range(args.steps):
+            for q, r in zip(queries, step()):
+                eprod += r.product_edges
+                pairs += r.count
+                per_query[q] = dict(count=r.count, hash="%016x" % r.hash, product_edges=r.product_edges,
+                                    levels=r.levels, max_depth=r.max_depth)
+            print("bench: plain step %d done" % i, file=sys.stderr, flush=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        rpq.rpq_profile_enable(False)
+        prof = rpq.rpq_profile_read(reset=True)
+        secs = ev0.elapsed_time(ev1) / 1e3
+        for q in queries:
+            per_query[q]["ms"] = round(qtimes[q] * 1e3 / max(1, args.steps), 3)
+        # dominant kernel of the plain form: the level expansion.  Algorithmic bytes:
+        # 4 B per edge item + 16 B per descriptor + 8 B per frontier word read
+        # + 8 B per visited-word read + 16 B per next-word OR (read + write)
+        launches = max(1, prof["expand_launches"])
+        alg = (4 * prof["edge_items"] + 16 * prof["descriptors"] + 8 * prof["row_words"]
+               + 8 * prof["word_reads"] + 16 * prof["word_updates"]) / launches
+        avg_ms = prof["expand_ms"] / launches
+        achieved = alg / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+        forms["plain"] = dict(
+            value=eprod / secs, ms_per_step=secs * 1e3 / args.steps, distinct_pairs_per_s=pairs / secs,
+            per_query=per_query,
+            roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
+                          frac=round(achieved / HBM_PEAK_GBPS, 5),
+                          traffic=load_traffic(args.traffic_file, "k_expand",
+                                               ["paper_2602_20748_amd/csrc/eval.hip"]),
+                          kernel="k_expand", avg_launch_ms=round(avg_ms, 5), launches=prof["expand_launches"],
+                          alg_bytes_per_launch=round(alg, 1),
+                          finalize_avg_ms=round(prof["finalize_ms"] / max(1, prof["finalize_launches"]), 5),
+                          counters={k: prof[k] for k in ("edge_items", "descriptors", "row_words", "word_reads",
+                                                         "word_updates", "expand_ms", "finalize_ms")}))
 
-    for i in range(args.warmup):
-        print("bench: warmup %d" % i, file=sys.stderr, flush=True)
-        step()
-    torch.cuda.synchronize()
-    for q in queries:
-        qtimes[q] = 0.0
-    rpq.rpq_profile_read(reset=True)
-    rpq.rpq_profile_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    eprod = 0
-    pairs = 0
-    per_query = {}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        res = step()
-        for q, r in zip(queries, res):
-            eprod += r.product_edges
-            pairs += r.count
-            per_query[q] = dict(count=r.count, hash="%016x" % r.hash, product_edges=r.product_edges,
-                                levels=r.levels, max_depth=r.max_depth)
-        print("bench: step %d done" % i, file=sys.stderr, flush=True)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    rpq.rpq_profile_enable(False)
-    prof = rpq.rpq_profile_read(reset=True)
-    secs = ev0.elapsed_time(ev1) / 1e3
-    ms_per_step = secs * 1e3 / args.steps
-    for q in queries:
-        per_query[q]["ms"] = round(qtimes[q] * 1e3 / max(1, args.steps), 3)
+    # ------------------------------------------------------------------ batched form
+    if args.only in ("", "batched"):
+        b = rpq.rpq_batch_create(g)
+        for q in queries:
+            b.add(rpq.rpq_nfa_compile(q, el.names), None, per_source=True)
+        tuned = None
+        if not args.no_autotune:
+            print("bench: autotuning the batch", file=sys.stderr, flush=True)
+            tuned = b.autotune()
+        for i in range(args.warmup):
+            print("bench: batched warmup %d" % i, file=sys.stderr, flush=True)
+            b.run()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        eprod = pairs = 0
+        kernel_ms = 0.0
+        tally = dict(edge_items=0, descriptors=0, word_reads=0, word_updates=0, finalized_rows=0,
+                     finalized_words=0, iterations=0)
+        per_query = {}
+        ev0.record(stream)
+        for i in range(args.steps):
+            b.run()
+            st = b.stats()
+            kernel_ms += st["last_kernel_ms"]
+            for k in tally:
+                tally[k] += st[k]
+            for qi, q in enumerate(queries):
+                r = b.result(qi)
+                eprod += r.product_edges
+                pairs += r.count
+                per_query[q] = dict(count=r.count, hash="%016x" % r.hash, product_edges=r.product_edges)
+            print("bench: batched step %d done" % i, file=sys.stderr, flush=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        secs = ev0.elapsed_time(ev1) / 1e3
+        st = b.stats()
+        K = st["row_words"]
+        # dominant kernel of the batched form: the persistent kernel (one launch per step).
+        # Algorithmic bytes = expansion (as in the plain form) + finalize (per row: 4 B id,
+        # 8K B next read, 8K B visited read, 8K B frontier-row write, 12 B label mask and slot;
+        # per non-zero word: 16 B next clear + visited write; 16 B per descriptor written)
+        # + compaction (8 B per touch word scanned per iteration, 4 B per row id).
+        exp = (4 * tally["edge_items"] + 16 * tally["descriptors"] + 8 * K * tally["descriptors"]
+               + 8 * tally["word_reads"] + 16 * tally["word_updates"])
+        fin = tally["finalized_rows"] * (4 + 24 * K + 12) + 16 * tally["finalized_words"] + 16 * tally["descriptors"]
+        cmp_ = 8 * tally["iterations"] * st["touch_words"] + 4 * tally["finalized_rows"]
+        alg = (exp + fin + cmp_) / max(1, args.steps)
+        kms = kernel_ms / max(1, args.steps)
+        achieved = alg / (kms / 1e3) / 1e9 if kms > 0 else 0.0
+        forms["batched"] = dict(
+            value=eprod / secs, ms_per_step=secs * 1e3 / args.steps, distinct_pairs_per_s=pairs / secs,
+            per_query=per_query, plan=dict(batch_width=st["batch_width"], slots=st["slots"], units=st["n_units"],
+                                           blocks=st["blocks"], tuned=tuned,
+                                           iterations_per_step=tally["iterations"] // max(1, args.steps),
+                                           phase_ms_last_step=st["phase_ms"]),
+            roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
+                          frac=round(achieved / HBM_PEAK_GBPS, 5),
+                          traffic=load_traffic(args.traffic_file, "k_batch",
+                                               ["paper_2602_20748_amd/csrc/batch.hip",
+                                                "paper_2602_20748_amd/csrc/internal.h"]),
+                          kernel="k_batch", avg_launch_ms=round(kms, 3), launches=args.steps,
+                          alg_bytes_per_launch=round(alg, 1),
+                          counters={k: v // max(1, args.steps) for k, v in tally.items()}))
+        b.close()
 
-    # roofline of the dominant kernel (level expansion): algorithmic bytes per launch
-    # = 4 B per edge item + 16 B per descriptor + 8 B per frontier word read
-    #   + 8 B per visited-word read + 16 B per next-word atomic OR (read + write)
-    launches = max(1, prof["expand_launches"])
-    alg_bytes = (4 * prof["edge_items"] + 16 * prof["descriptors"] + 8 * prof["row_words"]
-                 + 8 * prof["word_reads"] + 16 * prof["word_updates"])
-    bytes_per_launch = alg_bytes / launches
-    avg_ms = prof["expand_ms"] / launches
-    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = None
-    if os.path.exists(args.traffic_file):
-        try:
-            traffic = json.load(open(args.traffic_file)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBPS, 5), traffic=traffic,
-                    kernel="k_expand", avg_launch_ms=round(avg_ms, 5), launches=prof["expand_launches"],
-                    alg_bytes_per_launch=round(bytes_per_launch, 1),
-                    expand_share=round(prof["expand_ms"] / max(1e-9, prof["expand_ms"] + prof["finalize_ms"]), 4),
-                    finalize_avg_ms=round(prof["finalize_ms"] / max(1, prof["finalize_launches"]), 5),
-                    counters={k: prof[k] for k in ("edge_items", "descriptors", "row_words", "word_reads",
-                                                   "word_updates", "expand_ms", "finalize_ms")})
+    form = args.form if args.form in forms else next(iter(forms))
+    main_form = forms[form]
     cpu = None
     if args.cpu_baseline_seconds > 0:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(el, queries, args.cpu_baseline_seconds)
     line = {
         "metric": "product-graph edges/sec",
-        "value": eprod / secs,
+        "value": main_form["value"],
         "unit": "product-graph edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main_form["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic (seeded R-MAT; no dataset)",
         "config": {"workload": "%s: R-MAT scale 18, %d vertices, %d drawn / %d distinct edges, %d labels Zipf(1.1);"
-                               " all-pairs %s; plain form, one evaluation per query"
+                               " all-pairs %s; %s form"
                                % (args.workload, el.n_vertices, el.n_edges, info["n_edges"], el.n_labels,
-                                  ", ".join(queries)),
-                   "sources": el.n_vertices, "queries": queries, "form": "plain",
-                   "opts": {k: v for k, v in opts.items() if v}},
-        "distinct_pairs_per_s": pairs / secs,
-        "wall_s": wall,
-        "per_query": per_query,
-        "roofline": roofline,
+                                  ", ".join(queries), form),
+                   "sources": el.n_vertices, "queries": queries, "form": form},
+        "distinct_pairs_per_s": main_form["distinct_pairs_per_s"],
+        "batched_over_plain": (forms["batched"]["value"] / forms["plain"]["value"]
+                               if "batched" in forms and "plain" in forms else None),
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "roofline"} for k, v in forms.items()},
+        "roofline": main_form["roofline"],
+        "roofline_other": {k: v["roofline"] for k, v in forms.items() if k != form},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -262,8 +262,14 @@ typedef struct {
     uint32_t n_queries, n_units, slots, batch_width, blocks, reserved;
     uint64_t workspace_bytes;
     uint64_t iterations;         /* level iterations of the last run */
-    uint64_t edge_items, word_reads, word_updates;   /* expansion tallies of the last run */
+    uint64_t edge_items, descriptors, word_reads, word_updates;   /* expansion tallies, last run */
+    uint64_t finalized_rows, finalized_words;   /* finalize tallies: rows, non-zero next words */
+    uint64_t touch_words;        /* touch-bitmap words scanned per iteration */
+    uint64_t row_words;          /* K: 64-bit words per (state, vertex) row */
     double last_run_ms;          /* device time of the last graph launch */
+    double last_kernel_ms;       /* device time of the persistent kernel in it */
+    double phase_ms[8];          /* persistent-kernel time per phase: expand, compact, decide,
+                                    retire extract, retire keys, retire clear, refill+seed, finalize */
 } rpq_batch_info;
 
 /* Create an empty batch over graph g (host object; no device memory). opts may be NULL. */
@@ -305,6 +311,20 @@ int rpq_batch_result(rpq_batch_t b, uint32_t query_id, rpq_result* out);
 
 /* Plan and tallies of the batch (host struct). */
 int rpq_batch_stats(rpq_batch_t b, rpq_batch_info* out);
+
+/*
+ * Autotune the batch's unit width, slot count and descriptor size: each
+ * candidate (default set: widths 64..2048 x chunk 32/64 edges, slots sized
+ * automatically) whose plan fits in workspace_bytes runs a bounded prefix of
+ * the unit queue twice (capture, then replay), and the candidate with the most
+ * sources per millisecond on the replay wins.  The batch is re-planned with the
+ * winner (written to *best if non-NULL) and recaptured on its next run.
+ * Results of the timing runs are not meaningful; call rpq_batch_run afterwards.
+ * candidates: host array or NULL.  Errors: RPQ_ENOMEM if no candidate fits.
+ */
+int rpq_batch_autotune(rpq_batch_t b, const rpq_batch_opts* candidates, uint32_t n_candidates,
+                       void* workspace, uint64_t workspace_bytes, hipStream_t stream,
+                       rpq_batch_opts* best);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Profiling of the traversal kernels                                                         */

@@ -26,7 +26,7 @@ __all__ = [
     "RPQ_BUILD_IN_CSR", "RPQ_PAIRS", "RPQ_PER_SOURCE", "RPQ_ALL_SOURCES", "RPQ_REVERSE",
     "RPQ_MAX_STATES", "RPQ_MAX_LABELS", "EXPORTED_SYMBOLS", "rpq_profile_enable", "rpq_profile_read",
     "Batch", "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size",
-    "rpq_batch_run", "rpq_batch_result", "rpq_batch_stats",
+    "rpq_batch_run", "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -84,8 +84,11 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("n_queries", ctypes.c_uint32), ("n_units", ctypes.c_uint32), ("slots", ctypes.c_uint32),
                 ("batch_width", ctypes.c_uint32), ("blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("workspace_bytes", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
-                ("edge_items", ctypes.c_uint64), ("word_reads", ctypes.c_uint64), ("word_updates", ctypes.c_uint64),
-                ("last_run_ms", ctypes.c_double)]
+                ("edge_items", ctypes.c_uint64), ("descriptors", ctypes.c_uint64), ("word_reads", ctypes.c_uint64),
+                ("word_updates", ctypes.c_uint64), ("finalized_rows", ctypes.c_uint64),
+                ("finalized_words", ctypes.c_uint64), ("touch_words", ctypes.c_uint64), ("row_words", ctypes.c_uint64),
+                ("last_run_ms", ctypes.c_double), ("last_kernel_ms", ctypes.c_double),
+                ("phase_ms", ctypes.c_double * 8)]
 
 
 class _Result(ctypes.Structure):
@@ -101,7 +104,7 @@ EXPORTED_SYMBOLS = [
     "rpq_graph_export_csr", "rpq_nfa_compile", "rpq_nfa_reverse", "rpq_eval_workspace_size", "rpq_eval",
     "rpq_profile_enable", "rpq_profile_read",
     "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size", "rpq_batch_run",
-    "rpq_batch_result", "rpq_batch_stats",
+    "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune",
 ]
 
 _lib = None
@@ -144,6 +147,8 @@ def load_library():
         "rpq_batch_run": (ctypes.c_int, [vp, vp, u64, vp]),
         "rpq_batch_result": (ctypes.c_int, [vp, u32, ctypes.POINTER(_Result)]),
         "rpq_batch_stats": (ctypes.c_int, [vp, ctypes.POINTER(BatchInfo)]),
+        "rpq_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(BatchOpts), u32, vp, u64, vp,
+                                              ctypes.POINTER(BatchOpts)]),
         "rpq_profile_read": (ctypes.c_int, [ctypes.POINTER(Profile), ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -434,6 +439,9 @@ class Batch:
     def stats(self) -> dict:
         return rpq_batch_stats(self)
 
+    def autotune(self, candidates=None, workspace_bytes: int = 0, stream=None) -> dict:
+        return rpq_batch_autotune(self, candidates, workspace_bytes, stream)
+
 
 def rpq_batch_create(g: Graph, opts=None) -> Batch:
     o = None
@@ -511,4 +519,32 @@ def rpq_batch_result(b: Batch, qid: int) -> EvalResult:
 def rpq_batch_stats(b: Batch) -> dict:
     info = BatchInfo()
     _check(load_library().rpq_batch_stats(b.handle, ctypes.byref(info)))
-    return {name: getattr(info, name) for name, _ in BatchInfo._fields_}
+    out = {name: getattr(info, name) for name, _ in BatchInfo._fields_}
+    out["phase_ms"] = dict(zip(["expand", "compact", "decide", "retire_extract", "retire_keys", "retire_clear",
+                                "refill_seed", "finalize"], [round(x, 3) for x in info.phase_ms]))
+    return out
+
+
+def rpq_batch_autotune(b: Batch, candidates=None, workspace_bytes: int = 0, stream=None) -> dict:
+    """Pick the batch's width/slots/chunk by timing candidates (native tuner).
+
+    A workspace of workspace_bytes (default: 4x the current plan, at least 1 GiB) is
+    allocated for the timing runs and kept for the batch."""
+    torch = _torch()
+    if not workspace_bytes:
+        workspace_bytes = max(4 * rpq_batch_workspace_size(b), 1 << 30)
+    if b.ws is None or b.ws.numel() < workspace_bytes:
+        b.ws = None
+        b.ws = torch.empty(workspace_bytes, dtype=torch.uint8, device="cuda")
+    arr = None
+    n = 0
+    if candidates:
+        n = len(candidates)
+        arr = (BatchOpts * n)()
+        for i, c in enumerate(candidates):
+            for k, v in dict(c).items():
+                setattr(arr[i], k, int(v))
+    best = BatchOpts()
+    _check(load_library().rpq_batch_autotune(b.handle, arr, n, b.ws.data_ptr(), b.ws.numel(), _stream(stream),
+                                             ctypes.byref(best)))
+    return {name: getattr(best, name) for name, _ in BatchOpts._fields_}

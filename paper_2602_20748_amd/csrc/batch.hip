@@ -41,8 +41,8 @@ constexpr uint32_t S_IDLE = 0, S_RUN = 1, S_RETIRE = 2;
 
 struct Desc {
     uint32_t entry, beg;
-    uint32_t lenq;   // len | query << 16
-    uint32_t meta;   // label | q << 8 | slot << 13
+    uint32_t succ;   // delta(q, label) of the slot's automaton
+    uint32_t lens;   // len | slot << 16
 };
 
 struct BNfa {
@@ -84,7 +84,9 @@ struct BCtl {
     unsigned long long n_running, n_retiring, n_pairs_retiring;
     unsigned long long err, iterations;
     unsigned long long items, descs, wreads, wupds;
-    unsigned long long pad[2];
+    unsigned long long frows, fwords;   // finalize tallies: rows, non-zero next words
+    unsigned long long t_begin, t_end;  // constant-clock stamps (100 MHz) at kernel entry and exit
+    unsigned long long phase_ticks[8];  // constant-clock ticks per phase (block 0's view)
 };
 
 struct BArgs {
@@ -170,15 +172,14 @@ __device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t&
     const uint64_t n_batches = (n_desc + 63) / 64;
     for (uint64_t b = gwave(a); b < n_batches; b += gwaves(a)) {
         const uint64_t di = b * 64 + lane;
-        uint32_t len = 0, ent = 0, beg = 0, meta = 0, qq = 0;
+        uint32_t len = 0, ent = 0, beg = 0, succ0 = 0, lens = 0;
         if (di < n_desc) {
             const uint32_t* dw = reinterpret_cast<const uint32_t*>(desc + di);
             ent = xld(dw + 0);
             beg = xld(dw + 1);
-            const uint32_t lq = xld(dw + 2);
-            meta = xld(dw + 3);
-            len = lq & 0xFFFF;
-            qq = lq >> 16;
+            succ0 = xld(dw + 2);
+            lens = xld(dw + 3);
+            len = lens & 0xFFFF;
         }
         const uint32_t incl = rpqd::wave_incl_scan_u32(len);
         const uint32_t excl = incl - len;
@@ -198,14 +199,13 @@ __device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t&
             }
             const uint32_t c_ent = __shfl(ent, c, 64);
             const uint32_t c_beg = __shfl(beg, c, 64);
-            const uint32_t c_meta = __shfl(meta, c, 64);
+            const uint32_t c_succ = __shfl(succ0, c, 64);
+            const uint32_t c_lens = __shfl(lens, c, 64);
             const uint32_t c_ex = __shfl(excl, c, 64);
-            const uint32_t c_q = __shfl(qq, c, 64);
             if (item < total) {
                 const uint32_t w = a.dst[c_beg + (item - c_ex)];
-                const uint32_t lab = c_meta & 0xFF, q = (c_meta >> 8) & 0x1F, slot = c_meta >> 13;
-                const BNfa* nfa = a.nfas + c_q;
-                uint32_t succ = nfa->delta[q * L + lab];
+                const uint32_t slot = c_lens >> 16;
+                uint32_t succ = c_succ;
                 const uint64_t* fr = rows + (uint64_t)c_ent * K;
                 while (succ) {
                     const uint32_t q2 = __ffs(succ) - 1;
@@ -214,7 +214,7 @@ __device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t&
                     const uint64_t* vs = a.vis + row * K;
                     uint64_t* nx = a.next + row * K;
                     bool any = false;
-#pragma unroll
+#pragma unroll 1
                     for (int k0 = 0; k0 < K; k0 += kChunk) {
                         uint64_t f[kChunk], vw[kChunk];
                         uint64_t fany = 0;
@@ -534,7 +534,7 @@ __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
 // finalize: list p^1 -> frontier rows, Vis (with first-visit log), Ans (+ summary), descriptors
 // ------------------------------------------------------------------------------------------------
 template <int K>
-__device__ void phase_finalize(const BArgs& a, int p) {
+__device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_t& t_fwords) {
     const int np = p ^ 1;
     const uint64_t n = min((uint64_t)ld(&a.ctl->list_cnt[np]), a.list_cap);
     if (n == 0) return;
@@ -567,7 +567,7 @@ __device__ void phase_finalize(const BArgs& a, int p) {
             const bool is_final = (nfa->final >> q) & 1;
             uint32_t pc = 0;
             uint64_t vis_any = 0;
-#pragma unroll
+#pragma unroll 1
             for (int k0 = 0; k0 < K; k0 += kChunk) {
                 uint64_t nk[kChunk], vk[kChunk];
 #pragma unroll
@@ -583,10 +583,12 @@ __device__ void phase_finalize(const BArgs& a, int p) {
                         nx[k0 + k] = 0;
                         vs[k0 + k] = vk[k] | nk[k];
                         pc += (uint32_t)__popcll(nk[k]);
+                        ++t_fwords;
                         if (is_final) or_relaxed(&an[k0 + k], nk[k]);
                     }
                 }
             }
+            ++t_frows;
             if (is_final && pc) or_relaxed(&a.summ[(uint64_t)slot * a.summ_words + v / 64], 1ull << (v & 63));
             if (!vis_any && pc) {
                 const unsigned long long li = atomicAdd(&a.slots[slot].log_n, 1ull);
@@ -622,7 +624,6 @@ __device__ void phase_finalize(const BArgs& a, int p) {
             if (active && ndesc) {
                 uint64_t pos = dbase + incl - ndesc;
                 uint64_t mm = m;
-                const uint32_t meta_qs = (q << 8) | (slot << 13);
                 while (mm) {
                     const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
                     mm &= mm - 1;
@@ -633,8 +634,8 @@ __device__ void phase_finalize(const BArgs& a, int p) {
                             Desc dd;
                             dd.entry = (uint32_t)e;
                             dd.beg = b + o;
-                            dd.lenq = min(H, d - o) | (qid << 16);
-                            dd.meta = l | meta_qs;
+                            dd.succ = nfa->delta[q * L + l];
+                            dd.lens = min(H, d - o) | (slot << 16);
                             dout[pos] = dd;
                         } else {
                             atomicOr(&a.ctl->err, 2ull);
@@ -649,47 +650,55 @@ __device__ void phase_finalize(const BArgs& a, int p) {
 // ------------------------------------------------------------------------------------------------
 // the persistent kernel
 // ------------------------------------------------------------------------------------------------
-#define BAR()                                                              \
-    do {                                                                   \
-        if (!rpqd::grid_barrier(&a.ctl->gs, a.n_blocks, a.timeout)) return; \
+// grid barrier, then block 0 charges the time since the previous barrier to `phase`
+#define BAR(phase)                                                                   \
+    do {                                                                             \
+        if (!rpqd::grid_barrier(&a.ctl->gs, a.n_blocks, a.timeout)) return;          \
+        if (blockIdx.x == 0 && threadIdx.x == 0) {                                   \
+            const uint64_t now_ = wall_clock64();                                    \
+            a.ctl->phase_ticks[phase] += now_ - t_last;                              \
+            t_last = now_;                                                           \
+        }                                                                            \
     } while (0)
 
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_batch(BArgs a) {
-    uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0;
+__global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
+    uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0, t_frows = 0, t_fwords = 0;
     int p = 0;
     const uint64_t t_start = wall_clock64();
+    uint64_t t_last = t_start;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st64(&a.ctl->t_begin, t_start);
     for (uint32_t iter = 1;; ++iter) {
         // whole-kernel deadline: a run that exceeds it is abandoned (every block leaves at its
         // next barrier) and reported as an error
         if (blockIdx.x == 0 && threadIdx.x == 0 && wall_clock64() - t_start > a.deadline)
             __hip_atomic_store(&a.ctl->gs.abort, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         phase_expand<K>(a, p, t_items, t_descs, t_wread, t_wupd);
-        BAR();
+        BAR(0);
         phase_compact(a, p, iter);
-        BAR();
+        BAR(1);
         if (blockIdx.x == 0) phase_decide(a, iter);
-        BAR();
+        BAR(2);
         const uint32_t n_ret = (uint32_t)ld(&a.ctl->n_retiring);
         if (n_ret) {
             phase_retire_extract<K, false>(a, n_ret);
-            BAR();
+            BAR(3);
             if (ld(&a.ctl->n_pairs_retiring)) {
                 phase_retire_prefix(a, n_ret);
-                BAR();
+                BAR(4);
                 phase_retire_extract<K, true>(a, n_ret);
-                BAR();
+                BAR(4);
             }
             phase_retire_clear<K>(a, n_ret);
-            BAR();
+            BAR(5);
         }
         if (blockIdx.x == 0) phase_assign(a, iter);
-        BAR();
+        BAR(6);
         if (ld(&a.ctl->n_running) == 0) break;
         phase_seed<K>(a, p, iter);
-        BAR();
-        phase_finalize<K>(a, p);
-        BAR();
+        BAR(6);
+        phase_finalize<K>(a, p, t_frows, t_fwords);
+        BAR(7);
         p ^= 1;
         if (blockIdx.x == 0 && threadIdx.x == 0) st64(&a.ctl->iterations, iter);
     }
@@ -697,11 +706,20 @@ __global__ __launch_bounds__(kBlock) void k_batch(BArgs a) {
     t_descs = rpqd::wave_sum_u64(t_descs);
     t_wread = rpqd::wave_sum_u64(t_wread);
     t_wupd = rpqd::wave_sum_u64(t_wupd);
-    if ((threadIdx.x & 63) == 0 && t_items) {
-        atomicAdd(&a.ctl->items, (unsigned long long)t_items);
-        atomicAdd(&a.ctl->descs, (unsigned long long)t_descs);
-        atomicAdd(&a.ctl->wreads, (unsigned long long)t_wread);
-        atomicAdd(&a.ctl->wupds, (unsigned long long)t_wupd);
+    t_frows = rpqd::wave_sum_u64(t_frows);
+    t_fwords = rpqd::wave_sum_u64(t_fwords);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st64(&a.ctl->t_end, wall_clock64());
+    if ((threadIdx.x & 63) == 0) {
+        if (t_items) {
+            atomicAdd(&a.ctl->items, (unsigned long long)t_items);
+            atomicAdd(&a.ctl->descs, (unsigned long long)t_descs);
+            atomicAdd(&a.ctl->wreads, (unsigned long long)t_wread);
+            atomicAdd(&a.ctl->wupds, (unsigned long long)t_wupd);
+        }
+        if (t_frows) {
+            atomicAdd(&a.ctl->frows, (unsigned long long)t_frows);
+            atomicAdd(&a.ctl->fwords, (unsigned long long)t_fwords);
+        }
     }
 }
 #undef BAR
@@ -773,6 +791,8 @@ struct rpq_batch {
     BQueryOut* h_out = nullptr;      // pinned copy of the per-query outputs
     BCtl* h_ctl = nullptr;
     double last_ms = 0;
+    uint32_t unit_limit = 0;         // autotuning: run only the first units of the queue (0 = all)
+    double last_kernel_ms = 0;
 };
 
 namespace {
@@ -928,7 +948,7 @@ BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
     a.G = x.G;
     a.W = x.W;
     a.nchunks = x.nchunks;
-    a.n_units = x.n_units;
+    a.n_units = b->unit_limit ? std::min(x.n_units, b->unit_limit) : x.n_units;
     a.n_queries = (uint32_t)b->queries.size();
     a.n_blocks = n_blocks;
     a.slot_stride = x.slot_stride;
@@ -1223,6 +1243,8 @@ int rpq_batch_run(rpq_batch_t b, void* workspace, uint64_t workspace_bytes, hipS
     (void)hipEventDestroy(e1);
     b->last_ms = ms;
     RPQ_HIP(hipMemcpy(b->h_ctl, ws + x.off_ctl, sizeof(BCtl), hipMemcpyDeviceToHost));
+    // block 0 stamps the constant clock (100 MHz) when it enters and leaves the persistent kernel
+    if (b->h_ctl->t_end > b->h_ctl->t_begin) b->last_kernel_ms = (b->h_ctl->t_end - b->h_ctl->t_begin) / 1.0e5;
     if (b->h_ctl->gs.abort) {
         rpq::set_error(b->h_ctl->gs.abort == 2 ? "batched run exceeded its deadline and was abandoned"
                                                : "persistent kernel aborted at a grid barrier (grid not co-resident)");
@@ -1280,11 +1302,96 @@ int rpq_batch_stats(rpq_batch_t b, rpq_batch_info* out) {
     out->blocks = b->n_blocks;
     out->workspace_bytes = b->lay.total;
     out->last_run_ms = b->last_ms;
+    out->last_kernel_ms = b->last_kernel_ms;
+    if (b->h_ctl)
+        for (int i = 0; i < 8; ++i) out->phase_ms[i] = b->h_ctl->phase_ticks[i] / 1.0e5;
+    out->touch_words = b->lay.G * b->lay.slot_stride / 64;
+    out->row_words = b->lay.K;
     if (b->h_ctl) {
+        out->finalized_rows = b->h_ctl->frows;
+        out->finalized_words = b->h_ctl->fwords;
         out->iterations = b->h_ctl->iterations;
         out->edge_items = b->h_ctl->items;
+        out->descriptors = b->h_ctl->descs;
         out->word_reads = b->h_ctl->wreads;
         out->word_updates = b->h_ctl->wupds;
+    }
+    return RPQ_OK;
+}
+
+int rpq_batch_autotune(rpq_batch_t b, const rpq_batch_opts* candidates, uint32_t n_candidates, void* workspace,
+                       uint64_t workspace_bytes, hipStream_t stream, rpq_batch_opts* best) {
+    rpq::clear_error();
+    if (!b || !workspace) {
+        rpq::set_error("NULL argument");
+        return RPQ_EINVAL;
+    }
+    if (b->queries.empty()) {
+        if (best) *best = b->opts;
+        return RPQ_OK;
+    }
+    std::vector<rpq_batch_opts> cands;
+    if (candidates && n_candidates) {
+        cands.assign(candidates, candidates + n_candidates);
+    } else {
+        const uint32_t widths[] = {64, 256, 512, 1024, 2048};
+        const uint32_t chunks[] = {32, 64};
+        for (uint32_t w : widths)
+            for (uint32_t h : chunks) {
+                rpq_batch_opts o{};
+                o.batch_width = w;
+                o.chunk_edges = h;
+                cands.push_back(o);
+            }
+    }
+    const rpq_batch_opts saved = b->opts;
+    double best_rate = -1.0;
+    rpq_batch_opts best_opts = saved;
+    for (const rpq_batch_opts& c : cands) {
+        b->opts = c;
+        b->frozen = false;
+        if (plan(b) != RPQ_OK || b->lay.total > workspace_bytes) continue;
+        // time a bounded prefix of the unit queue: enough units for a few refills of every slot
+        const uint32_t prefix = std::max<uint32_t>(4 * b->lay.G, b->lay.n_units / 20);
+        b->unit_limit = std::min<uint32_t>(b->lay.n_units, prefix);
+        uint64_t sources_run = 0;
+        for (uint32_t u = 0; u < b->unit_limit; ++u) sources_run += b->units[u].n;
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        if (b->graph) {
+            (void)hipGraphDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        b->ws_captured = nullptr;
+        int rc = rpq_batch_run(b, workspace, workspace_bytes, stream);
+        if (rc == RPQ_OK) rc = rpq_batch_run(b, workspace, workspace_bytes, stream);   // replay: steady state
+        if (rc != RPQ_OK) continue;
+        const double rate = sources_run / std::max(1e-6, b->last_ms);
+        if (rate > best_rate) {
+            best_rate = rate;
+            best_opts = c;
+        }
+    }
+    // settle on the winner: full queue, fresh plan, capture on the next run
+    b->unit_limit = 0;
+    b->opts = best_rate > 0 ? best_opts : saved;
+    b->frozen = false;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    b->ws_captured = nullptr;
+    RPQ_TRY(plan(b));
+    if (best) *best = b->opts;
+    if (best_rate < 0) {
+        rpq::set_error("no autotuning candidate fits the workspace");
+        return RPQ_ENOMEM;
     }
     return RPQ_OK;
 }

@@ -66,9 +66,10 @@ constexpr uint64_t ERR_LIST = 1, ERR_DESC = 2, ERR_SOURCES = 4;
 
 // A unit of expansion work: edges [beg, beg + len) of one CSR row (v, label),
 // to be followed from frontier entry `entry` (state q, unit slot).
-// meta = label | q << 8 | slot << 13.
+// succ = delta(q, label): the successor states, so expansion needs no automaton lookup;
+// lens = len | slot << 16.
 struct Desc {
-    uint32_t entry, beg, len, meta;
+    uint32_t entry, beg, succ, lens;
 };
 
 struct DevNfa {
@@ -136,13 +137,14 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
 
     for (uint64_t b = wave; b < n_batches; b += n_waves) {
         const uint64_t di = b * 64 + lane;
-        uint32_t len = 0, ent = 0, beg = 0, meta = 0;
+        uint32_t len = 0, ent = 0, beg = 0, succ0 = 0, lens = 0;
         if (di < n_desc) {
             const Desc d = desc[di];
-            len = d.len;
             ent = d.entry;
             beg = d.beg;
-            meta = d.meta;
+            succ0 = d.succ;
+            lens = d.lens;
+            len = lens & 0xFFFF;
         }
         const uint32_t incl = rpqd::wave_incl_scan_u32(len);
         const uint32_t excl = incl - len;
@@ -163,12 +165,13 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
             }
             const uint32_t c_ent = __shfl(ent, c, 64);
             const uint32_t c_beg = __shfl(beg, c, 64);
-            const uint32_t c_meta = __shfl(meta, c, 64);
+            const uint32_t c_succ = __shfl(succ0, c, 64);
+            const uint32_t c_lens = __shfl(lens, c, 64);
             const uint32_t c_ex = __shfl(excl, c, 64);
             if (item < total) {
                 const uint32_t w = a.dst[c_beg + (item - c_ex)];
-                const uint32_t lab = c_meta & 0xFF, q = (c_meta >> 8) & 0x1F, slot = c_meta >> 13;
-                uint32_t succ = s_delta[q * L + lab];
+                const uint32_t slot = c_lens >> 16;
+                uint32_t succ = c_succ;
                 const uint64_t* fr = rows + (uint64_t)c_ent * K;
                 while (succ) {
                     const uint32_t q2 = __ffs(succ) - 1;
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
                     uint64_t* nx = a.next + row * K;
                     bool any = false;
                     // frontier and visited words in chunks of up to 8 (registers stay bounded)
-#pragma unroll
+#pragma unroll 1
                     for (int k0 = 0; k0 < K; k0 += kChunk) {
                         uint64_t f[kChunk], vw[kChunk];
                         uint64_t fany = 0;
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
             uint64_t* an = a.ans + ((uint64_t)slot * V + v) * K;
             const bool is_final = (fin >> q) & 1;
             uint32_t pc = 0;
-#pragma unroll
+#pragma unroll 1
             for (int k0 = 0; k0 < K; k0 += kChunk) {
                 uint64_t nk[kChunk], vk[kChunk];
 #pragma unroll
@@ -347,7 +350,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
             if (active && ndesc) {
                 uint64_t pos = dbase + incl - ndesc;
                 uint64_t mm = m;
-                const uint32_t meta_qs = (q << 8) | (slot << 13);
                 while (mm) {
                     const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
                     mm &= mm - 1;
@@ -358,8 +360,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
                             Desc dd;
                             dd.entry = (uint32_t)e;
                             dd.beg = b + o;
-                            dd.len = min(H, d - o);
-                            dd.meta = l | meta_qs;
+                            dd.succ = s_delta[q * L + l];
+                            dd.lens = min(H, d - o) | (slot << 16);
                             dout[pos] = dd;
                         } else {
                             atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_DESC);
@@ -630,7 +632,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
         G = std::min<uint64_t>(G, std::max<uint64_t>(1, kWorkspaceBudget / unit_bytes(QV, x.W)));
     }
     G = std::min<uint64_t>(G, units);
-    if (G > (1u << 19)) G = 1u << 19;   // slot ids travel in 19 bits of a descriptor
+    if (G > 65535) G = 65535;   // slot ids travel in 16 bits of a descriptor
     x.G = (uint32_t)G;
     x.list_cap = G * QV;
     if (x.list_cap >= 0xFFFFFFFFull) {
