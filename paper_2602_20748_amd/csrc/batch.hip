@@ -34,14 +34,14 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kChunk = 8;
+constexpr int kUnroll = 4;                 // rows per lane group loaded before any is updated
 constexpr uint32_t kChunkV = 4096;          // vertices per extraction chunk (64 summary words)
 
 constexpr uint32_t S_IDLE = 0, S_RUN = 1, S_RETIRE = 2;
 
 struct Desc {
     uint32_t entry, beg;
-    uint32_t succ;   // delta(q, label) of the slot's automaton
+    uint32_t state;  // one successor q' in delta(q, label) of the slot's automaton
     uint32_t lens;   // len | slot << 16
 };
 
@@ -158,26 +158,31 @@ __device__ __forceinline__ uint64_t gwave(const BArgs& a) {
 __device__ __forceinline__ uint64_t gwaves(const BArgs& a) { return (uint64_t)a.n_blocks * kWaves; }
 
 // ------------------------------------------------------------------------------------------------
-// expand: the level expansion of the plain form, per-slot automata
+// expand: the level expansion of the plain form (item phase: lane per edge item; word phase:
+// groups of K lanes per item, lane k on word k of the rows), with per-slot automata
 // ------------------------------------------------------------------------------------------------
 template <int K>
 __device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t& t_descs, uint64_t& t_wread,
                              uint64_t& t_wupd) {
+    constexpr int GS = 64 / K;
     const uint64_t n_desc = min((uint64_t)ld(&a.ctl->desc_cnt[p]), a.desc_cap);
     if (n_desc == 0) return;
     const int lane = threadIdx.x & 63;
+    const int grp = lane / K, k = lane % K;
+    const uint64_t gmask = (K == 64) ? ~0ull : (((1ull << K) - 1) << (grp * K));
     const Desc* desc = p ? a.desc1 : a.desc0;
     const uint64_t* rows = p ? a.rows1 : a.rows0;
-    const uint32_t L = a.L, V = a.V;
+    const uint32_t V = a.V;
+    const uint32_t stride = (uint32_t)a.slot_stride;
     const uint64_t n_batches = (n_desc + 63) / 64;
     for (uint64_t b = gwave(a); b < n_batches; b += gwaves(a)) {
         const uint64_t di = b * 64 + lane;
-        uint32_t len = 0, ent = 0, beg = 0, succ0 = 0, lens = 0;
+        uint32_t len = 0, ent = 0, beg = 0, st = 0, lens = 0;
         if (di < n_desc) {
             const uint32_t* dw = reinterpret_cast<const uint32_t*>(desc + di);
             ent = xld(dw + 0);
             beg = xld(dw + 1);
-            succ0 = xld(dw + 2);
+            st = xld(dw + 2);
             lens = xld(dw + 3);
             len = lens & 0xFFFF;
         }
@@ -199,47 +204,35 @@ __device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t&
             }
             const uint32_t c_ent = __shfl(ent, c, 64);
             const uint32_t c_beg = __shfl(beg, c, 64);
-            const uint32_t c_succ = __shfl(succ0, c, 64);
+            const uint32_t c_st = __shfl(st, c, 64);
             const uint32_t c_lens = __shfl(lens, c, 64);
             const uint32_t c_ex = __shfl(excl, c, 64);
+            uint32_t my_row = 0;
             if (item < total) {
                 const uint32_t w = a.dst[c_beg + (item - c_ex)];
-                const uint32_t slot = c_lens >> 16;
-                uint32_t succ = c_succ;
-                const uint64_t* fr = rows + (uint64_t)c_ent * K;
-                while (succ) {
-                    const uint32_t q2 = __ffs(succ) - 1;
-                    succ &= succ - 1;
-                    const uint64_t row = (uint64_t)slot * a.slot_stride + (uint64_t)q2 * V + w;
-                    const uint64_t* vs = a.vis + row * K;
-                    uint64_t* nx = a.next + row * K;
-                    bool any = false;
-#pragma unroll 1
-                    for (int k0 = 0; k0 < K; k0 += kChunk) {
-                        uint64_t f[kChunk], vw[kChunk];
-                        uint64_t fany = 0;
+                my_row = (c_lens >> 16) * stride + c_st * V + w;
+            }
+            const uint32_t n_here = min(64u, total - base);
+            for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
+                uint32_t r[kUnroll];
+                uint64_t f[kUnroll], vw[kUnroll];
 #pragma unroll
-                        for (int k = 0; k < kChunk; ++k) {
-                            f[k] = (k0 + k < K) ? xld(fr + k0 + k) : 0;
-                            fany |= f[k];
-                        }
-                        if (!fany) continue;
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t idx = j + u * GS + grp;
+                    r[u] = __shfl(my_row, idx & 63, 64);
+                    const uint32_t e = __shfl(c_ent, idx & 63, 64);
+                    f[u] = idx < n_here ? xld(rows + (uint64_t)e * K + k) : 0;
+                }
 #pragma unroll
-                        for (int k = 0; k < kChunk; ++k) vw[k] = (k0 + k < K) ? xld(vs + k0 + k) : 0;
+                for (int u = 0; u < kUnroll; ++u) vw[u] = f[u] ? xld(a.vis + (uint64_t)r[u] * K + k) : ~0ull;
 #pragma unroll
-                        for (int k = 0; k < kChunk; ++k) {
-                            if (f[k]) {
-                                ++t_wread;
-                                const uint64_t nb = f[k] & ~vw[k];
-                                if (nb) {
-                                    ++t_wupd;
-                                    or_relaxed(&nx[k0 + k], nb);
-                                    any = true;
-                                }
-                            }
-                        }
-                    }
-                    if (any) or_relaxed(&a.touch[row >> 6], 1ull << (row & 63));
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint64_t nb = f[u] & ~vw[u];
+                    t_wread += f[u] != 0;
+                    t_wupd += nb != 0;
+                    if (nb) or_relaxed(a.next + (uint64_t)r[u] * K + k, nb);
+                    const uint64_t hit = __ballot(nb != 0) & gmask;
+                    if (k == 0 && hit) or_relaxed(&a.touch[r[u] >> 6], 1ull << (r[u] & 63));
                 }
             }
         }
@@ -531,66 +524,83 @@ __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// finalize: list p^1 -> frontier rows, Vis (with first-visit log), Ans (+ summary), descriptors
+// finalize: list p^1 -> frontier rows, Vis (with first-visit log), Ans (+ summary), descriptors.
+// Word phase: groups of K lanes per row; row phase: lane per row (as in the plain form).
 // ------------------------------------------------------------------------------------------------
 template <int K>
 __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_t& t_fwords) {
+    constexpr int GS = 64 / K;
     const int np = p ^ 1;
     const uint64_t n = min((uint64_t)ld(&a.ctl->list_cnt[np]), a.list_cap);
     if (n == 0) return;
     const int lane = threadIdx.x & 63;
+    const int grp = lane / K, k = lane % K;
+    const uint64_t gmask = (K == 64) ? ~0ull : (((1ull << K) - 1) << (grp * K));
     const uint32_t* ids = np ? a.ids1 : a.ids0;
     uint64_t* rows = np ? a.rows1 : a.rows0;
     Desc* dout = np ? a.desc1 : a.desc0;
     unsigned long long* dcnt = &a.ctl->desc_cnt[np];
     const uint32_t H = a.H, L = a.L, V = a.V;
-    const uint64_t stride = (uint64_t)a.n_blocks * kBlock;
-    for (uint64_t e0 = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); e0 < n; e0 += stride) {
+    const uint32_t stride = (uint32_t)a.slot_stride;
+    for (uint64_t e0 = gwave(a) * 64; e0 < n; e0 += gwaves(a) * 64) {
         const uint64_t e = e0 + lane;
         const bool active = e < n;
-        uint32_t v = 0, q = 0, slot = 0, ndesc = 0, qid = 0;
+        uint32_t row32 = 0, slot = 0, lrow = 0, q = 0, v = 0, qid = 0, ndesc = 0;
         uint64_t m = 0, eprod = 0;
         const BNfa* nfa = a.nfas;
+        uint32_t my_ans = 0xFFFFFFFFu;   // Ans row of a final-state entry, else none
         if (active) {
-            const uint32_t row32 = xld(ids + e);
-            slot = (uint32_t)(row32 / a.slot_stride);
-            const uint32_t lrow = (uint32_t)(row32 - (uint64_t)slot * a.slot_stride);
+            row32 = xld(ids + e);
+            slot = row32 / stride;
+            lrow = row32 - slot * stride;
             q = lrow / V;
             v = lrow - q * V;
             qid = ld32(&a.slots[slot].query);
             nfa = a.nfas + qid;
-            const uint64_t row = row32;
-            uint64_t* nx = a.next + row * K;
-            uint64_t* vs = a.vis + row * K;
-            uint64_t* rw = rows + e * K;
-            uint64_t* an = a.ans + ((uint64_t)slot * V + v) * K;
-            const bool is_final = (nfa->final >> q) & 1;
-            uint32_t pc = 0;
-            uint64_t vis_any = 0;
-#pragma unroll 1
-            for (int k0 = 0; k0 < K; k0 += kChunk) {
-                uint64_t nk[kChunk], vk[kChunk];
+            if ((nfa->final >> q) & 1) my_ans = slot * V + v;
+        }
+        const uint32_t n_here = (uint32_t)min<uint64_t>(64, n - e0);
+        uint32_t my_info = 0;   // new source bits of this lane's row | 1 << 31 if Vis was non-empty
+        for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
+            uint32_t r[kUnroll], an[kUnroll];
+            uint64_t nk[kUnroll], vk[kUnroll];
 #pragma unroll
-                for (int k = 0; k < kChunk; ++k) nk[k] = (k0 + k < K) ? xld(nx + k0 + k) : 0;
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t idx = j + u * GS + grp;
+                r[u] = __shfl(row32, idx & 63, 64);
+                an[u] = __shfl(my_ans, idx & 63, 64);
+                const bool ok = idx < n_here;
+                nk[u] = ok ? xld(a.next + (uint64_t)r[u] * K + k) : 0;
+                vk[u] = ok ? xld(a.vis + (uint64_t)r[u] * K + k) : 0;
+            }
 #pragma unroll
-                for (int k = 0; k < kChunk; ++k) vk[k] = (k0 + k < K) ? xld(vs + k0 + k) : 0;
-#pragma unroll
-                for (int k = 0; k < kChunk; ++k) {
-                    if (k0 + k >= K) break;
-                    rw[k0 + k] = nk[k];
-                    vis_any |= vk[k];
-                    if (nk[k]) {
-                        nx[k0 + k] = 0;
-                        vs[k0 + k] = vk[k] | nk[k];
-                        pc += (uint32_t)__popcll(nk[k]);
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t idx = j + u * GS + grp;
+                uint32_t pc = 0;
+                if (idx < n_here) {
+                    rows[(e0 + idx) * K + k] = nk[u];
+                    if (nk[u]) {
+                        a.next[(uint64_t)r[u] * K + k] = 0;
+                        a.vis[(uint64_t)r[u] * K + k] = vk[u] | nk[u];
+                        pc = (uint32_t)__popcll(nk[u]);
                         ++t_fwords;
-                        if (is_final) or_relaxed(&an[k0 + k], nk[k]);
+                        if (an[u] != 0xFFFFFFFFu) or_relaxed(a.ans + (uint64_t)an[u] * K + k, nk[u]);
                     }
                 }
+#pragma unroll
+                for (int o = K / 2; o >= 1; o >>= 1) pc += __shfl_xor(pc, o, 64);
+                const uint32_t info = pc | ((__ballot(vk[u] != 0) & gmask) ? 0x80000000u : 0u);
+                const uint32_t rel = (uint32_t)lane - (j + u * GS);
+                const uint32_t got = __shfl(info, (rel % GS) * K, 64);
+                if (rel < (uint32_t)GS) my_info = got;
             }
+        }
+        if (active) {
+            const uint32_t pc = my_info & 0x7FFFFFFFu;
             ++t_frows;
-            if (is_final && pc) or_relaxed(&a.summ[(uint64_t)slot * a.summ_words + v / 64], 1ull << (v & 63));
-            if (!vis_any && pc) {
+            if (my_ans != 0xFFFFFFFFu && pc)
+                or_relaxed(&a.summ[(uint64_t)slot * a.summ_words + v / 64], 1ull << (v & 63));
+            if (!(my_info >> 31) && pc) {
                 const unsigned long long li = atomicAdd(&a.slots[slot].log_n, 1ull);
                 if (li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = lrow;
             }
@@ -602,8 +612,9 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
                 mm &= mm - 1;
                 const uint32_t r = v * L + l;
                 const uint32_t d = a.row_ptr[r + 1] - a.row_ptr[r];
-                wsum += (uint64_t)d * (uint32_t)__popc(nfa->delta[q * L + l]);
-                ndesc += (d + H - 1) / H;
+                const uint32_t ns = (uint32_t)__popc(nfa->delta[q * L + l]);
+                wsum += (uint64_t)d * ns;
+                ndesc += ns * ((d + H - 1) / H);
             }
             eprod = (uint64_t)pc * wsum;
         }
@@ -629,16 +640,21 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
                     mm &= mm - 1;
                     const uint32_t r = v * L + l;
                     const uint32_t b = a.row_ptr[r], d = a.row_ptr[r + 1] - b;
-                    for (uint32_t o = 0; o < d; o += H, ++pos) {
-                        if (pos < a.desc_cap) {
-                            Desc dd;
-                            dd.entry = (uint32_t)e;
-                            dd.beg = b + o;
-                            dd.succ = nfa->delta[q * L + l];
-                            dd.lens = min(H, d - o) | (slot << 16);
-                            dout[pos] = dd;
-                        } else {
-                            atomicOr(&a.ctl->err, 2ull);
+                    uint32_t succ = nfa->delta[q * L + l];
+                    while (succ) {
+                        const uint32_t q2 = __ffs(succ) - 1;
+                        succ &= succ - 1;
+                        for (uint32_t o = 0; o < d; o += H, ++pos) {
+                            if (pos < a.desc_cap) {
+                                Desc dd;
+                                dd.entry = (uint32_t)e;
+                                dd.beg = b + o;
+                                dd.state = q2;
+                                dd.lens = min(H, d - o) | (slot << 16);
+                                dout[pos] = dd;
+                            } else {
+                                atomicOr(&a.ctl->err, 2ull);
+                            }
                         }
                     }
                 }
@@ -821,7 +837,7 @@ int plan(rpq_batch* b) {
         return RPQ_EINVAL;
     }
     x.K = x.W / 64;
-    x.H = b->opts.chunk_edges ? b->opts.chunk_edges : 64;
+    x.H = b->opts.chunk_edges ? b->opts.chunk_edges : 16;
     if (x.H > 65535) {
         rpq::set_error("chunk_edges must be <= 65535");
         return RPQ_EINVAL;
@@ -851,8 +867,8 @@ int plan(rpq_batch* b) {
                               x.summ_words * 8 + x.slot_stride * 4;
     uint64_t G = b->opts.slots;
     if (!G) {
-        const uint64_t budget = 32ull << 30;
-        G = std::max<uint64_t>(1, std::min<uint64_t>(std::max<uint64_t>(1, 32768 / x.W), budget / per_slot));
+        const uint64_t budget = 64ull << 30;
+        G = std::max<uint64_t>(1, std::min<uint64_t>(std::max<uint64_t>(1, 65536 / x.W), budget / per_slot));
     }
     G = std::min<uint64_t>(G, std::max<uint32_t>(1, x.n_units));
     G = std::min<uint64_t>(G, 1024);
@@ -864,10 +880,16 @@ int plan(rpq_batch* b) {
     x.nchunks = (uint32_t)((g->V + kChunkV - 1) / kChunkV);
     // frontier list: worst case every row of every slot in one level
     x.list_cap = (uint64_t)x.G * x.slot_stride;
+    // descriptors: one per (frontier row, label, successor state, chunk of H edges)
+    uint32_t max_succ = 1;
+    for (auto& q : b->queries)
+        for (uint32_t i = 0; i < RPQ_MAX_STATES * RPQ_MAX_LABELS; ++i)
+            max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(q.nfa.delta[i]));
     uint64_t dper = 0;
     for (uint32_t q = 0; q < x.Qmax; ++q) dper += g->out.nonempty_rows + (g->E + x.H - 1) / x.H + 1;
-    x.desc_cap = (uint64_t)x.G * std::min<uint64_t>(dper, (uint64_t)x.Qmax * g->V * std::min<uint32_t>(g->L, 64) +
-                                                           (uint64_t)x.Qmax * ((g->E + x.H - 1) / x.H + 1));
+    x.desc_cap = (uint64_t)x.G * max_succ *
+                 std::min<uint64_t>(dper, (uint64_t)x.Qmax * g->V * std::min<uint32_t>(g->L, 64) +
+                                              (uint64_t)x.Qmax * ((g->E + x.H - 1) / x.H + 1));
     x.stage_keys = 0;
     for (auto& q : b->queries)
         if (q.pairs) x.stage_keys += q.capacity;
@@ -1335,7 +1357,7 @@ int rpq_batch_autotune(rpq_batch_t b, const rpq_batch_opts* candidates, uint32_t
         cands.assign(candidates, candidates + n_candidates);
     } else {
         const uint32_t widths[] = {64, 256, 512, 1024, 2048};
-        const uint32_t chunks[] = {32, 64};
+        const uint32_t chunks[] = {16, 32, 64};
         for (uint32_t w : widths)
             for (uint32_t h : chunks) {
                 rpq_batch_opts o{};

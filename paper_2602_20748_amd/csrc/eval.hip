@@ -44,7 +44,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kChunk = 8;   // frontier words handled together per edge item
 
 // counters[] slots (uint64)
 constexpr int C_LIST = 0;       // [0..1] list length per parity
@@ -64,12 +63,11 @@ constexpr int C_NCOUNTERS = 16;
 
 constexpr uint64_t ERR_LIST = 1, ERR_DESC = 2, ERR_SOURCES = 4;
 
-// A unit of expansion work: edges [beg, beg + len) of one CSR row (v, label),
-// to be followed from frontier entry `entry` (state q, unit slot).
-// succ = delta(q, label): the successor states, so expansion needs no automaton lookup;
-// lens = len | slot << 16.
+// A unit of expansion work: edges [beg, beg + len) of one CSR row (v, label), to be followed
+// from frontier entry `entry` into successor state `state` (one q' of delta(q, label); a row
+// with several successors gets one descriptor per successor).  lens = len | slot << 16.
 struct Desc {
-    uint32_t entry, beg, succ, lens;
+    uint32_t entry, beg, state, lens;
 };
 
 struct DevNfa {
@@ -118,31 +116,42 @@ __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint6
 }
 
 // ------------------------------------------------------------------------------------------------
-// level expansion: one lane per edge item, each item carrying all K words of its frontier row
+// level expansion.  Work is mapped twice per batch of 64 edge items:
+//   item phase  lane i takes item i: finds its descriptor (prefix of the wave's descriptor
+//               lengths), loads the edge target w (consecutive lanes, consecutive CSR slots)
+//               and forms the target row id (slot, q', w);
+//   word phase  the wave splits into 64/K groups of K lanes; group g takes items g, g + 64/K, ...
+//               and lane k of the group handles word k of the row, so the frontier row, the
+//               visited row and the Next row of an item are each read or updated as one
+//               contiguous K-word access instead of K scattered ones.
+// kUnroll items per group are loaded before any of them is updated (memory-level parallelism).
 // ------------------------------------------------------------------------------------------------
+constexpr int kUnroll = 4;
+
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
-    __shared__ uint32_t s_delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];
-    load_nfa(a, s_delta, nullptr, nullptr);
+    constexpr int GS = 64 / K;   // item groups per wave
     const uint64_t n_desc = min((uint64_t)a.counters[C_DESC + p], a.desc_cap);
     if (n_desc == 0) return;
     const int lane = threadIdx.x & 63;
+    const int grp = lane / K, k = lane % K;
+    const uint64_t gmask = (K == 64) ? ~0ull : (((1ull << K) - 1) << (grp * K));
     const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
     const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     const uint64_t n_batches = (n_desc + 63) / 64;
     const Desc* desc = desc_of(a, p);
     const uint64_t* rows = rows_of(a, p);
-    const uint32_t L = a.L, Q = a.Q, V = a.V;
+    const uint32_t Q = a.Q, V = a.V;
     uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0;
 
     for (uint64_t b = wave; b < n_batches; b += n_waves) {
         const uint64_t di = b * 64 + lane;
-        uint32_t len = 0, ent = 0, beg = 0, succ0 = 0, lens = 0;
+        uint32_t len = 0, ent = 0, beg = 0, st = 0, lens = 0;
         if (di < n_desc) {
             const Desc d = desc[di];
             ent = d.entry;
             beg = d.beg;
-            succ0 = d.succ;
+            st = d.state;
             lens = d.lens;
             len = lens & 0xFFFF;
         }
@@ -154,8 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
             t_descs += (uint64_t)min<uint64_t>(64, n_desc - b * 64);
         }
         for (uint32_t base = 0; base < total; base += 64) {
+            // item phase
             const uint32_t item = base + lane;
-            // descriptor of this item: the last lane c with excl[c] <= item
             int c = 0;
 #pragma unroll
             for (int step = 32; step >= 1; step >>= 1) {
@@ -165,48 +174,36 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
             }
             const uint32_t c_ent = __shfl(ent, c, 64);
             const uint32_t c_beg = __shfl(beg, c, 64);
-            const uint32_t c_succ = __shfl(succ0, c, 64);
+            const uint32_t c_st = __shfl(st, c, 64);
             const uint32_t c_lens = __shfl(lens, c, 64);
             const uint32_t c_ex = __shfl(excl, c, 64);
+            uint32_t my_row = 0;
             if (item < total) {
                 const uint32_t w = a.dst[c_beg + (item - c_ex)];
-                const uint32_t slot = c_lens >> 16;
-                uint32_t succ = c_succ;
-                const uint64_t* fr = rows + (uint64_t)c_ent * K;
-                while (succ) {
-                    const uint32_t q2 = __ffs(succ) - 1;
-                    succ &= succ - 1;
-                    const uint64_t row = ((uint64_t)slot * Q + q2) * V + w;
-                    const uint64_t* vs = a.vis + row * K;
-                    uint64_t* nx = a.next + row * K;
-                    bool any = false;
-                    // frontier and visited words in chunks of up to 8 (registers stay bounded)
-#pragma unroll 1
-                    for (int k0 = 0; k0 < K; k0 += kChunk) {
-                        uint64_t f[kChunk], vw[kChunk];
-                        uint64_t fany = 0;
+                my_row = ((c_lens >> 16) * Q + c_st) * V + w;
+            }
+            const uint32_t n_here = min(64u, total - base);
+            // word phase
+            for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
+                uint32_t r[kUnroll];
+                uint64_t f[kUnroll], vw[kUnroll];
 #pragma unroll
-                        for (int k = 0; k < kChunk; ++k) {
-                            f[k] = (k0 + k < K) ? fr[k0 + k] : 0;
-                            fany |= f[k];
-                        }
-                        if (!fany) continue;
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t idx = j + u * GS + grp;
+                    r[u] = __shfl(my_row, idx & 63, 64);
+                    const uint32_t e = __shfl(c_ent, idx & 63, 64);
+                    f[u] = idx < n_here ? rows[(uint64_t)e * K + k] : 0;
+                }
 #pragma unroll
-                        for (int k = 0; k < kChunk; ++k) vw[k] = (k0 + k < K) ? vs[k0 + k] : 0;
+                for (int u = 0; u < kUnroll; ++u) vw[u] = f[u] ? a.vis[(uint64_t)r[u] * K + k] : ~0ull;
 #pragma unroll
-                        for (int k = 0; k < kChunk; ++k) {
-                            if (f[k]) {
-                                ++t_wread;
-                                const uint64_t nb = f[k] & ~vw[k];
-                                if (nb) {
-                                    ++t_wupd;
-                                    or_relaxed(&nx[k0 + k], nb);
-                                    any = true;
-                                }
-                            }
-                        }
-                    }
-                    if (any) or_relaxed(&a.touch[row >> 6], 1ull << (row & 63));
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint64_t nb = f[u] & ~vw[u];
+                    t_wread += f[u] != 0;
+                    t_wupd += nb != 0;
+                    if (nb) or_relaxed(&a.next[(uint64_t)r[u] * K + k], nb);
+                    const uint64_t hit = __ballot(nb != 0) & gmask;
+                    if (k == 0 && hit) or_relaxed(&a.touch[r[u] >> 6], 1ull << (r[u] & 63));
                 }
             }
         }
@@ -268,12 +265,16 @@ __global__ __launch_bounds__(kBlock) void k_compact(Args a, int p, uint64_t n_ro
 }
 
 // ------------------------------------------------------------------------------------------------
-// finalize: one thread per new frontier row.  Next moves into the compact frontier row, Vis and
-// (for final states) Ans take the new bits, the product edges the row will examine are counted,
-// and its out-edges are cut into descriptors of at most H edges per label.
+// finalize.  Per batch of 64 new frontier rows:
+//   word phase  groups of K lanes take a row each (lane k, word k): Next moves into the compact
+//               frontier row, Vis and (for final states) Ans take the new bits, and the group
+//               counts the new source bits of the row;
+//   row phase   lane i takes row i: counts the product edges it will examine and cuts its
+//               out-edges into descriptors of at most H edges per (label, successor state).
 // ------------------------------------------------------------------------------------------------
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
+    constexpr int GS = 64 / K;
     __shared__ uint32_t s_delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];
     __shared__ uint64_t s_qlab[RPQ_MAX_STATES];
     __shared__ uint32_t s_final;
@@ -282,6 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
     const uint64_t n = min((uint64_t)a.counters[C_LIST + np], a.list_cap);
     if (n == 0) return;
     const int lane = threadIdx.x & 63;
+    const int grp = lane / K, k = lane % K;
     const uint32_t* ids = ids_of(a, np);
     uint64_t* rows = rows_of(a, np);
     Desc* dout = desc_of(a, np);
@@ -290,44 +292,56 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
     const uint32_t QV = a.Q * a.V;
     const uint32_t fin = s_final;
     uint64_t eprod = 0;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t e0 = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); e0 < n; e0 += stride) {
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
+    const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    for (uint64_t e0 = wave * 64; e0 < n; e0 += n_waves * 64) {
         const uint64_t e = e0 + lane;
         const bool active = e < n;
-        uint32_t v = 0, q = 0, slot = 0, ndesc = 0;
-        uint64_t m = 0;
-        if (active) {
-            const uint32_t row32 = ids[e];
-            slot = row32 / QV;
-            const uint32_t rem = row32 - slot * QV;
-            q = rem / V;
-            v = rem - q * V;
-            const uint64_t row = row32;
-            uint64_t* nx = a.next + row * K;
-            uint64_t* vs = a.vis + row * K;
-            uint64_t* rw = rows + e * K;
-            uint64_t* an = a.ans + ((uint64_t)slot * V + v) * K;
-            const bool is_final = (fin >> q) & 1;
-            uint32_t pc = 0;
-#pragma unroll 1
-            for (int k0 = 0; k0 < K; k0 += kChunk) {
-                uint64_t nk[kChunk], vk[kChunk];
+        const uint32_t my_row = active ? ids[e] : 0;
+        const uint32_t slot = my_row / QV;
+        const uint32_t rem = my_row - slot * QV;
+        const uint32_t q = rem / V;
+        const uint32_t v = rem - q * V;
+        // Ans row of a final-state entry, else none
+        const uint32_t my_ans = ((fin >> q) & 1) ? slot * V + v : 0xFFFFFFFFu;
+        const uint32_t n_here = (uint32_t)min<uint64_t>(64, n - e0);
+        uint32_t my_pc = 0;
+        // word phase
+        for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
+            uint32_t r[kUnroll], an[kUnroll];
+            uint64_t nk[kUnroll];
 #pragma unroll
-                for (int k = 0; k < kChunk; ++k) nk[k] = (k0 + k < K) ? nx[k0 + k] : 0;
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t idx = j + u * GS + grp;
+                r[u] = __shfl(my_row, idx & 63, 64);
+                an[u] = __shfl(my_ans, idx & 63, 64);
+                nk[u] = idx < n_here ? a.next[(uint64_t)r[u] * K + k] : 0;
+            }
 #pragma unroll
-                for (int k = 0; k < kChunk; ++k) vk[k] = (k0 + k < K) ? vs[k0 + k] : 0;
-#pragma unroll
-                for (int k = 0; k < kChunk; ++k) {
-                    if (k0 + k >= K) break;
-                    rw[k0 + k] = nk[k];
-                    if (nk[k]) {
-                        nx[k0 + k] = 0;
-                        vs[k0 + k] = vk[k] | nk[k];
-                        pc += (uint32_t)__popcll(nk[k]);
-                        if (is_final) or_relaxed(&an[k0 + k], nk[k]);
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t idx = j + u * GS + grp;
+                uint32_t pc = 0;
+                if (idx < n_here) {
+                    rows[(e0 + idx) * K + k] = nk[u];
+                    if (nk[u]) {
+                        a.next[(uint64_t)r[u] * K + k] = 0;
+                        or_relaxed(&a.vis[(uint64_t)r[u] * K + k], nk[u]);
+                        if (an[u] != 0xFFFFFFFFu) or_relaxed(&a.ans[(uint64_t)an[u] * K + k], nk[u]);
+                        pc = (uint32_t)__popcll(nk[u]);
                     }
                 }
+#pragma unroll
+                for (int o = K / 2; o >= 1; o >>= 1) pc += __shfl_xor(pc, o, 64);
+                // lane i keeps the count of row i
+                const uint32_t rel = (uint32_t)lane - (j + u * GS);
+                const uint32_t got = __shfl(pc, (rel % GS) * K, 64);
+                if (rel < (uint32_t)GS) my_pc = got;
             }
+        }
+        // row phase
+        uint32_t ndesc = 0;
+        uint64_t m = 0;
+        if (active) {
             m = a.lmask[v] & s_qlab[q];
             uint64_t wsum = 0;
             uint64_t mm = m;
@@ -336,10 +350,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
                 mm &= mm - 1;
                 const uint32_t r = v * L + l;
                 const uint32_t d = a.row_ptr[r + 1] - a.row_ptr[r];
-                wsum += (uint64_t)d * (uint32_t)__popc(s_delta[q * L + l]);
-                ndesc += (d + H - 1) / H;
+                const uint32_t ns = (uint32_t)__popc(s_delta[q * L + l]);
+                wsum += (uint64_t)d * ns;
+                ndesc += ns * ((d + H - 1) / H);
             }
-            eprod += (uint64_t)pc * wsum;
+            eprod += (uint64_t)my_pc * wsum;
         }
         const uint32_t incl = rpqd::wave_incl_scan_u32(ndesc);
         const uint32_t tot = __shfl(incl, 63, 64);
@@ -355,16 +370,21 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
                     mm &= mm - 1;
                     const uint32_t r = v * L + l;
                     const uint32_t b = a.row_ptr[r], d = a.row_ptr[r + 1] - b;
-                    for (uint32_t o = 0; o < d; o += H, ++pos) {
-                        if (pos < a.desc_cap) {
-                            Desc dd;
-                            dd.entry = (uint32_t)e;
-                            dd.beg = b + o;
-                            dd.succ = s_delta[q * L + l];
-                            dd.lens = min(H, d - o) | (slot << 16);
-                            dout[pos] = dd;
-                        } else {
-                            atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_DESC);
+                    uint32_t succ = s_delta[q * L + l];
+                    while (succ) {
+                        const uint32_t q2 = __ffs(succ) - 1;
+                        succ &= succ - 1;
+                        for (uint32_t o = 0; o < d; o += H, ++pos) {
+                            if (pos < a.desc_cap) {
+                                Desc dd;
+                                dd.entry = (uint32_t)e;
+                                dd.beg = b + o;
+                                dd.state = q2;
+                                dd.lens = min(H, d - o) | (slot << 16);
+                                dout[pos] = dd;
+                            } else {
+                                atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_DESC);
+                            }
                         }
                     }
                 }
@@ -585,11 +605,15 @@ void to_dev_nfa(const rpq_nfa* nfa, uint32_t L, DevNfa* d) {
         }
 }
 
-// Default shape: aim for about 32K sources in flight (measured on R-MAT scale 18:
-// throughput rises with the sources advanced per level until ~16K-32K), the widest
-// unit that the source count fills, and per-call workspace within ~24 GB.
-constexpr uint64_t kTargetInFlight = 32768;
-constexpr uint64_t kWorkspaceBudget = 24ull << 30;
+// Default shape: about 64K sources in flight, in units of up to 2048 sources, with
+// descriptors of at most 16 edges (measured on R-MAT scale 18, all-pairs: throughput
+// rises with the sources advanced per level up to ~64K; 2048-wide units beat 1024 and
+// 4096 at equal sources in flight; 16-edge descriptors beat 32 and 64), and per-call
+// workspace within 64 GB of the 288 GB device.
+constexpr uint64_t kTargetInFlight = 65536;
+constexpr uint64_t kWorkspaceBudget = 64ull << 30;
+constexpr uint32_t kMaxDefaultWidth = 2048;
+constexpr uint32_t kDefaultChunk = 16;
 
 uint64_t unit_bytes(uint64_t QV, uint32_t W) {
     // Vis + Next + two frontier lists of rows + row ids
@@ -598,7 +622,7 @@ uint64_t unit_bytes(uint64_t QV, uint32_t W) {
 
 uint32_t default_width(uint64_t n_sources, uint64_t QV) {
     uint32_t W = 64;
-    while (W < 4096 && (uint64_t)W * 2 <= std::max<uint64_t>(64, n_sources / 8)) W *= 2;
+    while (W < kMaxDefaultWidth && (uint64_t)W * 2 <= std::max<uint64_t>(64, n_sources / 8)) W *= 2;
     while (W > 64 && unit_bytes(QV, W) > kWorkspaceBudget) W /= 2;
     return W;
 }
@@ -617,7 +641,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
         return RPQ_EINVAL;
     }
     x.K = x.W / 64;
-    x.H = (o && o->chunk_edges) ? o->chunk_edges : 64;
+    x.H = (o && o->chunk_edges) ? o->chunk_edges : kDefaultChunk;
     if (x.H > 65535) {
         rpq::set_error("chunk_edges must be <= 65535");
         return RPQ_EINVAL;
@@ -642,7 +666,9 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     uint64_t dper = 0;
     for (uint32_t q = 0; q < x.Q; ++q) {
         const uint64_t rows_q = std::min<uint64_t>((uint64_t)x.V * popc64(dn.qlab[q]), csr.nonempty_rows);
-        dper += rows_q + (g->E + x.H - 1) / x.H + 1;
+        uint32_t max_succ = 0;
+        for (uint32_t l = 0; l < x.L; ++l) max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(dn.delta[q * x.L + l]));
+        dper += (uint64_t)max_succ * (rows_q + (g->E + x.H - 1) / x.H + 1);
     }
     x.desc_cap = G * dper;
     x.chunk_v = 4096;
@@ -700,7 +726,28 @@ Args make_args(const rpq_graph* g, uint32_t flags, const Layout& x, char* ws) {
     return a;
 }
 
-constexpr unsigned kLevelGrid = 2048;
+// Grid of a level kernel: as many blocks as the device keeps resident at once (the kernels
+// stride over their work, so a grid beyond residency would only add a tail round).
+unsigned resident_grid(const void* kernel) {
+    int dev = 0, n_cu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || n_cu <= 0 ||
+        per_cu <= 0)
+        return 2048;
+    return (unsigned)(n_cu * per_cu);
+}
+
+template <int K>
+struct LevelGrids {
+    unsigned expand, compact, finalize;
+    static const LevelGrids& get() {
+        static const LevelGrids g{resident_grid(reinterpret_cast<const void*>(&k_expand<K>)),
+                                  resident_grid(reinterpret_cast<const void*>(&k_compact)),
+                                  resident_grid(reinterpret_cast<const void*>(&k_finalize<K>))};
+        return g;
+    }
+};
 
 // Process-wide profiling state: event pairs around level kernels, resolved at
 // the host synchronisation points of rpq_eval.
@@ -767,12 +814,12 @@ int launch_level(const Args& a, int p, uint64_t n_rows, uint32_t level, hipStrea
         e2 = pr.get();
     }
     if (e0) RPQ_HIP(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(k_expand<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL(k_expand<K>, dim3(LevelGrids<K>::get().expand), dim3(kBlock), 0, s, a, p);
     RPQ_LAUNCH_CHECK();
     if (e1) RPQ_HIP(hipEventRecord(e1, s));
-    hipLaunchKernelGGL(k_compact, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p, n_rows, level);
+    hipLaunchKernelGGL(k_compact, dim3(LevelGrids<K>::get().compact), dim3(kBlock), 0, s, a, p, n_rows, level);
     RPQ_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_finalize<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL(k_finalize<K>, dim3(LevelGrids<K>::get().finalize), dim3(kBlock), 0, s, a, p);
     RPQ_LAUNCH_CHECK();
     if (e2) RPQ_HIP(hipEventRecord(e2, s));
     if (on && e0 && e1 && e2) {
@@ -791,9 +838,9 @@ void profile_resolve() {
 
 template <int K>
 int launch_finalize(const Args& a, int p, uint64_t n_rows, uint32_t level, hipStream_t s) {
-    hipLaunchKernelGGL(k_compact, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p, n_rows, level);
+    hipLaunchKernelGGL(k_compact, dim3(LevelGrids<K>::get().compact), dim3(kBlock), 0, s, a, p, n_rows, level);
     RPQ_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_finalize<K>, dim3(kLevelGrid), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL(k_finalize<K>, dim3(LevelGrids<K>::get().finalize), dim3(kBlock), 0, s, a, p);
     RPQ_LAUNCH_CHECK();
     return RPQ_OK;
 }

@@ -155,24 +155,24 @@ struct GridSync {
 };
 
 __device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned int n_blocks, uint64_t timeout_ticks) {
-    // A fence orders only the memory operations of the wave that executes it, so every
-    // wave releases its own global writes (stores and no-return atomics) before the
-    // workgroup meets, and every wave acquires (drops stale L1 lines) after the grid met.
-    __threadfence();
+    // The workgroup meets first (its writes happen-before thread 0's release fence); thread 0
+    // alone releases, arrives, waits and acquires for the whole workgroup, and the workgroup
+    // meets again before any wave reads.  One agent-scope fence pair per workgroup per barrier:
+    // on gfx950 each agent-scope fence writes back and invalidates the XCD's L2.
     __syncthreads();
     __shared__ int s_ok;
     if (threadIdx.x == 0) {
         int ok = 1;
-        const unsigned int gen = __hip_atomic_load(&gs->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
+        const unsigned int gen = __hip_atomic_load(&gs->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();   // release (also keeps the generation read before the arrival)
         const unsigned int arrived =
-            __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == n_blocks - 1) {
             __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&gs->generation, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&gs->generation, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(&gs->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     ok = 0;
                     break;
@@ -186,11 +186,10 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned int n_blocks
             }
         }
         if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-        __threadfence();
+        __threadfence();   // acquire
         s_ok = ok;
     }
     __syncthreads();
-    __threadfence();
     return s_ok != 0;
 }
 
