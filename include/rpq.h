@@ -173,6 +173,11 @@ int rpq_nfa_reverse(const rpq_nfa* in, rpq_nfa* out);
 #define RPQ_ALL_SOURCES  4u   /* sources == NULL: every vertex 0 .. n_vertices-1 */
 #define RPQ_REVERSE      8u   /* walk in-edges with the reversed automaton: for each given
                                  vertex y, the x with (x, y) in R(rho); keys are (y << 32) | x */
+#define RPQ_SPARSE      16u   /* per-source search with a device hash set of (source, state,
+                                 vertex) instead of per-unit bitmaps: workspace grows with what
+                                 the sources reach, not with V * states * sources (for few
+                                 sources on a large graph).  Same results; levels counts the
+                                 search's non-empty frontiers. */
 
 /* Tuning knobs; zero fields take defaults (the autotuner's choice when one is cached). */
 typedef struct {
@@ -211,6 +216,7 @@ typedef struct {
     uint64_t product_edges;
     uint64_t levels;
     uint64_t max_depth;
+    uint64_t workspace_needed;   /* out, on RPQ_ENOMEM: a workspace size to retry with */
 } rpq_result;
 
 /* Device workspace bytes rpq_eval needs for this query shape. */
@@ -327,6 +333,184 @@ int rpq_batch_stats(rpq_batch_t b, rpq_batch_info* out);
 int rpq_batch_autotune(rpq_batch_t b, const rpq_batch_opts* candidates, uint32_t n_candidates,
                        void* workspace, uint64_t workspace_bytes, hipStream_t stream,
                        rpq_batch_opts* best);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Conjunctive regular path queries                                                           */
+/* ------------------------------------------------------------------------------------------ */
+
+#define CRPQ_MAX_VARS 16
+#define CRPQ_MAX_ATOMS 16
+
+/* One atom x -rho-> y of a CRPQ (Definition 2): rho as an epsilon-free NFA (host struct). */
+typedef struct {
+    uint32_t src_var, dst_var;   /* variable ids below n_vars; src_var == dst_var is allowed */
+    rpq_nfa nfa;
+} crpq_atom;
+
+/* The query's variables (host struct; every pointer may be NULL = no constraint of that kind).
+ *   binding[i]       >= 0 fixes variable i to that vertex (a constant of the query); -1 = free
+ *   vertex_label[i]  >= 0 requires the vertex label of f(i) to equal it (Definition 2,
+ *                    condition 1); -1 = any.  Needs a graph created with vertex labels.
+ *   domain[i]        device array of domain_size[i] vertex ids (any order, duplicates allowed):
+ *                    f(i) must be one of them (a sample of the vertex set); NULL = any
+ *   neq[2 j], neq[2 j + 1]   pairs of variables that must map to different vertices
+ * Variables that appear in no atom range over their domain (a cartesian factor). */
+typedef struct {
+    uint32_t n_vars;
+    const int64_t* binding;
+    const int32_t* vertex_label;
+    const uint32_t* const* domain;
+    const uint64_t* domain_size;
+    const uint32_t* neq;
+    uint32_t n_neq;
+} crpq_vars;
+
+/* crpq_eval flags: how atoms are traversed (default: chosen per atom, see crpq_eval) */
+#define CRPQ_FORCE_DENSE   1u   /* every multi-step atom by the bit-parallel traversal */
+#define CRPQ_FORCE_SPARSE  2u   /* every multi-step atom by the per-source hash-set search */
+#define CRPQ_NO_EDGE_SCAN  4u   /* single-label atoms are traversed like the others */
+#define CRPQ_NO_REVERSE    8u   /* never traverse an atom backwards */
+
+/* Per-atom strategy codes reported in crpq_result.atom_strategy */
+#define CRPQ_STRATEGY_EDGE_SCAN 1u
+#define CRPQ_STRATEGY_DENSE     2u
+#define CRPQ_STRATEGY_SPARSE    3u
+#define CRPQ_STRATEGY_REVERSED  0x100u   /* or-ed in when the atom ran backwards from dst_var */
+
+/* Result of crpq_eval (host struct).
+ *   tuples, capacity: device buffer of capacity rows of n_free uint32 (row-major), or NULL
+ *     for count and checksum only.  Rows are the distinct assignments of the free variables
+ *     (those without a binding) in declared order, sorted lexicographically.
+ *   count: number of distinct rows; hash: sum over rows of the chained mix
+ *     m = mix64(v_1), m = mix64(m ^ v_i) for i = 2 .. n_free, modulo 2^64 (order-free).
+ *   written: rows written (min(count, capacity)).
+ *   workspace_needed: on RPQ_ENOMEM, a workspace size to retry with.
+ *   atom_pairs / atom_strategy: per atom, the size of its relation after the domain filters
+ *     and how it was evaluated; join_rows: largest intermediate table of the join. */
+typedef struct {
+    uint32_t* tuples;
+    uint64_t capacity;
+    uint64_t count, hash, written;
+    uint32_t n_free, reserved;
+    uint64_t workspace_needed;
+    uint64_t atom_pairs[CRPQ_MAX_ATOMS];
+    uint32_t atom_strategy[CRPQ_MAX_ATOMS];
+    uint64_t join_rows;
+} crpq_result;
+
+/*
+ * Evaluate a CRPQ (Definition 2): every homomorphism f from the variables to vertices with
+ * f(x) -> f(y) joined by a walk whose label word is in L(rho) for every atom, the vertex-label
+ * condition, the bindings, domains and inequalities.  The atoms are evaluated first and their
+ * results joined (Section 6.2):
+ *   1. domains: one bitmap of V bits per variable (binding, label, domain intersected);
+ *   2. atoms, smallest source domain first, each traversed from the smaller of its two
+ *      domains (backwards on the in-CSR when that is dst_var's), its result restricted to
+ *      both domains; after each atom the domains of its variables shrink to the values that
+ *      occur in its result (semi-join reduction).  An atom whose language holds only
+ *      one-label words is an edge scan; otherwise up to 65,536 sources take the bit-parallel
+ *      traversal of rpq_eval and more take a per-source search with a device hash set;
+ *   3. join: variables are bound one at a time in a matching order (constants and small
+ *      domains first, then the variable most connected to bound ones); for each partial row
+ *      the candidates of the new variable come from the shortest list among the atoms that
+ *      connect it to bound variables, and are checked against the other atoms, its domain
+ *      and the inequalities.  An atom needed in the direction opposite to how it was
+ *      materialised is transposed first.  When tuples == NULL the last variable is counted
+ *      and hashed without being materialised.
+ * graph: created with RPQ_BUILD_IN_CSR for backward traversal (else forward only).
+ * workspace: device, 256-byte aligned; every intermediate lives in it.  If it is too small the
+ *   call returns RPQ_ENOMEM with res->workspace_needed set: call again with that much.
+ * Errors: RPQ_EINVAL (bad variable ids, vertex ids, labels, automata, n_vars == 0 or above
+ *   CRPQ_MAX_VARS, n_atoms above CRPQ_MAX_ATOMS, vertex labels without graph labels),
+ *   RPQ_EOVERFLOW (count > capacity: the first capacity rows are written, count and hash are
+ *   complete), RPQ_ENOMEM, RPQ_EUNSUPPORTED (states * vertices >= 2^32), RPQ_EDEVICE.
+ */
+int crpq_eval(rpq_graph_t graph, const crpq_atom* atoms, uint32_t n_atoms, const crpq_vars* vars,
+              uint32_t flags, void* workspace, uint64_t workspace_bytes, crpq_result* res,
+              hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Serving: continuous admission of requests over one resident graph                          */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * A server keeps one graph resident and runs requests (RPQs and CRPQs) as they arrive.  Each
+ * request needs a workspace: its visited sets (per-unit bitmaps of V * states * unit-width bits,
+ * or the hash set of RPQ_SPARSE) and its traversal state.  Workspaces are carved from one device
+ * pool that the caller hands over at start (first fit, 256-byte aligned); the server never
+ * allocates device memory.  A request is admitted when its workspace fits in the free part of
+ * the pool (a request may pass queued ones that do not fit yet, unless the oldest has waited
+ * more than 50 ms), and runs at once on one of `workers` host threads, each with its own HIP
+ * stream, so the work of admitted requests overlaps on the device.  A dense RPQ larger than the
+ * whole pool is split: fewer source units in flight (and narrower units), the same result.  A
+ * request that asks for more workspace while running (RPQ_SPARSE, CRPQ) goes back to the front
+ * of the queue with the larger size.  This is the counterpart, across requests, of the paper's
+ * pooled segment memory (Section 5) and of its temporary reduction of the start-vertex batch when
+ * that pool runs short (ablation study, Section 8.4).
+ * Results are identical to running each request alone.
+ */
+typedef struct rpq_server* rpq_server_t;
+
+typedef struct {
+    uint32_t workers;     /* requests in flight at once (0 = 4), each on its own stream */
+    uint32_t reserved;
+} rpq_server_opts;
+
+#define RPQ_REQ_RPQ  1u
+#define RPQ_REQ_CRPQ 2u
+
+/* One request (host struct, copied by rpq_serve_submit; device buffers it names must stay
+ * valid until the request is done). */
+typedef struct {
+    uint32_t kind;                /* RPQ_REQ_RPQ or RPQ_REQ_CRPQ */
+    uint32_t flags;               /* rpq_eval flags (RPQ_REQ_RPQ) or crpq_eval flags (RPQ_REQ_CRPQ) */
+    double arrival_ms;            /* scheduled arrival on the server clock (rpq_serve_clock_ms), or
+                                     < 0 for the time of submission; latency is measured from it */
+    /* RPQ_REQ_RPQ: as rpq_eval */
+    rpq_nfa nfa;
+    const uint32_t* sources;      /* device, ascending; NULL with RPQ_ALL_SOURCES */
+    uint64_t n_sources;
+    uint64_t* pairs;              /* device [capacity] or NULL */
+    uint64_t capacity;
+    uint64_t* per_source;         /* device [n_sources][2] or NULL */
+    /* RPQ_REQ_CRPQ: as crpq_eval (host arrays are copied; domain arrays are device memory) */
+    const crpq_atom* atoms;
+    uint32_t n_atoms;
+    crpq_vars vars;
+    uint32_t* tuples;             /* device [tuple_capacity][n_free] or NULL */
+    uint64_t tuple_capacity;
+} rpq_request;
+
+/* State of one request (host struct). */
+typedef struct {
+    int32_t status;               /* rpq_status once done (RPQ_EOVERFLOW: outputs truncated) */
+    uint32_t done;                /* 0 while queued or running */
+    uint64_t count, hash, product_edges, written;
+    uint64_t workspace_bytes;     /* pool bytes the request ran with */
+    double arrival_ms, start_ms, end_ms;   /* server clock */
+} rpq_ticket;
+
+typedef struct {
+    uint64_t submitted, completed, failed, queued, running;
+    uint64_t pool_bytes, pool_in_use, pool_peak;
+    uint64_t product_edges;       /* over completed requests */
+} rpq_server_stats;
+
+/* Start a server on graph g with the device pool [pool, pool + pool_bytes) (256-byte aligned). */
+int rpq_serve_start(rpq_graph_t g, const rpq_server_opts* opts, void* pool, uint64_t pool_bytes,
+                    rpq_server_t* out);
+/* Queue a request; *ticket identifies it.  RPQ_ENOMEM if it can never fit in the pool,
+ * RPQ_EINVAL for a malformed request (checked before queueing). */
+int rpq_serve_submit(rpq_server_t s, const rpq_request* req, uint64_t* ticket);
+/* Current state of a request (done = 0 while pending). */
+int rpq_serve_poll(rpq_server_t s, uint64_t ticket, rpq_ticket* out);
+/* Block until the request is done, then as rpq_serve_poll. */
+int rpq_serve_wait(rpq_server_t s, uint64_t ticket, rpq_ticket* out);
+/* Milliseconds since rpq_serve_start on the server's monotonic clock. */
+int rpq_serve_clock_ms(rpq_server_t s, double* out);
+int rpq_serve_stats(rpq_server_t s, rpq_server_stats* out);
+/* Finish every queued and running request, join the workers and free the server. */
+int rpq_serve_stop(rpq_server_t s);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Profiling of the traversal kernels                                                         */

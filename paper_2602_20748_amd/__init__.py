@@ -23,17 +23,21 @@ __all__ = [
     "rpq_nfa_reverse", "rpq_graph_create", "rpq_graph_destroy", "rpq_graph_info_get",
     "rpq_graph_export_csr", "rpq_eval_workspace_size", "rpq_eval", "EvalResult", "Graph", "Nfa", "EvalOpts",
     "RPQ_OK", "RPQ_EINVAL", "RPQ_ENOMEM", "RPQ_EOVERFLOW", "RPQ_EDEVICE", "RPQ_EUNSUPPORTED",
-    "RPQ_BUILD_IN_CSR", "RPQ_PAIRS", "RPQ_PER_SOURCE", "RPQ_ALL_SOURCES", "RPQ_REVERSE",
+    "RPQ_BUILD_IN_CSR", "RPQ_PAIRS", "RPQ_PER_SOURCE", "RPQ_ALL_SOURCES", "RPQ_REVERSE", "RPQ_SPARSE",
     "RPQ_MAX_STATES", "RPQ_MAX_LABELS", "EXPORTED_SYMBOLS", "rpq_profile_enable", "rpq_profile_read",
     "Batch", "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size",
     "rpq_batch_run", "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune",
+    "crpq_eval", "CrpqOutput", "CrpqAtom", "CrpqVars", "CrpqResult", "CRPQ_FORCE_DENSE", "CRPQ_FORCE_SPARSE",
+    "CRPQ_NO_EDGE_SCAN", "CRPQ_NO_REVERSE", "CRPQ_STRATEGY_EDGE_SCAN", "CRPQ_STRATEGY_DENSE",
+    "CRPQ_STRATEGY_SPARSE", "CRPQ_STRATEGY_REVERSED", "Server", "Request", "Ticket", "ServerOpts", "ServerStats",
+    "RPQ_REQ_RPQ", "RPQ_REQ_CRPQ",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 RPQ_OK, RPQ_EINVAL, RPQ_ENOMEM, RPQ_EOVERFLOW, RPQ_EDEVICE, RPQ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RPQ_BUILD_IN_CSR = 1
-RPQ_PAIRS, RPQ_PER_SOURCE, RPQ_ALL_SOURCES, RPQ_REVERSE = 1, 2, 4, 8
+RPQ_PAIRS, RPQ_PER_SOURCE, RPQ_ALL_SOURCES, RPQ_REVERSE, RPQ_SPARSE = 1, 2, 4, 8, 16
 RPQ_MAX_STATES, RPQ_MAX_LABELS = 32, 64
 
 _STATUS = {0: "RPQ_OK", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM", -3: "RPQ_EOVERFLOW", -4: "RPQ_EDEVICE",
@@ -95,7 +99,59 @@ class _Result(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("per_source", ctypes.c_void_p),
                 ("pair_offset", ctypes.c_uint64), ("written", ctypes.c_uint64), ("count", ctypes.c_uint64),
                 ("hash", ctypes.c_uint64), ("product_edges", ctypes.c_uint64), ("levels", ctypes.c_uint64),
-                ("max_depth", ctypes.c_uint64)]
+                ("max_depth", ctypes.c_uint64), ("workspace_needed", ctypes.c_uint64)]
+
+
+CRPQ_MAX_VARS = 16
+CRPQ_MAX_ATOMS = 16
+CRPQ_FORCE_DENSE, CRPQ_FORCE_SPARSE, CRPQ_NO_EDGE_SCAN, CRPQ_NO_REVERSE = 1, 2, 4, 8
+CRPQ_STRATEGY_EDGE_SCAN, CRPQ_STRATEGY_DENSE, CRPQ_STRATEGY_SPARSE, CRPQ_STRATEGY_REVERSED = 1, 2, 3, 0x100
+
+
+class CrpqAtom(ctypes.Structure):
+    _fields_ = [("src_var", ctypes.c_uint32), ("dst_var", ctypes.c_uint32), ("nfa", Nfa)]
+
+
+class CrpqVars(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_uint32), ("binding", ctypes.POINTER(ctypes.c_int64)),
+                ("vertex_label", ctypes.POINTER(ctypes.c_int32)), ("domain", ctypes.POINTER(ctypes.c_void_p)),
+                ("domain_size", ctypes.POINTER(ctypes.c_uint64)), ("neq", ctypes.POINTER(ctypes.c_uint32)),
+                ("n_neq", ctypes.c_uint32)]
+
+
+class CrpqResult(ctypes.Structure):
+    _fields_ = [("tuples", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("count", ctypes.c_uint64),
+                ("hash", ctypes.c_uint64), ("written", ctypes.c_uint64), ("n_free", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("workspace_needed", ctypes.c_uint64),
+                ("atom_pairs", ctypes.c_uint64 * CRPQ_MAX_ATOMS), ("atom_strategy", ctypes.c_uint32 * CRPQ_MAX_ATOMS),
+                ("join_rows", ctypes.c_uint64)]
+
+
+RPQ_REQ_RPQ, RPQ_REQ_CRPQ = 1, 2
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("arrival_ms", ctypes.c_double),
+                ("nfa", Nfa), ("sources", ctypes.c_void_p), ("n_sources", ctypes.c_uint64),
+                ("pairs", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("per_source", ctypes.c_void_p),
+                ("atoms", ctypes.POINTER(CrpqAtom)), ("n_atoms", ctypes.c_uint32), ("vars", CrpqVars),
+                ("tuples", ctypes.c_void_p), ("tuple_capacity", ctypes.c_uint64)]
+
+
+class Ticket(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("done", ctypes.c_uint32), ("count", ctypes.c_uint64),
+                ("hash", ctypes.c_uint64), ("product_edges", ctypes.c_uint64), ("written", ctypes.c_uint64),
+                ("workspace_bytes", ctypes.c_uint64), ("arrival_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("end_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "queued", "running",
+                                                "pool_bytes", "pool_in_use", "pool_peak", "product_edges")]
 
 
 # Every symbol include/rpq.h declares (checked by the CPU test suite).
@@ -105,6 +161,8 @@ EXPORTED_SYMBOLS = [
     "rpq_profile_enable", "rpq_profile_read",
     "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size", "rpq_batch_run",
     "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune",
+    "crpq_eval", "rpq_serve_start", "rpq_serve_submit", "rpq_serve_poll", "rpq_serve_wait", "rpq_serve_clock_ms",
+    "rpq_serve_stats", "rpq_serve_stop",
 ]
 
 _lib = None
@@ -150,6 +208,15 @@ def load_library():
         "rpq_batch_autotune": (ctypes.c_int, [vp, ctypes.POINTER(BatchOpts), u32, vp, u64, vp,
                                               ctypes.POINTER(BatchOpts)]),
         "rpq_profile_read": (ctypes.c_int, [ctypes.POINTER(Profile), ctypes.c_int]),
+        "crpq_eval": (ctypes.c_int, [vp, ctypes.POINTER(CrpqAtom), u32, ctypes.POINTER(CrpqVars), u32, vp, u64,
+                                     ctypes.POINTER(CrpqResult), vp]),
+        "rpq_serve_start": (ctypes.c_int, [vp, ctypes.POINTER(ServerOpts), vp, u64, ctypes.POINTER(vp)]),
+        "rpq_serve_submit": (ctypes.c_int, [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]),
+        "rpq_serve_poll": (ctypes.c_int, [vp, u64, ctypes.POINTER(Ticket)]),
+        "rpq_serve_wait": (ctypes.c_int, [vp, u64, ctypes.POINTER(Ticket)]),
+        "rpq_serve_clock_ms": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "rpq_serve_stats": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
+        "rpq_serve_stop": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -373,15 +440,22 @@ def rpq_eval(g: Graph, nfa: Nfa, sources=None, flags: int = 0, opts=None, pairs=
     need = ctypes.c_uint64()
     _check(lib.rpq_eval_workspace_size(g.handle, ctypes.byref(nfa), n, flags,
                                        ctypes.byref(o) if o is not None else None, ctypes.byref(need)))
-    ws = workspace if workspace is not None else g.workspace(int(need.value))
-    res = _Result()
-    res.pairs = pairs.data_ptr() if pairs is not None else None
-    res.capacity = int(capacity or 0)
-    res.per_source = per_source.data_ptr() if per_source is not None else None
-    res.pair_offset = int(pair_offset)
-    rc = lib.rpq_eval(g.handle, ctypes.byref(nfa), src_t.data_ptr() if (src_t is not None and n) else None, n, flags,
-                      ctypes.byref(o) if o is not None else None, ws.data_ptr(), ws.numel(), ctypes.byref(res),
-                      _stream(stream))
+    ws_bytes = int(need.value)
+    for _ in range(16):
+        ws = workspace if workspace is not None else g.workspace(ws_bytes)
+        res = _Result()
+        res.pairs = pairs.data_ptr() if pairs is not None else None
+        res.capacity = int(capacity or 0)
+        res.per_source = per_source.data_ptr() if per_source is not None else None
+        res.pair_offset = int(pair_offset)
+        rc = lib.rpq_eval(g.handle, ctypes.byref(nfa), src_t.data_ptr() if (src_t is not None and n) else None, n,
+                          flags, ctypes.byref(o) if o is not None else None, ws.data_ptr(), ws.numel(),
+                          ctypes.byref(res), _stream(stream))
+        # the sparse search asks for more room when the sources reach more than it planned for
+        if rc == RPQ_ENOMEM and workspace is None and res.workspace_needed > ws.numel():
+            ws_bytes = int(res.workspace_needed)
+            continue
+        break
     _check(rc, allow=(RPQ_EOVERFLOW,) if allow_overflow else ())
     out_pairs = pairs[: res.written] if pairs is not None else None
     return EvalResult(int(res.count), int(res.hash), int(res.product_edges), int(res.levels), int(res.max_depth),
@@ -548,3 +622,232 @@ def rpq_batch_autotune(b: Batch, candidates=None, workspace_bytes: int = 0, stre
     _check(load_library().rpq_batch_autotune(b.handle, arr, n, b.ws.data_ptr(), b.ws.numel(), _stream(stream),
                                              ctypes.byref(best)))
     return {name: getattr(best, name) for name, _ in BatchOpts._fields_}
+
+
+# ---------------------------------------------------------------------------------------------
+# CRPQ
+# ---------------------------------------------------------------------------------------------
+class CrpqOutput:
+    """Result of crpq_eval: distinct assignments of the free variables."""
+
+    def __init__(self, r: CrpqResult, tuples, n_atoms: int, status: int):
+        self.count = int(r.count)
+        self.hash = int(r.hash)
+        self.written = int(r.written)
+        self.n_free = int(r.n_free)
+        self.tuples = tuples      # int32 CUDA tensor [written, n_free] (uint32 bits) or None
+        self.atom_pairs = [int(r.atom_pairs[i]) for i in range(n_atoms)]
+        self.atom_strategy = [int(r.atom_strategy[i]) for i in range(n_atoms)]
+        self.join_rows = int(r.join_rows)
+        self.status = status
+
+
+def _crpq_marshal(g: Graph, atoms, n_vars: int, binding, vertex_label, domain, neq, torch):
+    """ctypes atoms and variables of a CRPQ, plus the objects that must outlive the call."""
+    n_atoms = len(atoms)
+    arr = (CrpqAtom * max(1, n_atoms))()
+    for i, (x, rx, y) in enumerate(atoms):
+        arr[i].src_var = int(x)
+        arr[i].dst_var = int(y)
+        arr[i].nfa = rx if isinstance(rx, Nfa) else rpq_nfa_compile(rx, g.names)
+    v = CrpqVars()
+    v.n_vars = int(n_vars)
+    keep = [arr]
+    if binding is not None:
+        b = (ctypes.c_int64 * n_vars)(*[(-1 if x is None else int(x)) for x in binding])
+        keep.append(b)
+        v.binding = ctypes.cast(b, ctypes.POINTER(ctypes.c_int64))
+    if vertex_label is not None:
+        vl = (ctypes.c_int32 * n_vars)(*[(-1 if x is None else int(x)) for x in vertex_label])
+        keep.append(vl)
+        v.vertex_label = ctypes.cast(vl, ctypes.POINTER(ctypes.c_int32))
+    if domain is not None:
+        ptrs = (ctypes.c_void_p * n_vars)()
+        sizes = (ctypes.c_uint64 * n_vars)()
+        for i, d in enumerate(domain):
+            if d is None:
+                continue
+            t = _dev_u32(d, torch)
+            keep.append(t)
+            ptrs[i] = t.data_ptr() if t.numel() else None
+            sizes[i] = t.numel()
+            if not t.numel():   # an empty domain: a pointer is still needed to mean "constrained"
+                z = torch.zeros(1, dtype=torch.int32, device="cuda")
+                keep.append(z)
+                ptrs[i] = z.data_ptr()
+        keep += [ptrs, sizes]
+        v.domain = ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
+        v.domain_size = ctypes.cast(sizes, ctypes.POINTER(ctypes.c_uint64))
+    neq = list(neq)
+    if neq:
+        nq = (ctypes.c_uint32 * (2 * len(neq)))(*[int(x) for p in neq for x in p])
+        keep.append(nq)
+        v.neq = ctypes.cast(nq, ctypes.POINTER(ctypes.c_uint32))
+        v.n_neq = len(neq)
+    return arr, v, keep
+
+
+def _n_free(n_vars, binding):
+    return sum(1 for i in range(n_vars) if binding is None or binding[i] is None or binding[i] < 0)
+
+
+def crpq_eval(g: Graph, atoms, n_vars: int, binding=None, vertex_label=None, domain=None, neq=(),
+              tuples: bool = False, capacity: Optional[int] = None, flags: int = 0,
+              workspace_bytes: Optional[int] = None, stream=None, allow_overflow: bool = False) -> CrpqOutput:
+    """Evaluate a CRPQ (see crpq_eval in include/rpq.h).
+
+    atoms: sequence of (src_var, regex string or Nfa, dst_var).  binding / vertex_label: per
+    variable, None or -1 for no constraint.  domain: per variable, None or a vertex list (host
+    array or CUDA tensor).  neq: pairs of variables that must differ.  tuples=True returns the
+    sorted tuples (capacity rows, default: all of them).  The device workspace grows as the
+    library asks for it.
+    """
+    torch = _torch()
+    lib = load_library()
+    n_atoms = len(atoms)
+    arr, v, keep = _crpq_marshal(g, atoms, n_vars, binding, vertex_label, domain, neq, torch)
+    if workspace_bytes:
+        ws_bytes = int(workspace_bytes)
+    else:   # a quarter of the free device memory, at most 32 GiB
+        free, _ = torch.cuda.mem_get_info()
+        ws_bytes = max(256 << 20, min(free // 4, 32 << 30))
+    cap = capacity if capacity is not None else (1 << 20)
+    for attempt in range(12):
+        r = CrpqResult()
+        out_t = None
+        if tuples:
+            out_t = torch.empty((max(1, cap), max(1, _n_free(n_vars, binding))), dtype=torch.int32, device="cuda")
+            r.tuples = out_t.data_ptr()
+            r.capacity = cap
+        ws = g.workspace(ws_bytes)
+        rc = lib.crpq_eval(g.handle, arr, n_atoms, ctypes.byref(v), int(flags), ws.data_ptr(), ws.numel(),
+                           ctypes.byref(r), _stream(stream))
+        if rc == RPQ_ENOMEM and r.workspace_needed > ws.numel():
+            ws_bytes = int(r.workspace_needed)
+            continue
+        if rc == RPQ_EOVERFLOW and tuples and capacity is None and not allow_overflow:
+            cap = int(r.count)
+            continue
+        _check(rc, allow=(RPQ_EOVERFLOW,) if allow_overflow else ())
+        tt = None
+        if tuples:
+            tt = out_t[: int(r.written), : int(r.n_free)] if r.n_free else out_t[: int(r.written), :0]
+        return CrpqOutput(r, tt, n_atoms, rc)
+    raise RpqError(RPQ_ENOMEM, "crpq_eval: workspace kept growing (%d bytes last asked)" % ws_bytes)
+
+
+# ---------------------------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------------------------
+def _ticket_dict(t: Ticket) -> dict:
+    return dict(status=int(t.status), done=bool(t.done), count=int(t.count), hash=int(t.hash),
+                product_edges=int(t.product_edges), written=int(t.written), workspace_bytes=int(t.workspace_bytes),
+                arrival_ms=float(t.arrival_ms), start_ms=float(t.start_ms), end_ms=float(t.end_ms))
+
+
+class Server:
+    """A request loop over one resident graph (rpq_serve_* in include/rpq.h).
+
+    The device pool is one torch allocation of pool_bytes held by the server; requests run on
+    `workers` streams as the pool admits them.  Tensors a request names (sources, outputs,
+    domains) are kept alive until its ticket is collected with wait() or a done poll()."""
+
+    def __init__(self, g: Graph, pool_bytes: int, workers: int = 4):
+        torch = _torch()
+        self.g = g
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        o = ServerOpts()
+        o.workers = int(workers)
+        h = ctypes.c_void_p()
+        _check(load_library().rpq_serve_start(g.handle, ctypes.byref(o), self.pool.data_ptr(), self.pool.numel(),
+                                              ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def clock_ms(self) -> float:
+        x = ctypes.c_double()
+        _check(load_library().rpq_serve_clock_ms(self.handle, ctypes.byref(x)))
+        return float(x.value)
+
+    def _submit(self, req: Request, keep) -> int:
+        t = ctypes.c_uint64()
+        _check(load_library().rpq_serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def submit_rpq(self, nfa: Nfa, sources=None, flags: int = 0, pairs=None, per_source=None,
+                   arrival_ms: float = -1.0) -> int:
+        """Queue an RPQ (as rpq_eval).  pairs: a CUDA int64 tensor for keys; per_source: [n, 2]."""
+        torch = _torch()
+        req = Request()
+        req.kind = RPQ_REQ_RPQ
+        req.arrival_ms = float(arrival_ms)
+        req.nfa = nfa
+        keep = []
+        if sources is None:
+            flags |= RPQ_ALL_SOURCES
+            req.n_sources = rpq_graph_info_get(self.g)["n_vertices"]
+        else:
+            st = _dev_u32(sources, torch)
+            keep.append(st)
+            req.sources = st.data_ptr() if st.numel() else None
+            req.n_sources = st.numel()
+        if pairs is not None:
+            flags |= RPQ_PAIRS
+            req.pairs = pairs.data_ptr()
+            req.capacity = pairs.numel()
+            keep.append(pairs)
+        if per_source is not None:
+            flags |= RPQ_PER_SOURCE
+            req.per_source = per_source.data_ptr()
+            keep.append(per_source)
+        req.flags = flags
+        return self._submit(req, keep)
+
+    def submit_crpq(self, atoms, n_vars: int, binding=None, vertex_label=None, domain=None, neq=(),
+                    tuples=None, flags: int = 0, arrival_ms: float = -1.0) -> int:
+        """Queue a CRPQ (as crpq_eval).  tuples: a CUDA int32 tensor [capacity, n_free] or None."""
+        torch = _torch()
+        arr, v, keep = _crpq_marshal(self.g, atoms, n_vars, binding, vertex_label, domain, neq, torch)
+        req = Request()
+        req.kind = RPQ_REQ_CRPQ
+        req.flags = int(flags)
+        req.arrival_ms = float(arrival_ms)
+        req.atoms = arr
+        req.n_atoms = len(atoms)
+        req.vars = v
+        if tuples is not None:
+            req.tuples = tuples.data_ptr()
+            req.tuple_capacity = tuples.shape[0]
+            keep.append(tuples)
+        return self._submit(req, keep)
+
+    def poll(self, ticket: int) -> dict:
+        t = Ticket()
+        _check(load_library().rpq_serve_poll(self.handle, int(ticket), ctypes.byref(t)))
+        if t.done:
+            self._keep.pop(int(ticket), None)
+        return _ticket_dict(t)
+
+    def wait(self, ticket: int) -> dict:
+        t = Ticket()
+        _check(load_library().rpq_serve_wait(self.handle, int(ticket), ctypes.byref(t)))
+        self._keep.pop(int(ticket), None)
+        return _ticket_dict(t)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load_library().rpq_serve_stats(self.handle, ctypes.byref(st)))
+        return {n: int(getattr(st, n)) for n, _ in ServerStats._fields_}
+
+    def stop(self) -> None:
+        if self.handle is not None and self.handle.value:
+            _check(load_library().rpq_serve_stop(self.handle))
+        self.handle = None
+        self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

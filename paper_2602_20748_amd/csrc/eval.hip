@@ -92,6 +92,7 @@ struct Args {
     Desc* desc0;
     Desc* desc1;
     unsigned long long* counters;
+    const uint64_t* target;   // optional [V / 64] bitmap: only result vertices with their bit set count
     uint32_t V, L, Q, H;
     uint64_t list_cap, desc_cap;
 };
@@ -461,7 +462,8 @@ __global__ __launch_bounds__(kBlock) void k_extract(Args a, const uint32_t* __re
         if (WRITE && valid) cursor = srcbase[si] + partial[si * nchunks + chunk];
         for (uint32_t v0 = vbeg; v0 < vend; v0 += 64) {
             const uint32_t vv = v0 + lane;
-            const uint64_t word = vv < vend ? a.ans[((uint64_t)slot * V + vv) * K + k] : 0;
+            uint64_t word = vv < vend ? a.ans[((uint64_t)slot * V + vv) * K + k] : 0;
+            if (a.target && word && !((a.target[vv >> 6] >> (vv & 63)) & 1)) word = 0;
             uint64_t any = __ballot(word != 0);
             while (any) {
                 const int jj = __ffsll((long long)any) - 1;
@@ -717,6 +719,7 @@ Args make_args(const rpq_graph* g, uint32_t flags, const Layout& x, char* ws) {
     a.desc0 = reinterpret_cast<Desc*>(ws + x.off_desc[0]);
     a.desc1 = reinterpret_cast<Desc*>(ws + x.off_desc[1]);
     a.counters = reinterpret_cast<unsigned long long*>(ws + x.off_counters);
+    a.target = nullptr;
     a.V = x.V;
     a.L = x.L;
     a.Q = x.Q;
@@ -880,7 +883,7 @@ int prepare(rpq_graph_t g, const rpq_nfa* nfa_in, uint64_t n_sources, uint32_t f
         rpq::set_error("graph is NULL");
         return RPQ_EINVAL;
     }
-    if (flags & ~(RPQ_PAIRS | RPQ_PER_SOURCE | RPQ_ALL_SOURCES | RPQ_REVERSE)) {
+    if (flags & ~(RPQ_PAIRS | RPQ_PER_SOURCE | RPQ_ALL_SOURCES | RPQ_REVERSE | RPQ_SPARSE)) {
         rpq::set_error("unknown flags 0x%x", flags);
         return RPQ_EINVAL;
     }
@@ -907,6 +910,7 @@ int rpq_eval_workspace_size(rpq_graph_t g, const rpq_nfa* nfa, uint64_t n_source
         return RPQ_EINVAL;
     }
     if (g && (flags & RPQ_ALL_SOURCES) && n_sources == 0) n_sources = g->V;
+    if (flags & RPQ_SPARSE) return rpq::sparse_workspace_size(g, nfa, n_sources, flags, bytes);
     rpq_nfa eff;
     DevNfa dn;
     Layout lay;
@@ -919,6 +923,16 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
              const rpq_eval_opts* opts, void* workspace, uint64_t workspace_bytes, rpq_result* res,
              hipStream_t stream) {
     rpq::clear_error();
+    return rpq::eval_impl(g, nfa, sources, n_sources, flags, opts, nullptr, workspace, workspace_bytes, res, stream);
+}
+
+}  // extern "C"
+
+namespace rpq {
+
+int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
+              const rpq_eval_opts* opts, const uint64_t* target, void* workspace, uint64_t workspace_bytes,
+              rpq_result* res, hipStream_t stream) {
     if (!res) {
         rpq::set_error("result is NULL");
         return RPQ_EINVAL;
@@ -945,6 +959,14 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
         rpq::set_error("RPQ_PER_SOURCE with a NULL per_source buffer");
         return RPQ_EINVAL;
     }
+    res->workspace_needed = 0;
+    if (flags & RPQ_SPARSE) {
+        if (target) {
+            rpq::set_error("internal: a result filter is not supported with RPQ_SPARSE");
+            return RPQ_EINVAL;
+        }
+        return sparse_eval(g, nfa, sources, n_sources, flags, workspace, workspace_bytes, res, stream);
+    }
     rpq_nfa eff;
     DevNfa dn;
     Layout x;
@@ -952,6 +974,7 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
     if (!workspace || workspace_bytes < x.total) {
         rpq::set_error("workspace of %llu bytes is smaller than the %llu bytes needed",
                        (unsigned long long)workspace_bytes, (unsigned long long)x.total);
+        res->workspace_needed = x.total;
         return RPQ_ENOMEM;
     }
     if (reinterpret_cast<uintptr_t>(workspace) & 255) {
@@ -964,7 +987,12 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
 
     char* ws = reinterpret_cast<char*>(workspace);
     Args a = make_args(g, flags, x, ws);
-    uint64_t* stage = g->h_stage;
+    a.target = target;
+    uint64_t* stage = rpq::host_stage();
+    if (!stage) {
+        rpq::set_error("pinned host staging memory is unavailable");
+        return RPQ_EDEVICE;
+    }
     RPQ_HIP(hipMemcpyAsync(ws + x.off_nfa, &dn, sizeof dn, hipMemcpyHostToDevice, stream));
     RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(a.counters), C_NCOUNTERS, 0, stream));
     RPQ_TRY(rpq::fill_u64(a.next, (uint64_t)x.G * x.Q * x.V * x.K, 0, stream));
@@ -1072,6 +1100,10 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
     }
     return RPQ_OK;
 }
+
+}  // namespace rpq
+
+extern "C" {
 
 int rpq_profile_enable(int on) {
     Profiler& pr = profiler();

@@ -77,6 +77,23 @@ uint64_t radix_temp_bytes(uint64_t n);
 int radix_sort_u64(uint64_t* keys, uint64_t* alt, uint64_t n, int lo_bits, int hi_bits,
                    void* temp, hipStream_t s, uint64_t** sorted);
 
+// rpq_eval with an optional result-vertex filter (device bitmap of V bits, or null): the
+// traversal is unchanged and only result pairs whose non-source vertex has its bit set are
+// counted, hashed and written.
+int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
+              const rpq_eval_opts* opts, const uint64_t* target, void* workspace, uint64_t workspace_bytes,
+              rpq_result* res, hipStream_t stream);
+
+// 4 KB of pinned host memory private to the calling thread (small device-to-host reads of
+// counters), so that calls on one graph from several threads do not share a staging buffer.
+// Allocated on a thread's first use and kept until the process ends; null if pinning fails.
+uint64_t* host_stage();
+
+// The per-source hash-set search (RPQ_SPARSE) behind rpq_eval, and its starting workspace.
+int sparse_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
+                void* workspace, uint64_t workspace_bytes, rpq_result* res, hipStream_t stream);
+int sparse_workspace_size(rpq_graph_t g, const rpq_nfa* nfa, uint64_t n_sources, uint32_t flags, uint64_t* bytes);
+
 inline int bits_for(uint64_t max_value) {   // bits needed to represent values <= max_value
     int b = 0;
     while (b < 64 && (max_value >> b) != 0) ++b;

@@ -259,3 +259,16 @@ int radix_sort_u64(uint64_t* keys, uint64_t* alt, uint64_t n, int lo_bits, int h
 }
 
 }  // namespace rpq
+
+namespace rpq {
+
+uint64_t* host_stage() {
+    thread_local uint64_t* stage = nullptr;
+    if (!stage) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, 4096) == hipSuccess) stage = static_cast<uint64_t*>(p);
+    }
+    return stage;
+}
+
+}  // namespace rpq

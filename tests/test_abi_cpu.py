@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     text = open(os.path.join(ROOT, "include", "rpq.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rpq_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:rpq|crpq)_[a-z_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -43,6 +43,44 @@ def test_library_exports_every_declared_symbol(lib):
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(rpq.Nfa) == 16 + 4 * 32 * 64
     assert ctypes.sizeof(rpq.EvalOpts) == 16
+
+
+# ctypes mirror -> C struct of include/rpq.h
+STRUCTS = [("Nfa", "rpq_nfa"), ("GraphInfo", "rpq_graph_info"), ("EvalOpts", "rpq_eval_opts"),
+           ("_Result", "rpq_result"), ("Profile", "rpq_profile"), ("BatchOpts", "rpq_batch_opts"),
+           ("BatchInfo", "rpq_batch_info"), ("CrpqAtom", "crpq_atom"), ("CrpqVars", "crpq_vars"),
+           ("CrpqResult", "crpq_result"), ("ServerOpts", "rpq_server_opts"), ("Request", "rpq_request"),
+           ("Ticket", "rpq_ticket"), ("ServerStats", "rpq_server_stats")]
+
+
+def test_ctypes_layouts_match_the_c_header(tmp_path):
+    """Compile a probe against include/rpq.h with the host C compiler and compare every
+    struct size and field offset with the Python binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc") or shutil.which("cc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rpq.h"', "int main(void) {"]
+    for py, c in STRUCTS:
+        cls = getattr(rpq, py)
+        lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (c, c))
+        for f in cls._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (c, f[0], c, f[0]))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([gcc, "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                        "-I", "/opt/rocm/include", str(src), "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for py, c in STRUCTS:
+        cls = getattr(rpq, py)
+        assert int(got[c]) == ctypes.sizeof(cls), c
+        for f in cls._fields_:
+            assert int(got["%s.%s" % (c, f[0])]) == getattr(cls, f[0]).offset, (c, f[0])
 
 
 def nfa_as_oracle_shape(nfa):

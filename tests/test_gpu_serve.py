@@ -1,0 +1,158 @@
+"""GPU tests of the serving loop (rpq_serve_*): every request's result in a mixed stream equals
+its result alone, requests overlap on the device, and memory pressure only changes the schedule."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rpq():
+    import torch
+    import paper_2602_20748_amd as m
+    assert torch.cuda.is_available()
+    m.load_library()
+    return m
+
+
+@pytest.fixture(scope="module")
+def rmat18(rpq):
+    el = synth.workload_graph("rmat18_l8")
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, flags=rpq.RPQ_BUILD_IN_CSR,
+                             names=el.names)
+    yield el, g
+    g.close()
+
+
+def request_mix(rng, el, n):
+    """Single-source RPQs (sparse search), 512-source slice RPQs (bit-parallel) and 2-3 atom CRPQs
+    anchored at a random source (chain, fork, triangle)."""
+    mix = []
+    for i in range(n):
+        kind = i % 5
+        rx = synth.random_regex(rng, el.names[:6], max_leaves=6)
+        if kind in (0, 1):
+            mix.append(("rpq_sparse", rx, np.array([int(rng.integers(0, el.n_vertices))], np.uint32)))
+        elif kind in (2, 3):
+            lo = int(rng.integers(0, el.n_vertices - 512))
+            mix.append(("rpq_dense", rx, np.arange(lo, lo + 512, dtype=np.uint32)))
+        else:
+            s = int(rng.integers(0, el.n_vertices))
+            r1, r2, r3 = (synth.random_regex(rng, el.names[4:8], max_leaves=3) for _ in range(3))
+            shape = i % 3
+            if shape == 0:      # chain s -r1-> y -r2-> z
+                mix.append(("crpq", [(0, r1, 1), (1, r2, 2)], 3, [s, None, None]))
+            elif shape == 1:    # fork s -r1-> y and s -r2-> y
+                mix.append(("crpq", [(0, r1, 1), (0, r2, 1)], 2, [s, None]))
+            else:               # triangle s -r1-> y, y -r2-> z, s -r3-> z
+                mix.append(("crpq", [(0, r1, 1), (1, r2, 2), (0, r3, 2)], 3, [s, None, None]))
+    return mix
+
+
+def run_alone(rpq, g, el, item):
+    import torch
+    if item[0] == "crpq":
+        _, atoms, nv, binding = item
+        r = rpq.crpq_eval(g, atoms, nv, binding=binding)
+        return (r.count, r.hash, None)
+    kind, rx, src = item
+    nfa = rpq.rpq_nfa_compile(rx, el.names)
+    flags = rpq.RPQ_SPARSE if kind == "rpq_sparse" else 0
+    r = rpq.rpq_eval(g, nfa, src, flags=flags, pairs=True)
+    return (r.count, r.hash, r.product_edges, r.pairs.cpu().numpy().view(np.uint64).copy())
+
+
+def submit(rpq, srv, el, item):
+    import torch
+    if item[0] == "crpq":
+        _, atoms, nv, binding = item
+        return srv.submit_crpq(atoms, nv, binding=binding), None
+    kind, rx, src = item
+    nfa = rpq.rpq_nfa_compile(rx, el.names)
+    flags = rpq.RPQ_SPARSE if kind == "rpq_sparse" else 0
+    buf = torch.empty(1 << 20, dtype=torch.int64, device="cuda")
+    return srv.submit_rpq(nfa, src, flags=flags, pairs=buf), buf
+
+
+def check_mix(rpq, g, el, mix, alone, pool_bytes, workers):
+    srv = rpq.Server(g, pool_bytes, workers=workers)
+    sub = [submit(rpq, srv, el, it) for it in mix]
+    done = [srv.wait(t) for t, _ in sub]
+    st = srv.stats()
+    srv.stop()
+    for it, (t, buf), d, a in zip(mix, sub, done, alone):
+        # a pair buffer smaller than the result is filled and the request reports the overflow
+        assert d["status"] == 0 or (d["status"] == rpq.RPQ_EOVERFLOW and it[0] != "crpq"
+                                    and d["count"] > buf.numel()), (it, d)
+        if it[0] == "crpq":
+            assert (d["count"], d["hash"]) == a[:2], it
+        else:
+            assert (d["count"], d["hash"], d["product_edges"]) == a[:3], it
+            n = min(d["count"], buf.numel())
+            assert np.array_equal(buf[:n].cpu().numpy().view(np.uint64), a[3][:n]), it
+    assert st["completed"] == len(mix) and st["failed"] == 0 and st["pool_in_use"] == 0
+    return done, st
+
+
+def max_overlap(done):
+    ev = sorted([(d["start_ms"], 1) for d in done] + [(d["end_ms"], -1) for d in done])
+    cur = best = 0
+    for _, x in ev:
+        cur += x
+        best = max(best, cur)
+    return best
+
+
+def test_results_in_the_mix_equal_alone(rpq, rmat18):
+    el, g = rmat18
+    rng = np.random.default_rng(505)
+    mix = request_mix(rng, el, 40)
+    alone = []
+    for i, it in enumerate(mix):
+        say("case: serve alone %d %s" % (i, it[:2]))
+        alone.append(run_alone(rpq, g, el, it))
+    say("case: serve mix, 4 workers, 24 GiB pool")
+    done, st = check_mix(rpq, g, el, mix, alone, 24 << 30, 4)
+    assert max_overlap(done) >= 2          # admitted requests ran at the same time
+    assert all(d["end_ms"] >= d["start_ms"] >= d["arrival_ms"] for d in done)
+
+
+def test_memory_pressure_changes_only_the_schedule(rpq, rmat18):
+    el, g = rmat18
+    rng = np.random.default_rng(506)
+    mix = [it for it in request_mix(rng, el, 25) if it[0] != "crpq"]
+    alone = [run_alone(rpq, g, el, it) for it in mix]
+    # the smallest pool that admits the largest single request: requests run one or two at a time,
+    # and dense ones are split into fewer units in flight
+    nfas = [rpq.rpq_nfa_compile(it[1], el.names) for it in mix]
+    need = max(rpq.rpq_eval_workspace_size(g, n, 512, 0, dict(batch_width=64, concurrency=1))
+               for n, it in zip(nfas, mix) if it[0] == "rpq_dense")
+    say("case: serve under pressure, pool %d bytes" % need)
+    done, st = check_mix(rpq, g, el, mix, alone, int(need * 1.5), 4)
+    assert st["pool_peak"] <= int(need * 1.5)
+
+
+def test_submit_rejects(rpq, rmat18):
+    el, g = rmat18
+    srv = rpq.Server(g, 1 << 20, workers=2)
+    nfa = rpq.rpq_nfa_compile("a*", el.names)
+    with pytest.raises(rpq.RpqError) as e:   # a dense all-pairs query can never fit 1 MiB
+        srv.submit_rpq(nfa, None)
+    assert e.value.code == rpq.RPQ_ENOMEM
+    bad = rpq.Nfa()
+    with pytest.raises(rpq.RpqError) as e:
+        srv.submit_rpq(bad, np.array([1], np.uint32))
+    assert e.value.code == rpq.RPQ_EINVAL
+    t = srv.submit_rpq(nfa, np.array([5, 3], np.uint32), flags=rpq.RPQ_SPARSE)   # unsorted: fails when run
+    d = srv.wait(t)
+    assert d["done"] and d["status"] == rpq.RPQ_EINVAL
+    srv.stop()
