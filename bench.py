@@ -58,7 +58,101 @@ def parse_args():
                     help="time only one form (profiling runs only)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving measurement instead of the throughput step: Poisson streams of mixed "
+                         "requests at each --qps rate (prints one JSON line of its own)")
+    ap.add_argument("--qps", default="50,200,1000", help="serving: comma-separated arrival rates")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving: measured seconds per rate")
+    ap.add_argument("--serve-warmup-seconds", type=float, default=2.0, help="serving: warm-up seconds per rate")
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-pool-gib", type=float, default=96.0)
+    ap.add_argument("--serve-max-requests", type=int, default=4000,
+                    help="serving: cap on requests per rate (keeps the FIFO comparison bounded)")
     return ap.parse_args()
+
+
+def serve_main(args):
+    """Serving: requests of synth.serve_requests arrive as a Poisson stream at each rate; latency is
+    scheduled arrival -> completion.  The same requests then run one at a time (plain FIFO, no
+    overlap) for the edges/s comparison and to check that every result is the one it has alone."""
+    import numpy as np
+    import torch
+
+    import paper_2602_20748_amd as rpq
+    import synth
+
+    spec = synth.WORKLOADS[args.workload]
+    el = synth.workload_graph(args.workload)
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, flags=rpq.RPQ_BUILD_IN_CSR,
+                             names=el.names)
+    ring = [torch.empty(1 << 20, dtype=torch.int64, device="cuda") for _ in range(64)]
+    points = []
+    identical = True
+    for qps in [float(x) for x in args.qps.split(",") if x]:
+        n = int(min(args.serve_max_requests, qps * (args.serve_seconds + args.serve_warmup_seconds)))
+        reqs = synth.serve_requests(n, el.n_vertices, el.names, seed=spec["seed"] + 1000)
+        arrive = synth.poisson_arrivals(qps, n, seed=spec["seed"] + 3000) * 1e3
+        nfa = [rpq.rpq_nfa_compile(r[1], el.names) if r[0] != "crpq" else None for r in reqs]
+        print("bench: serving %d requests at %.0f QPS" % (n, qps), file=sys.stderr, flush=True)
+        srv = rpq.Server(g, int(args.serve_pool_gib * (1 << 30)), workers=args.serve_workers)
+        t0 = srv.clock_ms() + 50.0
+        tickets = []
+        for i, r in enumerate(reqs):
+            if i >= len(ring):   # a ring of pair buffers: the request that used this one must be done
+                srv.wait(tickets[i - len(ring)])
+            due = t0 + arrive[i]
+            while srv.clock_ms() < due:
+                time.sleep(max(0.0, min(0.002, (due - srv.clock_ms()) / 1e3)))
+            if r[0] == "crpq":
+                tickets.append(srv.submit_crpq(r[1], r[2], binding=r[3], arrival_ms=due))
+            else:
+                fl = rpq.RPQ_SPARSE if r[0] == "rpq_single" else 0
+                tickets.append(srv.submit_rpq(nfa[i], r[2], flags=fl, pairs=ring[i % len(ring)], arrival_ms=due))
+        done = [srv.wait(t) for t in tickets]
+        srv.stop()
+        warm = t0 + args.serve_warmup_seconds * 1e3
+        meas = [d for d in done if d["arrival_ms"] >= warm] or done
+        lat = np.array([d["end_ms"] - d["arrival_ms"] for d in meas])
+        span = (max(d["end_ms"] for d in meas) - min(d["arrival_ms"] for d in meas)) / 1e3
+        ep = sum(d["product_edges"] for d in meas)
+        # the same requests alone, one at a time
+        print("bench: FIFO replay of %d requests" % len(reqs), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        fifo_s = 0.0
+        fifo_ep = 0
+        for i, (r, d) in enumerate(zip(reqs, done)):
+            t = time.perf_counter()
+            if r[0] == "crpq":
+                a = rpq.crpq_eval(g, r[1], r[2], binding=r[3])
+                ok = (a.count, a.hash) == (d["count"], d["hash"])
+                e = 0
+            else:
+                fl = rpq.RPQ_SPARSE if r[0] == "rpq_single" else 0
+                a = rpq.rpq_eval(g, nfa[i], r[2], flags=fl, pairs=ring[0], allow_overflow=True)
+                ok = (a.count, a.hash, a.product_edges) == (d["count"], d["hash"], d["product_edges"])
+                e = a.product_edges
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            identical &= ok and d["status"] in (0, rpq.RPQ_EOVERFLOW)
+            if d["arrival_ms"] >= warm or len(meas) == len(done):
+                fifo_s += dt
+                fifo_ep += e
+        kinds = {k: sum(1 for r in reqs if r[0] == k) for k in ("rpq_single", "rpq_slice", "crpq")}
+        points.append(dict(qps=qps, requests=n, measured=len(meas), mix=kinds,
+                           p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
+                           completed_per_s=round(len(meas) / span, 2), served_edges_per_s=ep / span,
+                           fifo_edges_per_s=fifo_ep / fifo_s if fifo_s > 0 else None,
+                           served_over_fifo=((ep / span) / (fifo_ep / fifo_s)) if fifo_s > 0 and fifo_ep else None))
+        print("bench: %s" % json.dumps(points[-1]), file=sys.stderr, flush=True)
+    line = {
+        "metric": "p99 latency (serving)", "value": points[-1]["p99_ms"] if points else None, "unit": "ms",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "u64", "data": "synthetic (seeded R-MAT; Poisson arrivals)",
+        "config": {"workload": "%s serving: %d workers, %.0f GiB pool" % (args.workload, args.serve_workers,
+                                                                          args.serve_pool_gib)},
+        "results_identical_to_alone": identical, "points": points,
+    }
+    print(json.dumps(line), flush=True)
+    g.close()
 
 
 def copy_calibration(mib):
@@ -134,6 +228,10 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
+        return
+    if args.serve:
+        rpq.load_library()
+        serve_main(args)
         return
     rpq.load_library()
     spec = synth.WORKLOADS[args.workload]

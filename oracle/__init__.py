@@ -280,6 +280,7 @@ def crpq(g: OracleGraph, atoms: Sequence[Tuple[int, str, int]], n_vars: int, bin
     free = [i for i in range(n_vars) if not (binding is not None and binding[i] is not None and binding[i] >= 0)]
     out = set()
     assign: List[Optional[int]] = [None] * n_vars
+    dom_sets = [set(d.tolist()) for d in doms]   # built once; candidates() intersects with them
 
     def candidates(i):
         cand = None
@@ -294,9 +295,9 @@ def crpq(g: OracleGraph, atoms: Sequence[Tuple[int, str, int]], n_vars: int, bin
                 continue
             cand = set(c) if cand is None else (cand & c)
         if cand is None:
-            cand = set(doms[i].tolist())
+            cand = dom_sets[i]
         else:
-            cand &= set(doms[i].tolist())
+            cand = cand & dom_sets[i]
         return sorted(cand)
 
     def ok_atoms(i):

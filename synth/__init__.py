@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "EdgeList", "label_names", "zipf_probs", "uniform_graph", "rmat_graph",
     "social_graph", "random_regex_ast", "render_regex", "random_regex",
-    "regex_leaf_count", "sample_sources", "poisson_arrivals", "WORKLOADS",
+    "regex_leaf_count", "sample_sources", "poisson_arrivals", "serve_requests", "WORKLOADS",
     "workload_graph", "rmat_query_mix",
 ]
 
@@ -308,6 +308,38 @@ def poisson_arrivals(rate_qps: float, n: int, seed: int) -> np.ndarray:
     """Arrival times (seconds from 0) of a Poisson process with the given rate."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate_qps, size=n))
+
+
+def serve_requests(n: int, n_vertices: int, names: Sequence[str], seed: int,
+                   slice_width: int = 4096) -> List[tuple]:
+    """The serving stream's requests: about 40% single-source RPQs ("rpq_single", regex, sources),
+    40% RPQs over a slice of slice_width consecutive sources ("rpq_slice", regex, sources) and 20%
+    CRPQs of 2-3 atoms anchored at a random source s ("crpq", atoms, n_vars, binding): the chain
+    s -r1-> y -r2-> z, the fork s -r1-> y, s -r2-> y, or the triangle s -r1-> y, y -r2-> z,
+    s -r3-> z.  Regexes come from random_regex (1-11 label occurrences, depth <= 4)."""
+    rng = np.random.default_rng(seed)
+    n_slices = max(1, n_vertices // slice_width)
+    out = []
+    for _ in range(n):
+        u = rng.random()
+        if u < 0.4:
+            out.append(("rpq_single", random_regex(rng, names),
+                        np.array([int(rng.integers(0, n_vertices))], dtype=np.uint32)))
+        elif u < 0.8:
+            lo = int(rng.integers(0, n_slices)) * slice_width
+            out.append(("rpq_slice", random_regex(rng, names),
+                        np.arange(lo, min(n_vertices, lo + slice_width), dtype=np.uint32)))
+        else:
+            s = int(rng.integers(0, n_vertices))
+            shape = int(rng.integers(0, 3))
+            r = [random_regex(rng, names, max_leaves=4) for _ in range(3)]
+            if shape == 0:
+                out.append(("crpq", [(0, r[0], 1), (1, r[1], 2)], 3, [s, None, None]))
+            elif shape == 1:
+                out.append(("crpq", [(0, r[0], 1), (0, r[1], 1)], 2, [s, None]))
+            else:
+                out.append(("crpq", [(0, r[0], 1), (1, r[1], 2), (0, r[2], 2)], 3, [s, None, None]))
+    return out
 
 
 # ----------------------------------------------------------------------------------------------

@@ -238,27 +238,69 @@ def test_social_graph_small(rpq):
 
 
 @pytest.fixture(scope="module")
-def social_full():
+def social_full(rpq):
     say("generating the social graph (1M persons, 10M messages, 16,384 tags)")
-    return synth.social_graph()
+    el = synth.social_graph()
+    say("building the device graph")
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, vertex_label=el.vertex_label,
+                             flags=rpq.RPQ_BUILD_IN_CSR, names=el.names)
+    say("knows components")
+    comp, deg = knows_components(el, 1_000_000)
+    yield el, g, comp, deg
+    g.close()
 
 
-def test_social_graph_full_size(rpq, social_full):
-    el = social_full
+def test_social_full_size_query1(rpq, social_full):
+    """Query 1 at full size: full count against the closed form, every tuple's checksum, and the
+    oracle's join on a 1% sample of the tagged messages."""
+    el, g, comp, deg = social_full
     P, M = 1_000_000, 10_000_000
+    tag1 = P + M
+    atoms = [(0, "hasTag", 1), (0, "hasCreator", 2), (0, "replyOf*", 3)]
+    q1 = dict(binding=[None, tag1, None, None], vertex_label=[MESSAGE, TAG, PERSON, MESSAGE])
+    say("case: social full Q1, count and checksum")
+    c1 = rpq.crpq_eval(g, atoms, 4, **q1)
+    say("  count %d, strategies %s, atom pairs %s" % (c1.count, c1.atom_strategy, c1.atom_pairs))
+    tagged = np.unique(el.src[(el.label == 3) & (el.dst == tag1)].astype(np.int64))
+    depth = reply_depth(el, P, M)
+    assert c1.count == int((depth[tagged - P] + 1).sum())
+    say("case: social full Q1, tuples")
+    r1 = rpq.crpq_eval(g, atoms, 4, tuples=True, capacity=c1.count, **q1)
+    t1 = r1.tuples.cpu().numpy().view(np.uint32).astype(np.int64)
+    assert (r1.count, r1.hash) == (c1.count, c1.hash) and t1.shape == (c1.count, 3)
+    assert np.array_equal(np.unique(t1[:, 0]), tagged)
+    assert np.array_equal(np.lexsort((t1[:, 2], t1[:, 1], t1[:, 0])), np.arange(len(t1)))
+    assert r1.hash == chain_hash(t1)
     rng = np.random.default_rng(4003)
-    sample128 = np.sort(rng.choice(P, size=128, replace=False)).astype(np.uint32)
-    tagged = np.unique(el.src[(el.label == 3) & (el.dst == P + M)])
-    m_sample = np.sort(rng.choice(tagged, size=max(1, len(tagged) // 100), replace=False)).astype(np.uint32)
+    ms = np.sort(rng.choice(tagged, size=max(1, len(tagged) // 100), replace=False)).astype(np.uint32)
     say("building the oracle graph")
     og = oracle.OracleGraph.from_edgelist(el)
-    g, cyc, comp, deg = social_queries(rpq, el, P, M, sample128, check_oracle_m=dict(og=og, m_sample=m_sample))
-    # 1,024-person sample, count and checksum only: the count is the sum of cubes of the
-    # sample's per-component sizes (persons with a knows edge)
+    say("oracle join on %d sampled messages" % len(ms))
+    want = oracle.crpq(og, atoms, 4, binding=q1["binding"], var_label=q1["vertex_label"],
+                       var_domain=[ms, None, None, None], threads=16)
+    keep = np.isin(t1[:, 0], ms)
+    assert [tuple(int(v) for v in row) for row in t1[keep]] == want
+
+
+def test_social_full_size_cycle(rpq, social_full):
+    """The 3-cycle of knows.knows* at full size: exact tuples over 128 persons, the sum of cubes
+    for the count over 1,024."""
+    el, g, comp, deg = social_full
+    P = 1_000_000
+    rng = np.random.default_rng(4004)
+    cyc = [(0, "knows.knows*", 1), (1, "knows.knows*", 2), (2, "knows.knows*", 0)]
+    s128 = np.sort(rng.choice(P, size=128, replace=False)).astype(np.uint32)
+    say("case: social full 3-cycle, 128 persons, tuples")
+    r = rpq.crpq_eval(g, cyc, 3, domain=[s128] * 3, vertex_label=[PERSON] * 3, tuples=True)
+    want = cycle_tuples(s128, comp, deg)
+    assert r.count == len(want)
+    assert np.array_equal(r.tuples.cpu().numpy().view(np.uint32).astype(np.int64), want)
+    assert r.hash == chain_hash(want)
     s1024 = np.sort(rng.choice(P, size=1024, replace=False)).astype(np.uint32)
-    say("case: social Q2 sample=1024 count only")
+    say("case: social full 3-cycle, 1,024 persons, count only")
     r = rpq.crpq_eval(g, cyc, 3, domain=[s1024] * 3, vertex_label=[PERSON] * 3)
     live = s1024[deg[s1024] > 0]
     _, sizes = np.unique(comp[live], return_counts=True)
+    say("  count %d (sum of cubes %d), join rows %d" % (r.count, int((sizes.astype(np.int64) ** 3).sum()),
+                                                        r.join_rows))
     assert r.count == int((sizes.astype(np.int64) ** 3).sum())
-    g.close()
