@@ -39,10 +39,12 @@ constexpr uint32_t kChunkV = 4096;          // vertices per extraction chunk (64
 
 constexpr uint32_t S_IDLE = 0, S_RUN = 1, S_RETIRE = 2;
 
+// A slice [beg, beg + len) of the item space of frontier entry `entry` (entries with more than
+// H items are cut into such slices of at most H items; lighter ones are expanded straight from
+// the frontier list).
 struct Desc {
-    uint32_t entry, beg;
-    uint32_t state;  // one successor q' in delta(q, label) of the slot's automaton
-    uint32_t lens;   // len | slot << 16
+    uint32_t entry, len;
+    uint64_t beg;
 };
 
 struct BNfa {
@@ -158,84 +160,136 @@ __device__ __forceinline__ uint64_t gwave(const BArgs& a) {
 __device__ __forceinline__ uint64_t gwaves(const BArgs& a) { return (uint64_t)a.n_blocks * kWaves; }
 
 // ------------------------------------------------------------------------------------------------
-// expand: the level expansion of the plain form (item phase: lane per edge item; word phase:
-// groups of K lanes per item, lane k on word k of the rows), with per-slot automata
+// expand: the level expansion of the plain form with per-slot automata.  Segments (entry, first
+// item, item count): light entries of the frontier list whole, then descriptors of heavy ones.
+// Item phase: lane per item (segment by a wave prefix); word phase: groups of K lanes per item,
+// lane k on word k of the rows.
 // ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void entry_of(const BArgs& a, uint32_t row, uint32_t* slot, uint32_t* q, uint32_t* v,
+                                         const BNfa** nfa) {
+    const uint32_t stride = (uint32_t)a.slot_stride;
+    *slot = row / stride;
+    const uint32_t lrow = row - *slot * stride;
+    *q = lrow / a.V;
+    *v = lrow - *q * a.V;
+    *nfa = a.nfas + ld32(&a.slots[*slot].query);
+}
+
 template <int K>
-__device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t& t_descs, uint64_t& t_wread,
-                             uint64_t& t_wupd) {
+__device__ __forceinline__ void expand_segments(const BArgs& a, const uint64_t* rows, bool have, uint32_t ent,
+                                                uint32_t slot, uint32_t q, uint32_t v, uint64_t m,
+                                                const uint32_t* delta, uint64_t beg, uint32_t len,
+                                                uint64_t& t_items, uint64_t& t_wread, uint64_t& t_wupd) {
     constexpr int GS = 64 / K;
-    const uint64_t n_desc = min((uint64_t)ld(&a.ctl->desc_cnt[p]), a.desc_cap);
-    if (n_desc == 0) return;
     const int lane = threadIdx.x & 63;
     const int grp = lane / K, k = lane % K;
     const uint64_t gmask = (K == 64) ? ~0ull : (((1ull << K) - 1) << (grp * K));
-    const Desc* desc = p ? a.desc1 : a.desc0;
-    const uint64_t* rows = p ? a.rows1 : a.rows0;
     const uint32_t V = a.V;
     const uint32_t stride = (uint32_t)a.slot_stride;
-    const uint64_t n_batches = (n_desc + 63) / 64;
-    for (uint64_t b = gwave(a); b < n_batches; b += gwaves(a)) {
+    if (!have) len = 0;
+    const uint32_t incl = rpqd::wave_incl_scan_u32(len);
+    const uint32_t excl = incl - len;
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (lane == 0) t_items += total;
+    const uint64_t dptr = reinterpret_cast<uint64_t>(delta);
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t item = base + lane;
+        int c = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int cand = c + step;
+            const uint32_t e = __shfl(excl, cand, 64);
+            if (e <= item) c = cand;
+        }
+        const uint32_t c_ent = __shfl(ent, c, 64);
+        const uint32_t c_slot = __shfl(slot, c, 64);
+        const uint32_t c_q = __shfl(q, c, 64);
+        const uint32_t c_v = __shfl(v, c, 64);
+        const uint64_t c_m = __shfl(m, c, 64);
+        const uint64_t c_beg = __shfl(beg, c, 64);
+        const uint64_t c_delta = __shfl(dptr, c, 64);
+        const uint32_t c_ex = __shfl(excl, c, 64);
+        uint32_t my_row = 0;
+        if (item < total) {
+            uint32_t w = 0, q2 = 0;
+            rpqd::decode_item(a.row_ptr, a.dst, a.L, reinterpret_cast<const uint32_t*>(c_delta), c_v, c_q, c_m,
+                              c_beg + (item - c_ex), &w, &q2);
+            my_row = c_slot * stride + q2 * V + w;
+        }
+        const uint32_t n_here = min(64u, total - base);
+        for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
+            uint32_t r[kUnroll];
+            uint64_t f[kUnroll], vw[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t idx = j + u * GS + grp;
+                r[u] = __shfl(my_row, idx & 63, 64);
+                const uint32_t e = __shfl(c_ent, idx & 63, 64);
+                f[u] = idx < n_here ? xld(rows + (uint64_t)e * K + k) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) vw[u] = f[u] ? xld(a.vis + (uint64_t)r[u] * K + k) : ~0ull;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t nb = f[u] & ~vw[u];
+                t_wread += f[u] != 0;
+                t_wupd += nb != 0;
+                if (nb) or_relaxed(a.next + (uint64_t)r[u] * K + k, nb);
+                const uint64_t hit = __ballot(nb != 0) & gmask;
+                if (k == 0 && hit) or_relaxed(&a.touch[r[u] >> 6], 1ull << (r[u] & 63));
+            }
+        }
+    }
+}
+
+template <int K>
+__device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t& t_descs, uint64_t& t_wread,
+                             uint64_t& t_wupd) {
+    const uint64_t n_list = min((uint64_t)ld(&a.ctl->list_cnt[p]), a.list_cap);
+    const uint64_t n_desc = min((uint64_t)ld(&a.ctl->desc_cnt[p]), a.desc_cap);
+    if (n_list == 0) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t* ids = p ? a.ids1 : a.ids0;
+    const uint64_t* rows = p ? a.rows1 : a.rows0;
+    const Desc* desc = p ? a.desc1 : a.desc0;
+    const uint32_t H = a.H;
+    const uint64_t n_lb = (n_list + 63) / 64;
+    for (uint64_t b = gwave(a); b < n_lb; b += gwaves(a)) {
+        const uint64_t e = b * 64 + lane;
+        bool have = false;
+        uint32_t slot = 0, q = 0, v = 0, len = 0;
+        uint64_t m = 0;
+        const BNfa* nfa = a.nfas;
+        if (e < n_list) {
+            entry_of(a, xld(ids + e), &slot, &q, &v, &nfa);
+            m = a.lmask[v] & nfa->qlab[q];
+            const uint64_t work = m ? rpqd::entry_work(a.row_ptr, a.L, nfa->delta, v, q, m) : 0;
+            have = work != 0 && work <= H;
+            len = have ? (uint32_t)work : 0;
+        }
+        const uint64_t hb = __ballot(have);   // every lane takes part
+        if (lane == 0) t_descs += __popcll(hb);
+        expand_segments<K>(a, rows, have, (uint32_t)e, slot, q, v, m, nfa->delta, 0, len, t_items, t_wread, t_wupd);
+    }
+    const uint64_t n_db = (n_desc + 63) / 64;
+    for (uint64_t b = gwave(a); b < n_db; b += gwaves(a)) {
         const uint64_t di = b * 64 + lane;
-        uint32_t len = 0, ent = 0, beg = 0, st = 0, lens = 0;
+        bool have = false;
+        uint32_t ent = 0, slot = 0, q = 0, v = 0, len = 0;
+        uint64_t m = 0, beg = 0;
+        const BNfa* nfa = a.nfas;
         if (di < n_desc) {
             const uint32_t* dw = reinterpret_cast<const uint32_t*>(desc + di);
             ent = xld(dw + 0);
-            beg = xld(dw + 1);
-            st = xld(dw + 2);
-            lens = xld(dw + 3);
-            len = lens & 0xFFFF;
+            len = xld(dw + 1);
+            beg = (uint64_t)xld(dw + 2) | ((uint64_t)xld(dw + 3) << 32);
+            entry_of(a, xld(ids + ent), &slot, &q, &v, &nfa);
+            m = a.lmask[v] & nfa->qlab[q];
+            have = true;
         }
-        const uint32_t incl = rpqd::wave_incl_scan_u32(len);
-        const uint32_t excl = incl - len;
-        const uint32_t total = __shfl(incl, 63, 64);
-        if (lane == 0) {
-            t_items += total;
-            t_descs += min<uint64_t>(64, n_desc - b * 64);
-        }
-        for (uint32_t base = 0; base < total; base += 64) {
-            const uint32_t item = base + lane;
-            int c = 0;
-#pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                const int cand = c + step;
-                const uint32_t e = __shfl(excl, cand, 64);
-                if (e <= item) c = cand;
-            }
-            const uint32_t c_ent = __shfl(ent, c, 64);
-            const uint32_t c_beg = __shfl(beg, c, 64);
-            const uint32_t c_st = __shfl(st, c, 64);
-            const uint32_t c_lens = __shfl(lens, c, 64);
-            const uint32_t c_ex = __shfl(excl, c, 64);
-            uint32_t my_row = 0;
-            if (item < total) {
-                const uint32_t w = a.dst[c_beg + (item - c_ex)];
-                my_row = (c_lens >> 16) * stride + c_st * V + w;
-            }
-            const uint32_t n_here = min(64u, total - base);
-            for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
-                uint32_t r[kUnroll];
-                uint64_t f[kUnroll], vw[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t idx = j + u * GS + grp;
-                    r[u] = __shfl(my_row, idx & 63, 64);
-                    const uint32_t e = __shfl(c_ent, idx & 63, 64);
-                    f[u] = idx < n_here ? xld(rows + (uint64_t)e * K + k) : 0;
-                }
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) vw[u] = f[u] ? xld(a.vis + (uint64_t)r[u] * K + k) : ~0ull;
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const uint64_t nb = f[u] & ~vw[u];
-                    t_wread += f[u] != 0;
-                    t_wupd += nb != 0;
-                    if (nb) or_relaxed(a.next + (uint64_t)r[u] * K + k, nb);
-                    const uint64_t hit = __ballot(nb != 0) & gmask;
-                    if (k == 0 && hit) or_relaxed(&a.touch[r[u] >> 6], 1ull << (r[u] & 63));
-                }
-            }
-        }
+        const uint64_t hb = __ballot(have);   // every lane takes part
+        if (lane == 0) t_descs += __popcll(hb);
+        expand_segments<K>(a, rows, have, ent, slot, q, v, m, nfa->delta, beg, len, t_items, t_wread, t_wupd);
     }
 }
 
@@ -545,8 +599,8 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
     for (uint64_t e0 = gwave(a) * 64; e0 < n; e0 += gwaves(a) * 64) {
         const uint64_t e = e0 + lane;
         const bool active = e < n;
-        uint32_t row32 = 0, slot = 0, lrow = 0, q = 0, v = 0, qid = 0, ndesc = 0;
-        uint64_t m = 0, eprod = 0;
+        uint32_t row32 = 0, slot = 0, lrow = 0, q = 0, v = 0, qid = 0;
+        uint64_t eprod = 0, work = 0;
         const BNfa* nfa = a.nfas;
         uint32_t my_ans = 0xFFFFFFFFu;   // Ans row of a final-state entry, else none
         if (active) {
@@ -604,19 +658,9 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
                 const unsigned long long li = atomicAdd(&a.slots[slot].log_n, 1ull);
                 if (li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = lrow;
             }
-            m = a.lmask[v] & nfa->qlab[q];
-            uint64_t wsum = 0;
-            uint64_t mm = m;
-            while (mm) {
-                const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
-                mm &= mm - 1;
-                const uint32_t r = v * L + l;
-                const uint32_t d = a.row_ptr[r + 1] - a.row_ptr[r];
-                const uint32_t ns = (uint32_t)__popc(nfa->delta[q * L + l]);
-                wsum += (uint64_t)d * ns;
-                ndesc += ns * ((d + H - 1) / H);
-            }
-            eprod = (uint64_t)pc * wsum;
+            const uint64_t m = a.lmask[v] & nfa->qlab[q];
+            work = m ? rpqd::entry_work(a.row_ptr, L, nfa->delta, v, q, m) : 0;
+            eprod = (uint64_t)pc * work;
         }
         // product edges per query (one atomic per wave when the wave holds one query)
         const uint32_t q0 = __shfl(qid, __ffsll((long long)__ballot(active)) - 1, 64);
@@ -626,36 +670,37 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
         } else if (active && eprod) {
             atomicAdd(&a.qout[qid].eprod, (unsigned long long)eprod);
         }
-        const uint32_t incl = rpqd::wave_incl_scan_u32(ndesc);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        if (tot) {
+        // entries of more than H items are cut into descriptors, written by the whole wave
+        const uint64_t ndesc = work > H ? (work + H - 1) / H : 0;
+        const uint64_t dincl = rpqd::wave_incl_scan_u64(ndesc);
+        const uint64_t dexcl = dincl - ndesc;
+        const uint64_t dtot = __shfl(dincl, 63, 64);
+        if (dtot) {
             unsigned long long dbase = 0;
-            if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)tot);
+            if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)dtot);
             dbase = __shfl(dbase, 0, 64);
-            if (active && ndesc) {
-                uint64_t pos = dbase + incl - ndesc;
-                uint64_t mm = m;
-                while (mm) {
-                    const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
-                    mm &= mm - 1;
-                    const uint32_t r = v * L + l;
-                    const uint32_t b = a.row_ptr[r], d = a.row_ptr[r + 1] - b;
-                    uint32_t succ = nfa->delta[q * L + l];
-                    while (succ) {
-                        const uint32_t q2 = __ffs(succ) - 1;
-                        succ &= succ - 1;
-                        for (uint32_t o = 0; o < d; o += H, ++pos) {
-                            if (pos < a.desc_cap) {
-                                Desc dd;
-                                dd.entry = (uint32_t)e;
-                                dd.beg = b + o;
-                                dd.state = q2;
-                                dd.lens = min(H, d - o) | (slot << 16);
-                                dout[pos] = dd;
-                            } else {
-                                atomicOr(&a.ctl->err, 2ull);
-                            }
-                        }
+            for (uint64_t i0 = 0; i0 < dtot; i0 += 64) {
+                const uint64_t i = i0 + lane;
+                int c = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const int cand = c + step;
+                    const uint64_t ex = __shfl(dexcl, cand, 64);
+                    if (ex <= i) c = cand;
+                }
+                const uint64_t c_work = __shfl(work, c, 64);
+                const uint64_t c_ex = __shfl(dexcl, c, 64);
+                if (i < dtot) {
+                    const uint64_t pos = dbase + i;
+                    if (pos < a.desc_cap) {
+                        const uint64_t kk = i - c_ex;
+                        Desc dd;
+                        dd.entry = (uint32_t)(e0 + c);
+                        dd.beg = kk * H;
+                        dd.len = (uint32_t)min<uint64_t>(H, c_work - kk * H);
+                        dout[pos] = dd;
+                    } else {
+                        atomicOr(&a.ctl->err, 2ull);
                     }
                 }
             }
@@ -837,7 +882,7 @@ int plan(rpq_batch* b) {
         return RPQ_EINVAL;
     }
     x.K = x.W / 64;
-    x.H = b->opts.chunk_edges ? b->opts.chunk_edges : 16;
+    x.H = b->opts.chunk_edges ? b->opts.chunk_edges : 64;
     if (x.H > 65535) {
         rpq::set_error("chunk_edges must be <= 65535");
         return RPQ_EINVAL;
@@ -863,8 +908,18 @@ int plan(rpq_batch* b) {
     x.n_units = (uint32_t)b->units.size();
     x.slot_stride = ((uint64_t)x.Qmax * g->V + 63) / 64 * 64;
     x.summ_words = (g->V + 63) / 64;
+    // descriptors of one level and slot: entries with more than H items take ceil(work / H) <= 2 work / H
+    // each, and all entries of one state hold at most E * max |delta(q, l)| items
+    uint32_t max_succ = 1;
+    for (auto& q : b->queries)
+        for (uint32_t i = 0; i < RPQ_MAX_STATES * RPQ_MAX_LABELS; ++i)
+            max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(q.nfa.delta[i]));
+    const uint64_t desc_per_slot = 2 * (uint64_t)x.Qmax * max_succ * g->E / x.H + 2;
+    // per slot: Vis + Next, touch bits, Ans, summary, first-visit log, and its share of the two
+    // frontier lists (row id + K-word row per entry) and of the two descriptor buffers
     const uint64_t per_slot = x.slot_stride * x.K * 8 * 2 + x.slot_stride / 8 + (uint64_t)g->V * x.K * 8 +
-                              x.summ_words * 8 + x.slot_stride * 4;
+                              x.summ_words * 8 + x.slot_stride * 4 + 2 * x.slot_stride * (4 + x.K * 8) +
+                              2 * desc_per_slot * sizeof(Desc);
     uint64_t G = b->opts.slots;
     if (!G) {
         const uint64_t budget = 64ull << 30;
@@ -880,16 +935,7 @@ int plan(rpq_batch* b) {
     x.nchunks = (uint32_t)((g->V + kChunkV - 1) / kChunkV);
     // frontier list: worst case every row of every slot in one level
     x.list_cap = (uint64_t)x.G * x.slot_stride;
-    // descriptors: one per (frontier row, label, successor state, chunk of H edges)
-    uint32_t max_succ = 1;
-    for (auto& q : b->queries)
-        for (uint32_t i = 0; i < RPQ_MAX_STATES * RPQ_MAX_LABELS; ++i)
-            max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(q.nfa.delta[i]));
-    uint64_t dper = 0;
-    for (uint32_t q = 0; q < x.Qmax; ++q) dper += g->out.nonempty_rows + (g->E + x.H - 1) / x.H + 1;
-    x.desc_cap = (uint64_t)x.G * max_succ *
-                 std::min<uint64_t>(dper, (uint64_t)x.Qmax * g->V * std::min<uint32_t>(g->L, 64) +
-                                              (uint64_t)x.Qmax * ((g->E + x.H - 1) / x.H + 1));
+    x.desc_cap = (uint64_t)x.G * desc_per_slot;
     x.stage_keys = 0;
     for (auto& q : b->queries)
         if (q.pairs) x.stage_keys += q.capacity;
@@ -1357,7 +1403,7 @@ int rpq_batch_autotune(rpq_batch_t b, const rpq_batch_opts* candidates, uint32_t
         cands.assign(candidates, candidates + n_candidates);
     } else {
         const uint32_t widths[] = {64, 256, 512, 1024, 2048};
-        const uint32_t chunks[] = {16, 32, 64};
+        const uint32_t chunks[] = {32, 64, 256};
         for (uint32_t w : widths)
             for (uint32_t h : chunks) {
                 rpq_batch_opts o{};

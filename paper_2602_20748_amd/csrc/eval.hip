@@ -16,16 +16,18 @@
 //   Ans [V][K]     bits of result pairs (s_i, v)
 // G units advance together; their rows are tagged by a slot id.
 //
-// One level = two kernels:
-//   expand    reads work descriptors (entry, label, edge range), and for each
-//             edge v -l-> w and successor q' in delta(q, l) ORs the entry's
-//             frontier bits that are new for (q', w) into Next; the first
-//             writer of a row appends (slot, q', w) to the next list.
-//   finalize  for each new entry moves Next into a compact frontier row,
-//             ORs it into Vis (and into Ans when q' is final), counts the
-//             product edges it will examine, and cuts its out-edges per label
-//             into work descriptors of at most H edges (edge-balanced work
-//             for the next expand, whatever the degree skew).
+// One level = three kernels:
+//   expand    every frontier entry (q, v) owns a flattened item space: its edges over the
+//             labels q can follow, each counted once per successor state.  For each item
+//             (edge v -l-> w, successor q') it ORs the entry's frontier bits that are new for
+//             (q', w) into Next; the first writer of a row sets its touch bit.  Entries with
+//             at most H items are expanded straight from the frontier list; larger ones
+//             arrive as work descriptors of at most H items (edge-balanced work whatever the
+//             degree skew, with descriptor memory bounded by 2 * items / H).
+//   compact   the touched rows become the next frontier list (ballot/popcount prefix).
+//   finalize  for each new entry moves Next into a compact frontier row, ORs it into Vis
+//             (and into Ans when q' is final), counts the product edges it will examine,
+//             and cuts entries of more than H items into descriptors.
 // The fixpoint is reached when a level appends nothing; the host checks the
 // list counter every few levels (no hop bound).
 //
@@ -63,11 +65,11 @@ constexpr int C_NCOUNTERS = 16;
 
 constexpr uint64_t ERR_LIST = 1, ERR_DESC = 2, ERR_SOURCES = 4;
 
-// A unit of expansion work: edges [beg, beg + len) of one CSR row (v, label), to be followed
-// from frontier entry `entry` into successor state `state` (one q' of delta(q, label); a row
-// with several successors gets one descriptor per successor).  lens = len | slot << 16.
+// A slice [beg, beg + len) of the item space of frontier entry `entry` (an entry with more than
+// H items is cut into such slices of at most H items).
 struct Desc {
-    uint32_t entry, beg, state, lens;
+    uint32_t entry, len;
+    uint64_t beg;
 };
 
 struct DevNfa {
@@ -117,12 +119,13 @@ __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint6
 }
 
 // ------------------------------------------------------------------------------------------------
-// level expansion.  Work is mapped twice per batch of 64 edge items:
-//   item phase  lane i takes item i: finds its descriptor (prefix of the wave's descriptor
-//               lengths), loads the edge target w (consecutive lanes, consecutive CSR slots)
-//               and forms the target row id (slot, q', w);
+// level expansion.  Work comes as segments (entry, first item, item count): first every light
+// entry of the frontier list whole, then the descriptors of the heavy ones.  Per batch of
+// segments (one per lane) the work is mapped twice per 64 items:
+//   item phase  lane i takes item i: finds its segment (prefix of the wave's segment lengths),
+//               decodes the edge target w and successor q', and forms the target row id;
 //   word phase  the wave splits into 64/K groups of K lanes; group g takes items g, g + 64/K, ...
-//               and lane k of the group handles word k of the row, so the frontier row, the
+//               and lane k of the group handles word k of the rows, so the frontier row, the
 //               visited row and the Next row of an item are each read or updated as one
 //               contiguous K-word access instead of K scattered ones.
 // kUnroll items per group are loaded before any of them is updated (memory-level parallelism).
@@ -130,93 +133,138 @@ __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint6
 constexpr int kUnroll = 4;
 
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
-    constexpr int GS = 64 / K;   // item groups per wave
-    const uint64_t n_desc = min((uint64_t)a.counters[C_DESC + p], a.desc_cap);
-    if (n_desc == 0) return;
+__device__ __forceinline__ void expand_segments(const Args& a, const uint32_t* s_delta, const uint64_t* rows,
+                                                bool have, uint32_t ent, uint32_t slot, uint32_t q, uint32_t v,
+                                                uint64_t m, uint64_t beg, uint32_t len, uint64_t& t_items,
+                                                uint64_t& t_wread, uint64_t& t_wupd) {
+    constexpr int GS = 64 / K;
     const int lane = threadIdx.x & 63;
     const int grp = lane / K, k = lane % K;
     const uint64_t gmask = (K == 64) ? ~0ull : (((1ull << K) - 1) << (grp * K));
+    const uint32_t Q = a.Q, V = a.V;
+    if (!have) len = 0;
+    const uint32_t incl = rpqd::wave_incl_scan_u32(len);
+    const uint32_t excl = incl - len;
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (lane == 0) t_items += total;
+    for (uint32_t base = 0; base < total; base += 64) {
+        // item phase
+        const uint32_t item = base + lane;
+        int c = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const int cand = c + step;
+            const uint32_t e = __shfl(excl, cand, 64);
+            if (e <= item) c = cand;
+        }
+        const uint32_t c_ent = __shfl(ent, c, 64);
+        const uint32_t c_slot = __shfl(slot, c, 64);
+        const uint32_t c_q = __shfl(q, c, 64);
+        const uint32_t c_v = __shfl(v, c, 64);
+        const uint64_t c_m = __shfl(m, c, 64);
+        const uint64_t c_beg = __shfl(beg, c, 64);
+        const uint32_t c_ex = __shfl(excl, c, 64);
+        uint32_t my_row = 0;
+        if (item < total) {
+            uint32_t w = 0, q2 = 0;
+            rpqd::decode_item(a.row_ptr, a.dst, a.L, s_delta, c_v, c_q, c_m, c_beg + (item - c_ex), &w, &q2);
+            my_row = (c_slot * Q + q2) * V + w;
+        }
+        const uint32_t n_here = min(64u, total - base);
+        // word phase
+        for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
+            uint32_t r[kUnroll];
+            uint64_t f[kUnroll], vw[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t idx = j + u * GS + grp;
+                r[u] = __shfl(my_row, idx & 63, 64);
+                const uint32_t e = __shfl(c_ent, idx & 63, 64);
+                f[u] = idx < n_here ? rows[(uint64_t)e * K + k] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) vw[u] = f[u] ? a.vis[(uint64_t)r[u] * K + k] : ~0ull;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t nb = f[u] & ~vw[u];
+                t_wread += f[u] != 0;
+                t_wupd += nb != 0;
+                if (nb) or_relaxed(&a.next[(uint64_t)r[u] * K + k], nb);
+                const uint64_t hit = __ballot(nb != 0) & gmask;
+                if (k == 0 && hit) or_relaxed(&a.touch[r[u] >> 6], 1ull << (r[u] & 63));
+            }
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
+    __shared__ uint32_t s_delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];
+    __shared__ uint64_t s_qlab[RPQ_MAX_STATES];
+    load_nfa(a, s_delta, s_qlab, nullptr);
+    const uint64_t n_list = min((uint64_t)a.counters[C_LIST + p], a.list_cap);
+    const uint64_t n_desc = min((uint64_t)a.counters[C_DESC + p], a.desc_cap);
+    if (n_list == 0) return;
+    const int lane = threadIdx.x & 63;
     const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
     const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    const uint64_t n_batches = (n_desc + 63) / 64;
-    const Desc* desc = desc_of(a, p);
     const uint64_t* rows = rows_of(a, p);
-    const uint32_t Q = a.Q, V = a.V;
-    uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0;
-
-    for (uint64_t b = wave; b < n_batches; b += n_waves) {
+    const uint32_t* ids = ids_of(a, p);
+    const uint32_t QV = a.Q * a.V, V = a.V, H = a.H;
+    uint64_t t_items = 0, t_segs = 0, t_wread = 0, t_wupd = 0;
+    // light entries, straight from the frontier list
+    const uint64_t n_lb = (n_list + 63) / 64;
+    for (uint64_t b = wave; b < n_lb; b += n_waves) {
+        const uint64_t e = b * 64 + lane;
+        bool have = false;
+        uint32_t slot = 0, q = 0, v = 0, len = 0;
+        uint64_t m = 0;
+        if (e < n_list) {
+            const uint32_t row = ids[e];
+            slot = row / QV;
+            const uint32_t rem = row - slot * QV;
+            q = rem / V;
+            v = rem - q * V;
+            m = a.lmask[v] & s_qlab[q];
+            const uint64_t work = m ? rpqd::entry_work(a.row_ptr, a.L, s_delta, v, q, m) : 0;
+            have = work != 0 && work <= H;
+            len = have ? (uint32_t)work : 0;
+        }
+        t_segs += __popcll(__ballot(have)) * (lane == 0);
+        expand_segments<K>(a, s_delta, rows, have, (uint32_t)e, slot, q, v, m, 0, len, t_items, t_wread, t_wupd);
+    }
+    // heavy entries, as descriptors
+    const Desc* desc = desc_of(a, p);
+    const uint64_t n_db = (n_desc + 63) / 64;
+    for (uint64_t b = wave; b < n_db; b += n_waves) {
         const uint64_t di = b * 64 + lane;
-        uint32_t len = 0, ent = 0, beg = 0, st = 0, lens = 0;
+        bool have = false;
+        uint32_t ent = 0, slot = 0, q = 0, v = 0, len = 0;
+        uint64_t m = 0, beg = 0;
         if (di < n_desc) {
             const Desc d = desc[di];
             ent = d.entry;
             beg = d.beg;
-            st = d.state;
-            lens = d.lens;
-            len = lens & 0xFFFF;
+            len = d.len;
+            const uint32_t row = ids[ent];
+            slot = row / QV;
+            const uint32_t rem = row - slot * QV;
+            q = rem / V;
+            v = rem - q * V;
+            m = a.lmask[v] & s_qlab[q];
+            have = true;
         }
-        const uint32_t incl = rpqd::wave_incl_scan_u32(len);
-        const uint32_t excl = incl - len;
-        const uint32_t total = __shfl(incl, 63, 64);
-        if (lane == 0) {
-            t_items += total;
-            t_descs += (uint64_t)min<uint64_t>(64, n_desc - b * 64);
-        }
-        for (uint32_t base = 0; base < total; base += 64) {
-            // item phase
-            const uint32_t item = base + lane;
-            int c = 0;
-#pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                const int cand = c + step;
-                const uint32_t e = __shfl(excl, cand, 64);
-                if (e <= item) c = cand;
-            }
-            const uint32_t c_ent = __shfl(ent, c, 64);
-            const uint32_t c_beg = __shfl(beg, c, 64);
-            const uint32_t c_st = __shfl(st, c, 64);
-            const uint32_t c_lens = __shfl(lens, c, 64);
-            const uint32_t c_ex = __shfl(excl, c, 64);
-            uint32_t my_row = 0;
-            if (item < total) {
-                const uint32_t w = a.dst[c_beg + (item - c_ex)];
-                my_row = ((c_lens >> 16) * Q + c_st) * V + w;
-            }
-            const uint32_t n_here = min(64u, total - base);
-            // word phase
-            for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
-                uint32_t r[kUnroll];
-                uint64_t f[kUnroll], vw[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t idx = j + u * GS + grp;
-                    r[u] = __shfl(my_row, idx & 63, 64);
-                    const uint32_t e = __shfl(c_ent, idx & 63, 64);
-                    f[u] = idx < n_here ? rows[(uint64_t)e * K + k] : 0;
-                }
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) vw[u] = f[u] ? a.vis[(uint64_t)r[u] * K + k] : ~0ull;
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const uint64_t nb = f[u] & ~vw[u];
-                    t_wread += f[u] != 0;
-                    t_wupd += nb != 0;
-                    if (nb) or_relaxed(&a.next[(uint64_t)r[u] * K + k], nb);
-                    const uint64_t hit = __ballot(nb != 0) & gmask;
-                    if (k == 0 && hit) or_relaxed(&a.touch[r[u] >> 6], 1ull << (r[u] & 63));
-                }
-            }
-        }
+        t_segs += __popcll(__ballot(have)) * (lane == 0);
+        expand_segments<K>(a, s_delta, rows, have, ent, slot, q, v, m, beg, len, t_items, t_wread, t_wupd);
     }
     t_items = rpqd::wave_sum_u64(t_items);
-    t_descs = rpqd::wave_sum_u64(t_descs);
+    t_segs = rpqd::wave_sum_u64(t_segs);
     t_wread = rpqd::wave_sum_u64(t_wread);
     t_wupd = rpqd::wave_sum_u64(t_wupd);
     if (lane == 0 && t_items) {
         atomicAdd(&a.counters[C_ITEMS], (unsigned long long)t_items);
-        atomicAdd(&a.counters[C_DESCS], (unsigned long long)t_descs);
-        atomicAdd(&a.counters[C_ROWW], (unsigned long long)(t_descs * K));
+        atomicAdd(&a.counters[C_DESCS], (unsigned long long)t_segs);
+        atomicAdd(&a.counters[C_ROWW], (unsigned long long)(t_segs * K));
         atomicAdd(&a.counters[C_WREAD], (unsigned long long)t_wread);
         atomicAdd(&a.counters[C_WUPD], (unsigned long long)t_wupd);
     }
@@ -289,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
     uint64_t* rows = rows_of(a, np);
     Desc* dout = desc_of(a, np);
     unsigned long long* dcnt = &a.counters[C_DESC + np];
-    const uint32_t H = a.H, L = a.L, V = a.V;
+    const uint32_t H = a.H, V = a.V;
     const uint32_t QV = a.Q * a.V;
     const uint32_t fin = s_final;
     uint64_t eprod = 0;
@@ -339,54 +387,44 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
                 if (rel < (uint32_t)GS) my_pc = got;
             }
         }
-        // row phase
-        uint32_t ndesc = 0;
-        uint64_t m = 0;
+        // row phase: product edges; entries of more than H items are cut into descriptors
+        uint64_t work = 0;
         if (active) {
-            m = a.lmask[v] & s_qlab[q];
-            uint64_t wsum = 0;
-            uint64_t mm = m;
-            while (mm) {
-                const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
-                mm &= mm - 1;
-                const uint32_t r = v * L + l;
-                const uint32_t d = a.row_ptr[r + 1] - a.row_ptr[r];
-                const uint32_t ns = (uint32_t)__popc(s_delta[q * L + l]);
-                wsum += (uint64_t)d * ns;
-                ndesc += ns * ((d + H - 1) / H);
-            }
-            eprod += (uint64_t)my_pc * wsum;
+            const uint64_t m = a.lmask[v] & s_qlab[q];
+            work = m ? rpqd::entry_work(a.row_ptr, a.L, s_delta, v, q, m) : 0;
+            eprod += (uint64_t)my_pc * work;
         }
-        const uint32_t incl = rpqd::wave_incl_scan_u32(ndesc);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        if (tot) {
+        const uint64_t ndesc = work > H ? (work + H - 1) / H : 0;
+        const uint64_t dincl = rpqd::wave_incl_scan_u64(ndesc);
+        const uint64_t dexcl = dincl - ndesc;
+        const uint64_t dtot = __shfl(dincl, 63, 64);
+        if (dtot) {
             unsigned long long dbase = 0;
-            if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)tot);
+            if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)dtot);
             dbase = __shfl(dbase, 0, 64);
-            if (active && ndesc) {
-                uint64_t pos = dbase + incl - ndesc;
-                uint64_t mm = m;
-                while (mm) {
-                    const uint32_t l = (uint32_t)(__ffsll((long long)mm) - 1);
-                    mm &= mm - 1;
-                    const uint32_t r = v * L + l;
-                    const uint32_t b = a.row_ptr[r], d = a.row_ptr[r + 1] - b;
-                    uint32_t succ = s_delta[q * L + l];
-                    while (succ) {
-                        const uint32_t q2 = __ffs(succ) - 1;
-                        succ &= succ - 1;
-                        for (uint32_t o = 0; o < d; o += H, ++pos) {
-                            if (pos < a.desc_cap) {
-                                Desc dd;
-                                dd.entry = (uint32_t)e;
-                                dd.beg = b + o;
-                                dd.state = q2;
-                                dd.lens = min(H, d - o) | (slot << 16);
-                                dout[pos] = dd;
-                            } else {
-                                atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_DESC);
-                            }
-                        }
+            // the wave writes its descriptors together: descriptor i goes to the lane owning it
+            for (uint64_t i0 = 0; i0 < dtot; i0 += 64) {
+                const uint64_t i = i0 + lane;
+                int c = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const int cand = c + step;
+                    const uint64_t ex = __shfl(dexcl, cand, 64);
+                    if (ex <= i) c = cand;
+                }
+                const uint64_t c_work = __shfl(work, c, 64);
+                const uint64_t c_ex = __shfl(dexcl, c, 64);
+                if (i < dtot) {
+                    const uint64_t pos = dbase + i;
+                    if (pos < a.desc_cap) {
+                        const uint64_t k = i - c_ex;
+                        Desc dd;
+                        dd.entry = (uint32_t)(e0 + c);
+                        dd.beg = k * H;
+                        dd.len = (uint32_t)min<uint64_t>(H, c_work - k * H);
+                        dout[pos] = dd;
+                    } else {
+                        atomicOr(&a.counters[C_ERR], (unsigned long long)ERR_DESC);
                     }
                 }
             }
@@ -607,15 +645,14 @@ void to_dev_nfa(const rpq_nfa* nfa, uint32_t L, DevNfa* d) {
         }
 }
 
-// Default shape: about 64K sources in flight, in units of up to 2048 sources, with
-// descriptors of at most 16 edges (measured on R-MAT scale 18, all-pairs: throughput
-// rises with the sources advanced per level up to ~64K; 2048-wide units beat 1024 and
-// 4096 at equal sources in flight; 16-edge descriptors beat 32 and 64), and per-call
-// workspace within 64 GB of the 288 GB device.
+// Default shape: about 64K sources in flight, in units of up to 2048 sources (measured on
+// R-MAT scale 18, all-pairs: throughput rises with the sources advanced per level up to ~64K;
+// 2048-wide units beat 1024 and 4096 at equal sources in flight), entries of more than 64
+// items cut into slices, and per-call workspace within 64 GB of the 288 GB device.
 constexpr uint64_t kTargetInFlight = 65536;
 constexpr uint64_t kWorkspaceBudget = 64ull << 30;
 constexpr uint32_t kMaxDefaultWidth = 2048;
-constexpr uint32_t kDefaultChunk = 16;
+constexpr uint32_t kDefaultChunk = 64;
 
 uint64_t unit_bytes(uint64_t QV, uint32_t W) {
     // Vis + Next + two frontier lists of rows + row ids
@@ -631,7 +668,6 @@ uint32_t default_width(uint64_t n_sources, uint64_t QV) {
 
 int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32_t flags,
                 const rpq_eval_opts* o, Layout* Lo) {
-    const rpq::Csr& csr = (flags & RPQ_REVERSE) ? g->in : g->out;
     Layout x;
     std::memset(&x, 0, sizeof x);
     x.Q = dn.Q;
@@ -652,10 +688,20 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     const uint64_t units = std::max<uint64_t>(1, (n_sources + x.W - 1) / x.W);
     const uint64_t QV = (uint64_t)x.Q * x.V;
     const uint64_t bitmap_bytes = QV * x.K * 8;
+    // descriptors of one level and unit: entries with work > H take ceil(work / H) <= 2 work / H
+    // each, and the work of all entries of state q is at most E * max |delta(q, l)|
+    uint64_t items = 0;
+    for (uint32_t q = 0; q < x.Q; ++q) {
+        uint32_t max_succ = 0;
+        for (uint32_t l = 0; l < x.L; ++l) max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(dn.delta[q * x.L + l]));
+        items += (uint64_t)max_succ * g->E;   // the in-CSR holds the same distinct edges
+    }
+    const uint64_t desc_per_unit = 2 * items / x.H + 2;
     uint64_t G = (o && o->concurrency) ? o->concurrency : 0;
     if (!G) {
         G = std::max<uint64_t>(1, kTargetInFlight / x.W);
-        G = std::min<uint64_t>(G, std::max<uint64_t>(1, kWorkspaceBudget / unit_bytes(QV, x.W)));
+        const uint64_t per_unit = unit_bytes(QV, x.W) + 2 * desc_per_unit * sizeof(Desc);
+        G = std::min<uint64_t>(G, std::max<uint64_t>(1, kWorkspaceBudget / per_unit));
     }
     G = std::min<uint64_t>(G, units);
     if (G > 65535) G = 65535;   // slot ids travel in 16 bits of a descriptor
@@ -665,14 +711,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
         rpq::set_error("concurrency * states * vertices must stay below 2^32; lower concurrency");
         return RPQ_EUNSUPPORTED;
     }
-    uint64_t dper = 0;
-    for (uint32_t q = 0; q < x.Q; ++q) {
-        const uint64_t rows_q = std::min<uint64_t>((uint64_t)x.V * popc64(dn.qlab[q]), csr.nonempty_rows);
-        uint32_t max_succ = 0;
-        for (uint32_t l = 0; l < x.L; ++l) max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(dn.delta[q * x.L + l]));
-        dper += (uint64_t)max_succ * (rows_q + (g->E + x.H - 1) / x.H + 1);
-    }
-    x.desc_cap = G * dper;
+    x.desc_cap = G * desc_per_unit;
     x.chunk_v = 4096;
     x.nchunks = (uint32_t)((x.V + x.chunk_v - 1) / x.chunk_v);
     uint64_t off = 0;

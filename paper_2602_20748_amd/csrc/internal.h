@@ -155,6 +155,48 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
+// Item space of a frontier entry (state q, vertex v) with label set m (labels of v that q can
+// follow): labels in ascending order, within a label its edges in CSR order, within an edge the
+// successor states of delta(q, l) in ascending order.  delta is the compact [q * L + l] table.
+__device__ __forceinline__ uint64_t entry_work(const uint32_t* __restrict__ row_ptr, uint32_t L,
+                                               const uint32_t* delta, uint32_t v, uint32_t q, uint64_t m) {
+    uint64_t work = 0;
+    while (m) {
+        const uint32_t l = (uint32_t)(__ffsll((long long)m) - 1);
+        m &= m - 1;
+        const uint64_t r = (uint64_t)v * L + l;
+        work += (uint64_t)(row_ptr[r + 1] - row_ptr[r]) * (uint32_t)__popc(delta[q * L + l]);
+    }
+    return work;
+}
+
+// Item o of that space: edge target *w and successor state *q2.
+__device__ __forceinline__ void decode_item(const uint32_t* __restrict__ row_ptr, const uint32_t* __restrict__ dst,
+                                            uint32_t L, const uint32_t* delta, uint32_t v, uint32_t q, uint64_t m,
+                                            uint64_t o, uint32_t* w, uint32_t* q2) {
+    while (m) {
+        const uint32_t l = (uint32_t)(__ffsll((long long)m) - 1);
+        m &= m - 1;
+        const uint64_t r = (uint64_t)v * L + l;
+        const uint32_t b = row_ptr[r], d = row_ptr[r + 1] - b;
+        uint32_t succ = delta[q * L + l];
+        const uint32_t ns = (uint32_t)__popc(succ);
+        const uint64_t cnt = (uint64_t)d * ns;
+        if (o < cnt) {
+            uint64_t e = o, k = 0;
+            if (ns != 1) {
+                e = o / ns;
+                k = o - e * ns;
+            }
+            *w = dst[b + e];
+            for (uint64_t i = 0; i < k; ++i) succ &= succ - 1;
+            *q2 = (uint32_t)(__ffs(succ) - 1);
+            return;
+        }
+        o -= cnt;
+    }
+}
+
 }  // namespace rpqd
 
 // ---- grid-wide barrier for persistent kernels (device) ----

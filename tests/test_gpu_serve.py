@@ -152,7 +152,12 @@ def test_submit_rejects(rpq, rmat18):
     with pytest.raises(rpq.RpqError) as e:
         srv.submit_rpq(bad, np.array([1], np.uint32))
     assert e.value.code == rpq.RPQ_EINVAL
+    srv.stop()
+    srv = rpq.Server(g, 64 << 20, workers=2)
     t = srv.submit_rpq(nfa, np.array([5, 3], np.uint32), flags=rpq.RPQ_SPARSE)   # unsorted: fails when run
     d = srv.wait(t)
     assert d["done"] and d["status"] == rpq.RPQ_EINVAL
+    ok = srv.wait(srv.submit_rpq(nfa, np.array([3, 5], np.uint32), flags=rpq.RPQ_SPARSE))
+    assert ok["status"] == 0 and ok["count"] > 0   # the server keeps serving after a failed request
+    assert srv.stats()["failed"] == 1
     srv.stop()
