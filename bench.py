@@ -61,7 +61,8 @@ def parse_args():
     ap.add_argument("--serve", action="store_true",
                     help="serving measurement instead of the throughput step: Poisson streams of mixed "
                          "requests at each --qps rate (prints one JSON line of its own)")
-    ap.add_argument("--qps", default="50,200,1000", help="serving: comma-separated arrival rates")
+    ap.add_argument("--qps", default="burst,10,50,100",
+                    help="serving: comma-separated arrival rates; 'burst' = every request at once (capacity)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving: measured seconds per rate")
     ap.add_argument("--serve-warmup-seconds", type=float, default=2.0, help="serving: warm-up seconds per rate")
     ap.add_argument("--serve-workers", type=int, default=4)
@@ -88,12 +89,15 @@ def serve_main(args):
     ring = [torch.empty(1 << 20, dtype=torch.int64, device="cuda") for _ in range(64)]
     points = []
     identical = True
-    for qps in [float(x) for x in args.qps.split(",") if x]:
-        n = int(min(args.serve_max_requests, qps * (args.serve_seconds + args.serve_warmup_seconds)))
+    for tok in [x for x in args.qps.split(",") if x]:
+        burst = tok == "burst"   # every request arrives at once: the server's capacity
+        qps = float("inf") if burst else float(tok)
+        n = int(args.serve_max_requests if burst else
+                min(args.serve_max_requests, qps * (args.serve_seconds + args.serve_warmup_seconds)))
         reqs = synth.serve_requests(n, el.n_vertices, el.names, seed=spec["seed"] + 1000)
-        arrive = synth.poisson_arrivals(qps, n, seed=spec["seed"] + 3000) * 1e3
+        arrive = np.zeros(n) if burst else synth.poisson_arrivals(qps, n, seed=spec["seed"] + 3000) * 1e3
         nfa = [rpq.rpq_nfa_compile(r[1], el.names) if r[0] != "crpq" else None for r in reqs]
-        print("bench: serving %d requests at %.0f QPS" % (n, qps), file=sys.stderr, flush=True)
+        print("bench: serving %d requests at %s QPS" % (n, tok), file=sys.stderr, flush=True)
         srv = rpq.Server(g, int(args.serve_pool_gib * (1 << 30)), workers=args.serve_workers)
         t0 = srv.clock_ms() + 50.0
         tickets = []
@@ -108,9 +112,15 @@ def serve_main(args):
             else:
                 fl = rpq.RPQ_SPARSE if r[0] == "rpq_single" else 0
                 tickets.append(srv.submit_rpq(nfa[i], r[2], flags=fl, pairs=ring[i % len(ring)], arrival_ms=due))
-        done = [srv.wait(t) for t in tickets]
+            if (i + 1) % 100 == 0:
+                print("bench: submitted %d / %d" % (i + 1, n), file=sys.stderr, flush=True)
+        done = []
+        for t in tickets:
+            done.append(srv.wait(t))
+            if len(done) % 100 == 0:
+                print("bench: completed %d / %d" % (len(done), n), file=sys.stderr, flush=True)
         srv.stop()
-        warm = t0 + args.serve_warmup_seconds * 1e3
+        warm = t0 if burst else t0 + args.serve_warmup_seconds * 1e3
         meas = [d for d in done if d["arrival_ms"] >= warm] or done
         lat = np.array([d["end_ms"] - d["arrival_ms"] for d in meas])
         span = (max(d["end_ms"] for d in meas) - min(d["arrival_ms"] for d in meas)) / 1e3
@@ -120,7 +130,10 @@ def serve_main(args):
         torch.cuda.synchronize()
         fifo_s = 0.0
         fifo_ep = 0
+        fifo_times = []
         for i, (r, d) in enumerate(zip(reqs, done)):
+            if (i + 1) % 100 == 0:
+                print("bench: FIFO %d / %d" % (i + 1, n), file=sys.stderr, flush=True)
             t = time.perf_counter()
             if r[0] == "crpq":
                 a = rpq.crpq_eval(g, r[1], r[2], binding=r[3])
@@ -133,16 +146,25 @@ def serve_main(args):
                 e = a.product_edges
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
+            fifo_times.append(dt)
             identical &= ok and d["status"] in (0, rpq.RPQ_EOVERFLOW)
             if d["arrival_ms"] >= warm or len(meas) == len(done):
                 fifo_s += dt
                 fifo_ep += e
         kinds = {k: sum(1 for r in reqs if r[0] == k) for k in ("rpq_single", "rpq_slice", "crpq")}
-        points.append(dict(qps=qps, requests=n, measured=len(meas), mix=kinds,
+        service = {k: round(float(np.mean([d["end_ms"] - d["start_ms"] for r, d in zip(reqs, done) if r[0] == k]
+                                          or [0.0])), 3) for k in kinds}
+        fifo_kind = {k: round(1e3 * float(np.mean([t for r, t in zip(reqs, fifo_times) if r[0] == k] or [0.0])), 3)
+                     for k in kinds}
+        points.append(dict(qps="burst" if burst else qps, requests=n, measured=len(meas), mix=kinds, workers=args.serve_workers,
+                           service_ms_by_kind=service, fifo_ms_by_kind=fifo_kind,
                            p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
                            completed_per_s=round(len(meas) / span, 2), served_edges_per_s=ep / span,
                            fifo_edges_per_s=fifo_ep / fifo_s if fifo_s > 0 else None,
-                           served_over_fifo=((ep / span) / (fifo_ep / fifo_s)) if fifo_s > 0 and fifo_ep else None))
+                           # below capacity the served rate is the offered load; the ratio means
+                           # something only when every request is waiting at once
+                           served_over_fifo=((ep / span) / (fifo_ep / fifo_s))
+                           if burst and fifo_s > 0 and fifo_ep else None))
         print("bench: %s" % json.dumps(points[-1]), file=sys.stderr, flush=True)
     line = {
         "metric": "p99 latency (serving)", "value": points[-1]["p99_ms"] if points else None, "unit": "ms",

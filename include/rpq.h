@@ -187,7 +187,8 @@ typedef struct {
                                 workspace <= 64 GB) */
     uint32_t sync_every;     /* levels launched between host checks for the fixpoint (0 = 4) */
     uint32_t chunk_edges;    /* items (edge x successor state) per expansion work slice: entries
-                                with more items are cut into slices of this size (0 = 64) */
+                                with more items are cut into slices of this size (0 = 16, raised
+                                while the slice buffers would exceed a quarter of a unit's bitmaps) */
 } rpq_eval_opts;
 
 /*
@@ -263,7 +264,8 @@ typedef struct rpq_batch* rpq_batch_t;
 typedef struct {
     uint32_t batch_width;   /* sources per unit: 64 .. 4096, power of two (0 = 512) */
     uint32_t slots;         /* units advanced together (0 = sized for ~64K sources in flight, <= 64 GB) */
-    uint32_t chunk_edges;   /* items (edge x successor state) per work slice (0 = 64) */
+    uint32_t chunk_edges;   /* items (edge x successor state) per work slice (0 = 16, raised while the
+                               slice buffers would exceed a quarter of a slot's bitmaps) */
     uint32_t reserved;
 } rpq_batch_opts;
 
@@ -323,7 +325,7 @@ int rpq_batch_stats(rpq_batch_t b, rpq_batch_info* out);
 
 /*
  * Autotune the batch's unit width, slot count and descriptor size: each
- * candidate (default set: widths 64..2048 x chunk 32/64/256 items, slots sized
+ * candidate (default set: widths 64..2048 x chunk 16/64 items, slots sized
  * automatically) whose plan fits in workspace_bytes runs a bounded prefix of
  * the unit queue twice (capture, then replay), and the candidate with the most
  * sources per millisecond on the replay wins.  The batch is re-planned with the

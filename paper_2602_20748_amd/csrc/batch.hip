@@ -882,7 +882,7 @@ int plan(rpq_batch* b) {
         return RPQ_EINVAL;
     }
     x.K = x.W / 64;
-    x.H = b->opts.chunk_edges ? b->opts.chunk_edges : 64;
+    x.H = b->opts.chunk_edges ? b->opts.chunk_edges : 16;
     if (x.H > 65535) {
         rpq::set_error("chunk_edges must be <= 65535");
         return RPQ_EINVAL;
@@ -914,6 +914,11 @@ int plan(rpq_batch* b) {
     for (auto& q : b->queries)
         for (uint32_t i = 0; i < RPQ_MAX_STATES * RPQ_MAX_LABELS; ++i)
             max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(q.nfa.delta[i]));
+    const uint64_t bitmap_bytes = x.slot_stride * x.K * 8 * 2;   // Vis + Next of one slot
+    // default slice size: the smallest that keeps a slot's slice buffers within a quarter of its bitmaps
+    while (!b->opts.chunk_edges && x.H < 256 &&
+           2 * (2 * (uint64_t)x.Qmax * max_succ * g->E / x.H + 2) * sizeof(Desc) > bitmap_bytes / 4)
+        x.H *= 2;
     const uint64_t desc_per_slot = 2 * (uint64_t)x.Qmax * max_succ * g->E / x.H + 2;
     // per slot: Vis + Next, touch bits, Ans, summary, first-visit log, and its share of the two
     // frontier lists (row id + K-word row per entry) and of the two descriptor buffers
@@ -1403,7 +1408,7 @@ int rpq_batch_autotune(rpq_batch_t b, const rpq_batch_opts* candidates, uint32_t
         cands.assign(candidates, candidates + n_candidates);
     } else {
         const uint32_t widths[] = {64, 256, 512, 1024, 2048};
-        const uint32_t chunks[] = {32, 64, 256};
+        const uint32_t chunks[] = {16, 64};
         for (uint32_t w : widths)
             for (uint32_t h : chunks) {
                 rpq_batch_opts o{};

@@ -971,9 +971,13 @@ __global__ __launch_bounds__(kBlock) void k_key_tallies(const uint64_t* __restri
     if (__lane_id() == 0 && h) atomicAdd(&acc[0], (unsigned long long)h);
 }
 
-uint64_t sparse_start_slots(uint64_t n_src, uint32_t Q) {
+// Starting hash-set size: 16 slots per (source, state), at least 2^16, and as large as the free
+// workspace allows up to 2^24 slots (filling 2^24 slots costs tens of microseconds, a restart
+// after an overflow costs a whole search).
+uint64_t sparse_start_slots(uint64_t n_src, uint32_t Q, uint64_t free_bytes = 0) {
     uint64_t T = 1ull << 16;
     while (T < 16 * n_src * (uint64_t)Q && T < (1ull << 34)) T *= 2;
+    while (T < (1ull << 24) && (2 * T) * 20 + (2 * T) * 12 + (1ull << 20) <= free_bytes) T *= 2;
     return T;
 }
 
@@ -1053,7 +1057,8 @@ int sparse_eval(rpq_graph_t g, const rpq_nfa* nfa_in, const uint32_t* sources, u
             }
         }
         const rpq::Csr& csr = reverse ? g->in : g->out;
-        uint64_t T = sparse_start_slots(n_sources, nfa.n_states);
+        // room for the search and, after it, the sort of up to T/2 pairs (~12 bytes per slot)
+        uint64_t T = sparse_start_slots(n_sources, nfa.n_states, c.ar.free_bytes());
         uint64_t* keys = nullptr;
         uint64_t nk = 0, eprod = 0, levels = 0;
         for (;;) {

@@ -647,12 +647,14 @@ void to_dev_nfa(const rpq_nfa* nfa, uint32_t L, DevNfa* d) {
 
 // Default shape: about 64K sources in flight, in units of up to 2048 sources (measured on
 // R-MAT scale 18, all-pairs: throughput rises with the sources advanced per level up to ~64K;
-// 2048-wide units beat 1024 and 4096 at equal sources in flight), entries of more than 64
-// items cut into slices, and per-call workspace within 64 GB of the 288 GB device.
+// 2048-wide units beat 1024 and 4096 at equal sources in flight), entries of more than 16
+// items cut into slices (16 beat 32, 64, 128 and 256 there; raised on graphs where the slice
+// buffers would outgrow a quarter of the bitmaps), and per-call workspace within 64 GB of the
+// 288 GB device.
 constexpr uint64_t kTargetInFlight = 65536;
 constexpr uint64_t kWorkspaceBudget = 64ull << 30;
 constexpr uint32_t kMaxDefaultWidth = 2048;
-constexpr uint32_t kDefaultChunk = 64;
+constexpr uint32_t kDefaultChunk = 16;
 
 uint64_t unit_bytes(uint64_t QV, uint32_t W) {
     // Vis + Next + two frontier lists of rows + row ids
@@ -684,6 +686,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
         rpq::set_error("chunk_edges must be <= 65535");
         return RPQ_EINVAL;
     }
+    const bool auto_chunk = !(o && o->chunk_edges);
     x.sync_every = (o && o->sync_every) ? o->sync_every : 4;
     const uint64_t units = std::max<uint64_t>(1, (n_sources + x.W - 1) / x.W);
     const uint64_t QV = (uint64_t)x.Q * x.V;
@@ -696,6 +699,9 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
         for (uint32_t l = 0; l < x.L; ++l) max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(dn.delta[q * x.L + l]));
         items += (uint64_t)max_succ * g->E;   // the in-CSR holds the same distinct edges
     }
+    // default slice size: the smallest (fastest) that keeps a unit's two slice buffers within a
+    // quarter of its bitmaps
+    while (auto_chunk && x.H < 256 && 2 * (2 * items / x.H + 2) * sizeof(Desc) > unit_bytes(QV, x.W) / 4) x.H *= 2;
     const uint64_t desc_per_unit = 2 * items / x.H + 2;
     uint64_t G = (o && o->concurrency) ? o->concurrency : 0;
     if (!G) {

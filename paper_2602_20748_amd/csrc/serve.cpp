@@ -314,6 +314,8 @@ int rpq_serve_submit(rpq_server_t s, const rpq_request* r, uint64_t* ticket) {
         const uint64_t n = (r->flags & RPQ_ALL_SOURCES) && r->n_sources == 0 ? s->g->V : r->n_sources;
         if (r->flags & RPQ_SPARSE) {
             RPQ_TRY(rpq_eval_workspace_size(s->g, &r->nfa, n, r->flags, nullptr, &j->need));
+            // room for the search to grow without a trip back through the queue
+            j->need = std::max<uint64_t>(j->need, std::min<uint64_t>(pool / 16, 512ull << 20));
             if (j->need > pool) {
                 rpq::set_error("sparse request needs %llu bytes; the pool has %llu", (unsigned long long)j->need,
                                (unsigned long long)pool);

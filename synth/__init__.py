@@ -316,7 +316,9 @@ def serve_requests(n: int, n_vertices: int, names: Sequence[str], seed: int,
     40% RPQs over a slice of slice_width consecutive sources ("rpq_slice", regex, sources) and 20%
     CRPQs of 2-3 atoms anchored at a random source s ("crpq", atoms, n_vars, binding): the chain
     s -r1-> y -r2-> z, the fork s -r1-> y, s -r2-> y, or the triangle s -r1-> y, y -r2-> z,
-    s -r3-> z.  Regexes come from random_regex (1-11 label occurrences, depth <= 4)."""
+    s -r3-> z.  RPQ regexes come from random_regex (1-11 label occurrences, depth <= 4); CRPQ
+    atoms draw 1-3 occurrences from the rarer half of the labels, whose closures stay small, so
+    a chain's second atom does not start from most of the graph."""
     rng = np.random.default_rng(seed)
     n_slices = max(1, n_vertices // slice_width)
     out = []
@@ -332,7 +334,8 @@ def serve_requests(n: int, n_vertices: int, names: Sequence[str], seed: int,
         else:
             s = int(rng.integers(0, n_vertices))
             shape = int(rng.integers(0, 3))
-            r = [random_regex(rng, names, max_leaves=4) for _ in range(3)]
+            rare = list(names[len(names) // 2:]) or list(names)
+            r = [random_regex(rng, rare, max_leaves=3) for _ in range(3)]
             if shape == 0:
                 out.append(("crpq", [(0, r[0], 1), (1, r[1], 2)], 3, [s, None, None]))
             elif shape == 1:
