@@ -311,11 +311,11 @@ def main():
         for q in queries:
             per_query[q]["ms"] = round(qtimes[q] * 1e3 / max(1, args.steps), 3)
         # dominant kernel of the plain form: the level expansion.  Algorithmic bytes:
-        # 4 B per edge item + 16 B per descriptor + 8 B per frontier word read
-        # + 8 B per visited-word read + 16 B per next-word OR (read + write)
+        # 4 B per item + 16 B per segment + 8 B per frontier word read
+        # + 16 B per visited-word read (visited and next-frontier word) + 8 B per next-word OR (write)
         launches = max(1, prof["expand_launches"])
         alg = (4 * prof["edge_items"] + 16 * prof["descriptors"] + 8 * prof["row_words"]
-               + 8 * prof["word_reads"] + 16 * prof["word_updates"]) / launches
+               + 16 * prof["word_reads"] + 8 * prof["word_updates"]) / launches
         avg_ms = prof["expand_ms"] / launches
         achieved = alg / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
         forms["plain"] = dict(
@@ -374,7 +374,7 @@ def main():
         # per non-zero word: 16 B next clear + visited write; 16 B per descriptor written)
         # + compaction (8 B per touch word scanned per iteration, 4 B per row id).
         exp = (4 * tally["edge_items"] + 16 * tally["descriptors"] + 8 * K * tally["descriptors"]
-               + 8 * tally["word_reads"] + 16 * tally["word_updates"])
+               + 16 * tally["word_reads"] + 8 * tally["word_updates"])
         fin = tally["finalized_rows"] * (4 + 24 * K + 12) + 16 * tally["finalized_words"] + 16 * tally["descriptors"]
         cmp_ = 8 * tally["iterations"] * st["touch_words"] + 4 * tally["finalized_rows"]
         alg = (exp + fin + cmp_) / max(1, args.steps)

@@ -527,8 +527,9 @@ int rpq_serve_stop(rpq_server_t s);
  *   edge_items    (entry, edge) pairs expanded (each reads one 4-byte neighbour id)
  *   descriptors   16-byte work descriptors read
  *   row_words     8-byte frontier words read (one per descriptor and word)
- *   word_reads    8-byte visited words read (frontier word != 0, per successor state)
- *   word_updates  8-byte atomic ORs into the next-frontier bitmap
+ *   word_reads    8-byte visited words read, each with the 8-byte next-frontier word beside it
+ *                 (frontier word != 0)
+ *   word_updates  8-byte atomic ORs into the next-frontier bitmap (bits not yet there)
  */
 typedef struct {
     uint64_t expand_launches;

@@ -219,7 +219,7 @@ __device__ __forceinline__ void expand_segments(const BArgs& a, const uint64_t* 
         const uint32_t n_here = min(64u, total - base);
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
             uint32_t r[kUnroll];
-            uint64_t f[kUnroll], vw[kUnroll];
+            uint64_t f[kUnroll], vw[kUnroll], nx[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t idx = j + u * GS + grp;
@@ -228,10 +228,14 @@ __device__ __forceinline__ void expand_segments(const BArgs& a, const uint64_t* 
                 f[u] = idx < n_here ? xld(rows + (uint64_t)e * K + k) : 0;
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) vw[u] = f[u] ? xld(a.vis + (uint64_t)r[u] * K + k) : ~0ull;
+            for (int u = 0; u < kUnroll; ++u) {
+                // visited and Next words together (as in the plain form)
+                vw[u] = f[u] ? xld(a.vis + (uint64_t)r[u] * K + k) : ~0ull;
+                nx[u] = f[u] ? xld(a.next + (uint64_t)r[u] * K + k) : ~0ull;
+            }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t nb = f[u] & ~vw[u];
+                const uint64_t nb = f[u] & ~vw[u] & ~nx[u];
                 t_wread += f[u] != 0;
                 t_wupd += nb != 0;
                 if (nb) or_relaxed(a.next + (uint64_t)r[u] * K + k, nb);

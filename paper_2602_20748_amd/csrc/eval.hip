@@ -174,7 +174,7 @@ __device__ __forceinline__ void expand_segments(const Args& a, const uint32_t* s
         // word phase
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
             uint32_t r[kUnroll];
-            uint64_t f[kUnroll], vw[kUnroll];
+            uint64_t f[kUnroll], vw[kUnroll], nx[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t idx = j + u * GS + grp;
@@ -183,10 +183,16 @@ __device__ __forceinline__ void expand_segments(const Args& a, const uint32_t* s
                 f[u] = idx < n_here ? rows[(uint64_t)e * K + k] : 0;
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) vw[u] = f[u] ? a.vis[(uint64_t)r[u] * K + k] : ~0ull;
+            for (int u = 0; u < kUnroll; ++u) {
+                // the visited word and the Next word together: bits already in Next need no OR, and
+                // the OR then finds its line in L2 (Next only gains bits during an expansion, so a
+                // stale copy can only let through an OR that is not needed)
+                vw[u] = f[u] ? a.vis[(uint64_t)r[u] * K + k] : ~0ull;
+                nx[u] = f[u] ? a.next[(uint64_t)r[u] * K + k] : ~0ull;
+            }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t nb = f[u] & ~vw[u];
+                const uint64_t nb = f[u] & ~vw[u] & ~nx[u];
                 t_wread += f[u] != 0;
                 t_wupd += nb != 0;
                 if (nb) or_relaxed(&a.next[(uint64_t)r[u] * K + k], nb);
