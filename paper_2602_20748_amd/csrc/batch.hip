@@ -556,27 +556,48 @@ template <int K>
 __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
     const int np = p ^ 1;
     uint32_t* ids = np ? a.ids1 : a.ids0;
+    const int lane = threadIdx.x & 63;
     const uint64_t total = (uint64_t)a.G * a.W;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (uint64_t)a.n_blocks * kBlock) {
-        const uint32_t slot = (uint32_t)(i / a.W), j = (uint32_t)(i % a.W);
-        if (ld32(&a.slots[slot].state) != S_RUN || ld32(&a.slots[slot].start_iter) != iter) continue;
-        const BUnit unit = a.units[ld32(&a.slots[slot].unit)];
-        if (j >= unit.n) continue;
-        const BQuery& Qy = a.queries[unit.query];
-        const uint64_t sidx = unit.src_off + j;
-        const uint32_t s = Qy.sources ? Qy.sources[sidx] : (uint32_t)sidx;
-        uint32_t init = a.nfas[unit.query].init;
-        while (init) {
-            const uint32_t q = __ffs(init) - 1;
-            init &= init - 1;
-            const uint64_t lrow = (uint64_t)q * a.V + s;
-            const uint64_t row = (uint64_t)slot * a.slot_stride + lrow;
-            or_relaxed(&a.next[row * K + (j >> 6)], 1ull << (j & 63));
-            // one list entry per (slot, q, s): the first source bit of a word is enough since
-            // sources are distinct vertices, every (q, s) row gets exactly one source
-            const unsigned long long pos = atomicAdd(&a.ctl->list_cnt[np], 1ull);
-            if (pos < a.list_cap) ids[pos] = (uint32_t)row;
-            else atomicOr(&a.ctl->err, 1ull);
+    const uint64_t stride = (uint64_t)a.n_blocks * kBlock;
+    // wave-uniform loop so that list appends can be counted once per wave
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); i0 < total; i0 += stride) {
+        const uint64_t i = i0 + lane;
+        bool seed = false;
+        uint32_t slot = 0, j = 0, s = 0, init = 0;
+        if (i < total) {
+            slot = (uint32_t)(i / a.W);
+            j = (uint32_t)(i % a.W);
+            if (ld32(&a.slots[slot].state) == S_RUN && ld32(&a.slots[slot].start_iter) == iter) {
+                const BUnit unit = a.units[ld32(&a.slots[slot].unit)];
+                if (j < unit.n) {
+                    const BQuery& Qy = a.queries[unit.query];
+                    const uint64_t sidx = unit.src_off + j;
+                    s = Qy.sources ? Qy.sources[sidx] : (uint32_t)sidx;
+                    init = a.nfas[unit.query].init;
+                    seed = true;
+                }
+            }
+        }
+        // one list entry per (slot, q, s): sources are distinct vertices, so every (q, s) row of a
+        // slot gets exactly one source bit
+        while (__ballot(seed && init != 0)) {
+            const bool take = seed && init != 0;
+            uint64_t row = 0;
+            if (take) {
+                const uint32_t q = __ffs(init) - 1;
+                init &= init - 1;
+                row = (uint64_t)slot * a.slot_stride + (uint64_t)q * a.V + s;
+                or_relaxed(&a.next[row * K + (j >> 6)], 1ull << (j & 63));
+            }
+            const uint64_t m = __ballot(take);
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&a.ctl->list_cnt[np], (unsigned long long)__popcll(m));
+            base = __shfl(base, 0, 64);
+            const unsigned long long pos = base + __popcll(m & rpqd::lanemask_lt());
+            if (take) {
+                if (pos < a.list_cap) ids[pos] = (uint32_t)row;
+                else atomicOr(&a.ctl->err, 1ull);
+            }
         }
     }
 }
@@ -653,15 +674,28 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
                 if (rel < (uint32_t)GS) my_info = got;
             }
         }
+        // first-visit log: rows whose Vis was empty and that gained bits.  The list is slot-major, so
+        // the appending lanes of a wave usually share a slot: then one counter update serves the wave
+        const bool first = active && !(my_info >> 31) && (my_info & 0x7FFFFFFFu);
+        const uint64_t fmask = __ballot(first);
+        if (fmask) {
+            const uint32_t s0 = __shfl(slot, __ffsll((long long)fmask) - 1, 64);
+            if (__ballot(first && slot != s0) == 0) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(&a.slots[s0].log_n, (unsigned long long)__popcll(fmask));
+                base = __shfl(base, 0, 64);
+                const unsigned long long li = base + __popcll(fmask & rpqd::lanemask_lt());
+                if (first && li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = lrow;
+            } else if (first) {
+                const unsigned long long li = atomicAdd(&a.slots[slot].log_n, 1ull);
+                if (li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = lrow;
+            }
+        }
         if (active) {
             const uint32_t pc = my_info & 0x7FFFFFFFu;
             ++t_frows;
             if (my_ans != 0xFFFFFFFFu && pc)
                 or_relaxed(&a.summ[(uint64_t)slot * a.summ_words + v / 64], 1ull << (v & 63));
-            if (!(my_info >> 31) && pc) {
-                const unsigned long long li = atomicAdd(&a.slots[slot].log_n, 1ull);
-                if (li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = lrow;
-            }
             const uint64_t m = a.lmask[v] & nfa->qlab[q];
             work = m ? rpqd::entry_work(a.row_ptr, L, nfa->delta, v, q, m) : 0;
             eprod = (uint64_t)pc * work;
