@@ -388,16 +388,21 @@ __device__ void phase_retire_extract(const BArgs& a, uint32_t n_ret) {
         uint64_t cnt = 0, h = 0, cursor = 0;
         const uint64_t pidx = ((uint64_t)slot * a.W + j) * a.nchunks + chunk;
         if (WRITE && valid) cursor = a.srcbase[(uint64_t)slot * a.W + j] + a.partial[pidx];
+        // per 64-vertex group with a non-empty summary word: one load per lane (lane = vertex),
+        // then the non-zero words in ascending vertex order
         uint64_t any = __ballot(sw != 0);
         while (any) {
             const int wl = __ffsll((long long)any) - 1;
             any &= any - 1;
-            uint64_t bits = __shfl(sw, wl, 64);
-            while (bits) {
-                const int bb = __ffsll((long long)bits) - 1;
-                bits &= bits - 1;
-                const uint32_t v = vbeg + (uint32_t)wl * 64 + bb;
-                const uint64_t word = xld(a.ans + ((uint64_t)slot * a.V + v) * K + k);
+            const uint64_t bits = __shfl(sw, wl, 64);
+            const uint32_t vg = vbeg + (uint32_t)wl * 64;
+            const uint64_t mine = ((bits >> lane) & 1) ? xld(a.ans + ((uint64_t)slot * a.V + vg + lane) * K + k) : 0;
+            uint64_t nz = __ballot(mine != 0);
+            while (nz) {
+                const int jj = __ffsll((long long)nz) - 1;
+                nz &= nz - 1;
+                const uint64_t word = __shfl(mine, jj, 64);
+                const uint32_t v = vg + (uint32_t)jj;
                 if (valid && ((word >> lane) & 1)) {
                     const uint64_t key = (s << 32) | v;
                     if (WRITE) {
