@@ -324,7 +324,7 @@ int rpq_batch_result(rpq_batch_t b, uint32_t query_id, rpq_result* out);
 int rpq_batch_stats(rpq_batch_t b, rpq_batch_info* out);
 
 /*
- * Autotune the batch's unit width, slot count and descriptor size: each
+ * Autotune the batch's unit width, slot count and slice size: each
  * candidate (default set: widths 64..2048 x chunk 16/64 items, slots sized
  * automatically) whose plan fits in workspace_bytes runs a bounded prefix of
  * the unit queue twice (capture, then replay), and the candidate with the most
@@ -524,9 +524,11 @@ int rpq_serve_stop(rpq_server_t s);
  * calls while enabled (host struct).  Durations come from HIP events
  * recorded on the caller's stream around each launch; the work counts are
  * exact device-side tallies of the expansion kernel:
- *   edge_items    (entry, edge) pairs expanded (each reads one 4-byte neighbour id)
- *   descriptors   16-byte work descriptors read
- *   row_words     8-byte frontier words read (one per descriptor and word)
+ *   edge_items    items expanded: (frontier entry, edge, successor state), each reading one
+ *                 4-byte neighbour id
+ *   descriptors   work segments: light frontier entries taken whole from the list and 16-byte
+ *                 slices of heavy ones
+ *   row_words     8-byte frontier words read (K per segment)
  *   word_reads    8-byte visited words read, each with the 8-byte next-frontier word beside it
  *                 (frontier word != 0)
  *   word_updates  8-byte atomic ORs into the next-frontier bitmap (bits not yet there)

@@ -141,18 +141,10 @@ __device__ __forceinline__ void or_relaxed(uint64_t* p, uint64_t v) {
 }
 
 
-// Loads of data written in an earlier phase of the persistent kernel.
-#ifdef RPQ_COHERENT_LOADS
-__device__ __forceinline__ uint64_t xld(const uint64_t* p) {
-    return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t xld(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-#else
+// Loads of data written in an earlier phase of the persistent kernel: plain loads, ordered by the
+// grid barrier's release/acquire fences.
 __device__ __forceinline__ uint64_t xld(const uint64_t* p) { return *p; }
 __device__ __forceinline__ uint32_t xld(const uint32_t* p) { return *p; }
-#endif
 
 __device__ __forceinline__ uint64_t gwave(const BArgs& a) {
     return (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
@@ -161,7 +153,7 @@ __device__ __forceinline__ uint64_t gwaves(const BArgs& a) { return (uint64_t)a.
 
 // ------------------------------------------------------------------------------------------------
 // expand: the level expansion of the plain form with per-slot automata.  Segments (entry, first
-// item, item count): light entries of the frontier list whole, then descriptors of heavy ones.
+// item, item count): light entries of the frontier list whole, then slices of heavy ones.
 // Item phase: lane per item (segment by a wave prefix); word phase: groups of K lanes per item,
 // lane k on word k of the rows.
 // ------------------------------------------------------------------------------------------------
@@ -608,7 +600,7 @@ __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// finalize: list p^1 -> frontier rows, Vis (with first-visit log), Ans (+ summary), descriptors.
+// finalize: list p^1 -> frontier rows, Vis (with first-visit log), Ans (+ summary), slices of heavy entries.
 // Word phase: groups of K lanes per row; row phase: lane per row (as in the plain form).
 // ------------------------------------------------------------------------------------------------
 template <int K>
@@ -713,7 +705,7 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
         } else if (active && eprod) {
             atomicAdd(&a.qout[qid].eprod, (unsigned long long)eprod);
         }
-        // entries of more than H items are cut into descriptors, written by the whole wave
+        // entries of more than H items are cut into slices of at most H items, written by the whole wave
         const uint64_t ndesc = work > H ? (work + H - 1) / H : 0;
         const uint64_t dincl = rpqd::wave_incl_scan_u64(ndesc);
         const uint64_t dexcl = dincl - ndesc;
@@ -951,7 +943,7 @@ int plan(rpq_batch* b) {
     x.n_units = (uint32_t)b->units.size();
     x.slot_stride = ((uint64_t)x.Qmax * g->V + 63) / 64 * 64;
     x.summ_words = (g->V + 63) / 64;
-    // descriptors of one level and slot: entries with more than H items take ceil(work / H) <= 2 work / H
+    // slices of one level and slot: entries with more than H items take ceil(work / H) <= 2 work / H
     // each, and all entries of one state hold at most E * max |delta(q, l)| items
     uint32_t max_succ = 1;
     for (auto& q : b->queries)
@@ -964,7 +956,7 @@ int plan(rpq_batch* b) {
         x.H *= 2;
     const uint64_t desc_per_slot = 2 * (uint64_t)x.Qmax * max_succ * g->E / x.H + 2;
     // per slot: Vis + Next, touch bits, Ans, summary, first-visit log, and its share of the two
-    // frontier lists (row id + K-word row per entry) and of the two descriptor buffers
+    // frontier lists (row id + K-word row per entry) and of the two slice buffers
     const uint64_t per_slot = x.slot_stride * x.K * 8 * 2 + x.slot_stride / 8 + (uint64_t)g->V * x.K * 8 +
                               x.summ_words * 8 + x.slot_stride * 4 + 2 * x.slot_stride * (4 + x.K * 8) +
                               2 * desc_per_slot * sizeof(Desc);

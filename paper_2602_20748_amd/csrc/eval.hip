@@ -22,12 +22,12 @@
 //             (edge v -l-> w, successor q') it ORs the entry's frontier bits that are new for
 //             (q', w) into Next; the first writer of a row sets its touch bit.  Entries with
 //             at most H items are expanded straight from the frontier list; larger ones
-//             arrive as work descriptors of at most H items (edge-balanced work whatever the
-//             degree skew, with descriptor memory bounded by 2 * items / H).
+//             arrive as slices of at most H items (edge-balanced work whatever the degree
+//             skew, with slice memory bounded by 2 * items / H).
 //   compact   the touched rows become the next frontier list (ballot/popcount prefix).
 //   finalize  for each new entry moves Next into a compact frontier row, ORs it into Vis
 //             (and into Ans when q' is final), counts the product edges it will examine,
-//             and cuts entries of more than H items into descriptors.
+//             and cuts entries of more than H items into slices.
 // The fixpoint is reached when a level appends nothing; the host checks the
 // list counter every few levels (no hop bound).
 //
@@ -49,7 +49,7 @@ constexpr int kWaves = kBlock / 64;
 
 // counters[] slots (uint64)
 constexpr int C_LIST = 0;       // [0..1] list length per parity
-constexpr int C_DESC = 2;       // [2..3] descriptor count per parity
+constexpr int C_DESC = 2;       // [2..3] slice count per parity
 constexpr int C_EPROD = 4;      // product edges examined
 constexpr int C_ERR = 6;        // capacity / validation error flags
 constexpr int C_PAIRBASE = 7;   // global key index where the current group starts
@@ -120,7 +120,7 @@ __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint6
 
 // ------------------------------------------------------------------------------------------------
 // level expansion.  Work comes as segments (entry, first item, item count): first every light
-// entry of the frontier list whole, then the descriptors of the heavy ones.  Per batch of
+// entry of the frontier list whole, then the slices of the heavy ones.  Per batch of
 // segments (one per lane) the work is mapped twice per 64 items:
 //   item phase  lane i takes item i: finds its segment (prefix of the wave's segment lengths),
 //               decodes the edge target w and successor q', and forms the target row id;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
         t_segs += __popcll(__ballot(have)) * (lane == 0);
         expand_segments<K>(a, s_delta, rows, have, (uint32_t)e, slot, q, v, m, 0, len, t_items, t_wread, t_wupd);
     }
-    // heavy entries, as descriptors
+    // heavy entries, as slices
     const Desc* desc = desc_of(a, p);
     const uint64_t n_db = (n_desc + 63) / 64;
     for (uint64_t b = wave; b < n_db; b += n_waves) {
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
 __global__ __launch_bounds__(kBlock) void k_compact(Args a, int p, uint64_t n_rows, uint32_t level) {
     const int np = p ^ 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // the list and descriptors of parity p were consumed by the expansion that just ran
+        // the list and slices of parity p were consumed by the expansion that just ran
         a.counters[C_LIST + p] = 0;
         a.counters[C_DESC + p] = 0;
     }
@@ -324,8 +324,9 @@ __global__ __launch_bounds__(kBlock) void k_compact(Args a, int p, uint64_t n_ro
 //   word phase  groups of K lanes take a row each (lane k, word k): Next moves into the compact
 //               frontier row, Vis and (for final states) Ans take the new bits, and the group
 //               counts the new source bits of the row;
-//   row phase   lane i takes row i: counts the product edges it will examine and cuts its
-//               out-edges into descriptors of at most H edges per (label, successor state).
+//   row phase   lane i takes row i: counts the items of its item space (the product edges each of
+//               its new source bits will examine); the slices of rows with more than H items are
+//               written by the whole wave.
 // ------------------------------------------------------------------------------------------------
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
                 if (rel < (uint32_t)GS) my_pc = got;
             }
         }
-        // row phase: product edges; entries of more than H items are cut into descriptors
+        // row phase: product edges; entries of more than H items are cut into slices
         uint64_t work = 0;
         if (active) {
             const uint64_t m = a.lmask[v] & s_qlab[q];
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
             unsigned long long dbase = 0;
             if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)dtot);
             dbase = __shfl(dbase, 0, 64);
-            // the wave writes its descriptors together: descriptor i goes to the lane owning it
+            // the wave writes its slices together: slice i is described by the lane owning it
             for (uint64_t i0 = 0; i0 < dtot; i0 += 64) {
                 const uint64_t i = i0 + lane;
                 int c = 0;
@@ -697,7 +698,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     const uint64_t units = std::max<uint64_t>(1, (n_sources + x.W - 1) / x.W);
     const uint64_t QV = (uint64_t)x.Q * x.V;
     const uint64_t bitmap_bytes = QV * x.K * 8;
-    // descriptors of one level and unit: entries with work > H take ceil(work / H) <= 2 work / H
+    // slices of one level and unit: entries with work > H take ceil(work / H) <= 2 work / H
     // each, and the work of all entries of state q is at most E * max |delta(q, l)|
     uint64_t items = 0;
     for (uint32_t q = 0; q < x.Q; ++q) {
@@ -716,7 +717,6 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
         G = std::min<uint64_t>(G, std::max<uint64_t>(1, kWorkspaceBudget / per_unit));
     }
     G = std::min<uint64_t>(G, units);
-    if (G > 65535) G = 65535;   // slot ids travel in 16 bits of a descriptor
     x.G = (uint32_t)G;
     x.list_cap = G * QV;
     if (x.list_cap >= 0xFFFFFFFFull) {
