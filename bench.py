@@ -14,11 +14,14 @@ Two forms of the same step are timed:
            autotuner during warm-up.
 `value` is the product-graph edges per second of --form (default plain, the
 one-launch-per-query form this workload is defined on);
-both forms are reported.
+both forms are reported.  Beside them, batched vs plain is also measured
+where batching is meant to pay (256 single-source queries; 128 single-source
++ 128 slice queries, generated regexes) -- skip with --no-mixes.
 
 Metric: product-graph edges per second (per source, the product edges
 examined, counted on the Glushkov automaton), with distinct pairs per second.
 Prints one JSON line.  --gpus > 1 is not supported by this single-GPU build.
+--serve measures serving latency instead (its own JSON line).
 """
 from __future__ import annotations
 
@@ -58,6 +61,8 @@ def parse_args():
                     help="time only one form (profiling runs only)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--no-mixes", action="store_true",
+                    help="skip the batched-vs-plain comparison on many-query mixes")
     ap.add_argument("--serve", action="store_true",
                     help="serving measurement instead of the throughput step: Poisson streams of mixed "
                          "requests at each --qps rate (prints one JSON line of its own)")
@@ -233,6 +238,57 @@ def load_traffic(path, kernel, source_files):
         return None
 
 
+def mixes(g, el, seed):
+    """Batched vs plain where batching is meant to pay: 256 single-source queries, and 128
+    single-source queries with 128 all-pairs queries over 4,096-source slices (generated regexes,
+    seeded).  Wall time of the plain launches one after the other vs one batched run (plan from the
+    autotuner, graph captured on a first run); results must be identical."""
+    import numpy as np
+    import torch
+
+    import paper_2602_20748_amd as rpq
+    import synth
+
+    out = {}
+    for kind in ("single_source_256", "mixed_128_single_128_slices"):
+        mix = synth.rmat_query_mix(256, el.n_vertices, el.names, seed=seed + 1000, slice_width=4096)
+        if kind.startswith("single"):
+            rng = np.random.default_rng(seed + 2000)
+            mix = [(rx, np.array([int(rng.integers(0, el.n_vertices))], np.uint32)) for rx, _ in mix]
+        nfas = [rpq.rpq_nfa_compile(rx, el.names) for rx, _ in mix]
+        print("bench: mix %s" % kind, file=sys.stderr, flush=True)
+        res = []
+        for rep in range(2):   # the first pass warms the workspaces
+            res = []
+            eprod = 0
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for nfa, (_, src) in zip(nfas, mix):
+                r = rpq.rpq_eval(g, nfa, src)
+                res.append((r.count, r.hash, r.product_edges))
+                eprod += r.product_edges
+            torch.cuda.synchronize()
+            t_plain = time.perf_counter() - t
+        b = rpq.rpq_batch_create(g)
+        for nfa, (_, src) in zip(nfas, mix):
+            b.add(nfa, src)
+        tuned = b.autotune()
+        b.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t
+        st = b.stats()
+        same = all((b.result(i).count, b.result(i).hash, b.result(i).product_edges) == res[i] for i in range(len(mix)))
+        out[kind] = dict(queries=len(mix), product_edges=eprod, plain_ms=round(t_plain * 1e3, 2),
+                         batched_ms=round(t_batch * 1e3, 2), batched_over_plain=round(t_plain / t_batch, 3),
+                         results_identical=same, plan=dict(batch_width=st["batch_width"], slots=st["slots"],
+                                                            units=st["n_units"], tuned=tuned))
+        b.close()
+    return out
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -332,6 +388,8 @@ def main():
                                                          "word_updates", "expand_ms", "finalize_ms")}))
 
     # ------------------------------------------------------------------ batched form
+    g.release_workspace()
+    torch.cuda.empty_cache()
     if args.only in ("", "batched"):
         b = rpq.rpq_batch_create(g)
         for q in queries:
@@ -396,6 +454,11 @@ def main():
                           counters={k: v // max(1, args.steps) for k, v in tally.items()}))
         b.close()
 
+    mix_results = None
+    if not args.no_mixes and not args.only and not args.queries:
+        g.release_workspace()
+        torch.cuda.empty_cache()
+        mix_results = mixes(g, el, spec["seed"])
     form = args.form if args.form in forms else next(iter(forms))
     main_form = forms[form]
     cpu = None
@@ -423,6 +486,7 @@ def main():
         "distinct_pairs_per_s": main_form["distinct_pairs_per_s"],
         "batched_over_plain": (forms["batched"]["value"] / forms["plain"]["value"]
                                if "batched" in forms and "plain" in forms else None),
+        "batched_vs_plain_mixes": mix_results,
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "roofline"} for k, v in forms.items()},
         "roofline": main_form["roofline"],
         "roofline_other": {k: v["roofline"] for k, v in forms.items() if k != form},

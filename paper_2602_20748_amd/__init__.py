@@ -315,6 +315,10 @@ class Graph:
     def info(self) -> dict:
         return rpq_graph_info_get(self)
 
+    def release_workspace(self) -> None:
+        """Drop the cached workspace (the memory returns to torch's allocator)."""
+        self._ws.clear()
+
     def workspace(self, nbytes: int):
         """A cached device workspace of at least nbytes (grown on demand)."""
         torch = _torch()
@@ -602,11 +606,15 @@ def rpq_batch_stats(b: Batch) -> dict:
 def rpq_batch_autotune(b: Batch, candidates=None, workspace_bytes: int = 0, stream=None) -> dict:
     """Pick the batch's width/slots/chunk by timing candidates (native tuner).
 
-    A workspace of workspace_bytes (default: 4x the current plan, at least 1 GiB) is
-    allocated for the timing runs and kept for the batch."""
+    A workspace of workspace_bytes (default: 4x the current plan, at least 1 GiB, at most three
+    quarters of the free device memory) is allocated for the timing runs and kept for the batch;
+    candidates whose plan does not fit it are skipped."""
     torch = _torch()
     if not workspace_bytes:
-        workspace_bytes = max(4 * rpq_batch_workspace_size(b), 1 << 30)
+        plan = rpq_batch_workspace_size(b)
+        free, _ = torch.cuda.mem_get_info()
+        held = b.ws.numel() if b.ws is not None else 0
+        workspace_bytes = max(plan, min(max(4 * plan, 1 << 30), (free + held) * 3 // 4))
     if b.ws is None or b.ws.numel() < workspace_bytes:
         b.ws = None
         b.ws = torch.empty(workspace_bytes, dtype=torch.uint8, device="cuda")
