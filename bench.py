@@ -104,6 +104,7 @@ def serve_main(args):
         nfa = [rpq.rpq_nfa_compile(r[1], el.names) if r[0] != "crpq" else None for r in reqs]
         print("bench: serving %d requests at %s QPS" % (n, tok), file=sys.stderr, flush=True)
         srv = rpq.Server(g, int(args.serve_pool_gib * (1 << 30)), workers=args.serve_workers)
+        last_note = time.time()
         t0 = srv.clock_ms() + 50.0
         tickets = []
         for i, r in enumerate(reqs):
@@ -117,14 +118,18 @@ def serve_main(args):
             else:
                 fl = rpq.RPQ_SPARSE if r[0] == "rpq_single" else 0
                 tickets.append(srv.submit_rpq(nfa[i], r[2], flags=fl, pairs=ring[i % len(ring)], arrival_ms=due))
-            if (i + 1) % 100 == 0:
+            if time.time() - last_note > 10:
+                last_note = time.time()
                 print("bench: submitted %d / %d" % (i + 1, n), file=sys.stderr, flush=True)
         done = []
         for t in tickets:
             done.append(srv.wait(t))
-            if len(done) % 100 == 0:
+            if time.time() - last_note > 10:
+                last_note = time.time()
                 print("bench: completed %d / %d" % (len(done), n), file=sys.stderr, flush=True)
         srv.stop()
+        del srv
+        torch.cuda.empty_cache()   # the pool goes back before the FIFO replay allocates its workspaces
         warm = t0 if burst else t0 + args.serve_warmup_seconds * 1e3
         meas = [d for d in done if d["arrival_ms"] >= warm] or done
         lat = np.array([d["end_ms"] - d["arrival_ms"] for d in meas])
@@ -137,7 +142,8 @@ def serve_main(args):
         fifo_ep = 0
         fifo_times = []
         for i, (r, d) in enumerate(zip(reqs, done)):
-            if (i + 1) % 100 == 0:
+            if time.time() - last_note > 10:
+                last_note = time.time()
                 print("bench: FIFO %d / %d" % (i + 1, n), file=sys.stderr, flush=True)
             t = time.perf_counter()
             if r[0] == "crpq":
@@ -171,6 +177,8 @@ def serve_main(args):
                            served_over_fifo=((ep / span) / (fifo_ep / fifo_s))
                            if burst and fifo_s > 0 and fifo_ep else None))
         print("bench: %s" % json.dumps(points[-1]), file=sys.stderr, flush=True)
+        g.release_workspace()
+        torch.cuda.empty_cache()
     line = {
         "metric": "p99 latency (serving)", "value": points[-1]["p99_ms"] if points else None, "unit": "ms",
         "n_gpus": 1, "higher_is_better": False, "dtype": "u64", "data": "synthetic (seeded R-MAT; Poisson arrivals)",

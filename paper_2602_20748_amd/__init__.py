@@ -849,10 +849,12 @@ class Server:
         return {n: int(getattr(st, n)) for n, _ in ServerStats._fields_}
 
     def stop(self) -> None:
+        """Finish every request, join the workers and release the device pool."""
         if self.handle is not None and self.handle.value:
             _check(load_library().rpq_serve_stop(self.handle))
         self.handle = None
         self._keep.clear()
+        self.pool = None
 
     def __del__(self):
         try:
