@@ -346,6 +346,11 @@ def test_parser_readings():
     assert parse("a|b.c", NAMES) == ("alt", ("lab", 0), ("cat", ("lab", 1), ("lab", 2)))
     assert parse("a+", NAMES) == ("plus", ("lab", 0))
     assert parse("knows.knows*", ["knows", "hasTag"]) == ("cat", ("lab", 0), ("star", ("lab", 0)))
+    # label names are matched longest first, so a name that extends another wins
+    nm = ["a", "ab", "b"]
+    assert parse("ab*", nm) == ("star", ("lab", 1))
+    assert parse("a.b*", nm) == ("cat", ("lab", 0), ("star", ("lab", 2)))
+    assert parse("aab", nm) == ("cat", ("lab", 0), ("lab", 1))
     with pytest.raises(ValueError):
         parse("a.(b", NAMES)
     with pytest.raises(ValueError):
@@ -457,6 +462,32 @@ def test_product_edges_closed_form_for_a_dot_b():
         db = mats[1].sum(axis=1).astype(np.int64)
         want = int(sum(da[s] + db[mats[0][s]].sum() for s in range(n)))
         assert rpq(g, "a.b").product_edges == want
+
+
+def test_hop_count_is_the_largest_first_reach_distance():
+    # For a* the product pairs reached at depth k >= 1 are (w, 1) with w first
+    # reached by a k-edge walk, so the deepest level is the largest such k over
+    # the sources: found here from Boolean matrix powers, not by a search.
+    n = 9
+    path = OracleGraph(n, np.arange(n - 1, dtype=np.uint32), np.zeros(n - 1, np.uint8),
+                       np.arange(1, n, dtype=np.uint32), 1, ["a"])
+    assert rpq(path, "a*").max_hops == n - 1
+    assert rpq(path, "a*", sources=np.array([5], np.uint32)).max_hops == n - 1 - 5
+    rng = np.random.default_rng(41)
+    for trial in range(15):
+        n = int(rng.integers(1, 40))
+        src, lab, dst = random_graph(rng, n, 2 * n, 1)
+        g = OracleGraph(n, src, lab, dst, 1, ["a"])
+        A = label_mats(n, 1, zip(src.tolist(), lab.tolist(), dst.tolist()))[0].astype(np.int64)
+        seen = np.zeros((n, n), dtype=bool)
+        P = np.eye(n, dtype=np.int64)
+        ecc = np.zeros(n, dtype=np.int64)
+        for k in range(1, n + 1):
+            P = ((P @ A) > 0).astype(np.int64)
+            new = (P > 0) & ~seen
+            ecc[new.any(axis=1)] = k
+            seen |= P > 0
+        assert rpq(g, "a*").max_hops == int(ecc.max()), trial
 
 
 # ------------------------------------------------------------------------------------------------
