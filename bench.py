@@ -38,6 +38,12 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0
 
 
+def describe_graph(spec):
+    if spec["kind"] == "rmat":
+        return "R-MAT scale %d" % spec["scale"]
+    return spec["kind"]
+
+
 def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,8 +59,10 @@ def parse_args():
     ap.add_argument("--no-autotune", action="store_true", help="batched form: keep the default plan")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline leg (0 disables it)")
-    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic_rmat18.json"),
+    ap.add_argument("--traffic-file", default="",
                     help="measured HBM bytes per launch of the dominant kernels (rocprofv3 --pmc), if present")
+    ap.add_argument("--sources", type=int, default=0,
+                    help="plain/batched forms: evaluate from this many seeded sampled sources (0 = all pairs)")
     ap.add_argument("--queries", default="",
                     help="comma-separated subset of the workload's queries (profiling runs only)")
     ap.add_argument("--only", choices=["", "plain", "batched"], default="",
@@ -228,8 +236,9 @@ def cpu_baseline(el, queries, budget_s):
                     n, el.n_vertices, len(queries), dt, eprod))
 
 
-def load_traffic(path, kernel, source_files):
-    """Measured HBM bytes per launch, valid only for the kernel sources it was taken with."""
+def load_traffic(path, kernel, source_files, tag):
+    """Measured HBM bytes per launch, valid only for the kernel sources and the workload
+    (tag = workload name, source count, queries) it was taken with."""
     import hashlib
     if not os.path.exists(path):
         return None
@@ -239,7 +248,7 @@ def load_traffic(path, kernel, source_files):
         for f in source_files:
             h.update(open(os.path.join(ROOT, f), "rb").read())
         ent = d.get(kernel)
-        if not ent or ent.get("sources_sha256") != h.hexdigest():
+        if not ent or ent.get("sources_sha256") != h.hexdigest() or ent.get("tag") != tag:
             return None
         return ent.get("bytes_per_launch")
     except Exception:
@@ -321,13 +330,23 @@ def main():
         return
     rpq.load_library()
     spec = synth.WORKLOADS[args.workload]
-    queries = spec["queries"]
+    queries = spec.get("queries", [])
     if args.queries:
         queries = [q for q in args.queries.split(",") if q]
+    if not queries:
+        print("bench.py: workload %s has no default queries; pass --queries" % args.workload, file=sys.stderr)
+        sys.exit(2)
     print("bench: generating %s" % args.workload, file=sys.stderr, flush=True)
     el = synth.workload_graph(args.workload)
     g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
     info = g.info()
+    src_host = None
+    if args.sources:
+        src_host = synth.sample_sources(el.n_vertices, args.sources, spec["seed"] + 1000)
+    src_dev = torch.from_numpy(src_host.view("int32").copy()).cuda() if src_host is not None else None
+    n_src = el.n_vertices if src_host is None else int(src_host.size)
+    traffic_tag = "%s|%s|%s" % (args.workload, "all" if src_host is None else n_src, ",".join(queries))
+    traffic_file = args.traffic_file or os.path.join(ROOT, "profiles", "traffic_%s.json" % args.workload)
     stream = torch.cuda.current_stream()
     forms = {}
 
@@ -335,7 +354,7 @@ def main():
     if args.only in ("", "plain"):
         opts = dict(batch_width=args.batch_width, concurrency=args.concurrency, sync_every=args.sync_every,
                     chunk_edges=args.chunk_edges)
-        per_source = torch.zeros((el.n_vertices, 2), dtype=torch.int64, device="cuda")
+        per_source = torch.zeros((n_src, 2), dtype=torch.int64, device="cuda")
         qtimes = {q: 0.0 for q in queries}
 
         def step():
@@ -343,7 +362,7 @@ def main():
             for q in queries:
                 t = time.perf_counter()
                 nfa = rpq.rpq_nfa_compile(q, el.names)
-                out.append(rpq.rpq_eval(g, nfa, None, opts=opts, per_source=per_source))
+                out.append(rpq.rpq_eval(g, nfa, src_dev, opts=opts, per_source=per_source))
                 qtimes[q] += time.perf_counter() - t
             return out
 
@@ -387,9 +406,10 @@ def main():
             per_query=per_query,
             roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
                           frac=round(achieved / HBM_PEAK_GBPS, 5),
-                          traffic=load_traffic(args.traffic_file, "k_expand",
-                                               ["paper_2602_20748_amd/csrc/eval.hip"]),
-                          kernel="k_expand", avg_launch_ms=round(avg_ms, 5), launches=prof["expand_launches"],
+                          traffic=load_traffic(traffic_file, "k_expand",
+                                               ["paper_2602_20748_amd/csrc/eval.hip"], traffic_tag),
+                          kernel="k_expand", traffic_tag=traffic_tag,
+                          avg_launch_ms=round(avg_ms, 5), launches=prof["expand_launches"],
                           alg_bytes_per_launch=round(alg, 1),
                           finalize_avg_ms=round(prof["finalize_ms"] / max(1, prof["finalize_launches"]), 5),
                           counters={k: prof[k] for k in ("edge_items", "descriptors", "row_words", "word_reads",
@@ -401,7 +421,7 @@ def main():
     if args.only in ("", "batched"):
         b = rpq.rpq_batch_create(g)
         for q in queries:
-            b.add(rpq.rpq_nfa_compile(q, el.names), None, per_source=True)
+            b.add(rpq.rpq_nfa_compile(q, el.names), src_dev, per_source=True)
         tuned = None
         if not args.no_autotune:
             print("bench: autotuning the batch", file=sys.stderr, flush=True)
@@ -454,9 +474,9 @@ def main():
                                            phase_ms_last_step=st["phase_ms"]),
             roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
                           frac=round(achieved / HBM_PEAK_GBPS, 5),
-                          traffic=load_traffic(args.traffic_file, "k_batch",
+                          traffic=load_traffic(traffic_file, "k_batch",
                                                ["paper_2602_20748_amd/csrc/batch.hip",
-                                                "paper_2602_20748_amd/csrc/internal.h"]),
+                                                "paper_2602_20748_amd/csrc/internal.h"], traffic_tag),
                           kernel="k_batch", avg_launch_ms=round(kms, 3), launches=args.steps,
                           alg_bytes_per_launch=round(alg, 1),
                           counters={k: v // max(1, args.steps) for k, v in tally.items()}))
@@ -486,11 +506,13 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic (seeded R-MAT; no dataset)",
-        "config": {"workload": "%s: R-MAT scale 18, %d vertices, %d drawn / %d distinct edges, %d labels Zipf(1.1);"
-                               " all-pairs %s; %s form"
-                               % (args.workload, el.n_vertices, el.n_edges, info["n_edges"], el.n_labels,
+        "config": {"workload": "%s: %s, %d vertices, %d drawn / %d distinct edges, %d labels Zipf(%g);"
+                               " %s %s; %s form"
+                               % (args.workload, describe_graph(spec), el.n_vertices, el.n_edges, info["n_edges"],
+                                  el.n_labels, spec.get("zipf_s", 1.1),
+                                  "all-pairs" if src_host is None else "%d sampled sources," % n_src,
                                   ", ".join(queries), form),
-                   "sources": el.n_vertices, "queries": queries, "form": form},
+                   "sources": n_src, "queries": queries, "form": form},
         "distinct_pairs_per_s": main_form["distinct_pairs_per_s"],
         "batched_over_plain": (forms["batched"]["value"] / forms["plain"]["value"]
                                if "batched" in forms and "plain" in forms else None),
