@@ -230,10 +230,28 @@ def cpu_baseline(el, queries, budget_s):
         if dt >= budget_s / 2 or n >= el.n_vertices or n >= 8192:
             break
         n = min(el.n_vertices, n * 2)
+    # the same oracle on one thread, over the first sixteenth of the sample
+    src1 = src[: max(1, n // 16)]
+    t0 = time.perf_counter()
+    e1 = 0
+    for q in queries:
+        e1 += oracle.rpq(og, q, sources=src1, pairs=False, threads=1).product_edges
+    dt1 = time.perf_counter() - t0
     return dict(value=eprod / dt, unit="product-graph edges/s", cores=threads, kind="oracle",
-                pairs_per_s=pairs / dt,
-                sample="%d seeded sources (of %d) x %d queries, %.1f s, %d product edges" % (
-                    n, el.n_vertices, len(queries), dt, eprod))
+                pairs_per_s=pairs / dt, single_thread_value=e1 / dt1, host_cpu=host_cpu_model(),
+                host_logical_cpus=os.cpu_count(),
+                sample="%d seeded sources (of %d) x %d queries, %.1f s, %d product edges; single thread: first %d "
+                       "of them, %.1f s" % (n, el.n_vertices, len(queries), dt, eprod, src1.size, dt1))
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def load_traffic(path, kernel, source_files, tag):
