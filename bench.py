@@ -113,11 +113,27 @@ def serve_main(args):
         print("bench: serving %d requests at %s QPS" % (n, tok), file=sys.stderr, flush=True)
         srv = rpq.Server(g, int(args.serve_pool_gib * (1 << 30)), workers=args.serve_workers)
         last_note = time.time()
+
+        def wait(t):
+            # poll rather than block, so that a long wait still reports the server's state
+            nonlocal last_note
+            while True:
+                d = srv.poll(t)
+                if d["done"]:
+                    return d
+                if time.time() - last_note > 10:
+                    last_note = time.time()
+                    st = srv.stats()
+                    print("bench: waiting for request %d: completed %d, failed %d, queued %d, running %d, "
+                          "pool in use %.1f GiB" % (t, st["completed"], st["failed"], st["queued"], st["running"],
+                                                    st["pool_in_use"] / 2 ** 30), file=sys.stderr, flush=True)
+                time.sleep(0.001)
+
         t0 = srv.clock_ms() + 50.0
         tickets = []
         for i, r in enumerate(reqs):
             if i >= len(ring):   # a ring of pair buffers: the request that used this one must be done
-                srv.wait(tickets[i - len(ring)])
+                wait(tickets[i - len(ring)])
             due = t0 + arrive[i]
             while srv.clock_ms() < due:
                 time.sleep(max(0.0, min(0.002, (due - srv.clock_ms()) / 1e3)))
@@ -131,7 +147,7 @@ def serve_main(args):
                 print("bench: submitted %d / %d" % (i + 1, n), file=sys.stderr, flush=True)
         done = []
         for t in tickets:
-            done.append(srv.wait(t))
+            done.append(wait(t))
             if time.time() - last_note > 10:
                 last_note = time.time()
                 print("bench: completed %d / %d" % (len(done), n), file=sys.stderr, flush=True)
