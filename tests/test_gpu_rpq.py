@@ -216,6 +216,30 @@ def test_overflow_and_resume(rpq):
     g.close()
 
 
+def test_largest_automaton_and_label_alphabet(rpq):
+    # 64 edge labels (the most a graph may have) and queries of 31 label occurrences,
+    # i.e. 32 automaton states (the most the device tables hold); one more occurrence is refused
+    rng = np.random.default_rng(64)
+    names = ["l%d" % i for i in range(64)]
+    n, m = 300, 6000
+    src = rng.integers(0, n, size=m).astype(np.uint32)
+    dst = rng.integers(0, n, size=m).astype(np.uint32)
+    lab = rng.integers(0, 64, size=m).astype(np.uint8)
+    g = rpq.rpq_graph_create(src, lab, dst, n, 64, names=names)
+    og = oracle.OracleGraph(n, src, lab, dst, 64, names)
+    union31 = "(" + "|".join(names[:31]) + ")*"
+    chain31 = "(%s).(%s)*.(%s)" % ("|".join(names[33:43]), "|".join(names[43:53]), "|".join(names[53:64]))
+    for regex in (union31, chain31, "(" + "|".join(names[32:63]) + ")+"):
+        say("case: 32-state query %s..." % regex[:40])
+        assert rpq.rpq_nfa_compile(regex, names).n_states == 32
+        for sources in (None, synth.sample_sources(n, 77, seed=5)):
+            check_against_oracle(rpq, g, og, regex, sources=sources)
+    with pytest.raises(rpq.RpqError) as ei:
+        rpq.rpq_nfa_compile("(" + "|".join(names[:32]) + ")*", names)
+    assert ei.value.code == rpq.RPQ_EUNSUPPORTED
+    g.close()
+
+
 def test_invalid_inputs(rpq):
     import torch
     el = synth.workload_graph("uniform_v1000_e5000_l4")
