@@ -301,8 +301,19 @@ struct SArgs {
     uint64_t* pairs;
     uint64_t pair_cap;
     unsigned long long* ctr;     // [0] next frontier length, [1] pairs, [2] error flags, [3] product edges
+    uint64_t ins_limit;          // new entries this launch may add before the table counts as full
     uint32_t V;
 };
+
+// Flags in ctr[2]: an insert ran out of probes, or the table passed its load limit.  Either one
+// ends the run (the host retries with a larger table), so the waves of the launch stop early
+// instead of probing an overfull table.
+constexpr unsigned long long kFlagProbe = 1, kFlagFull = 2;
+
+__device__ __forceinline__ bool run_over(const SArgs& a) {
+    const unsigned long long f = __hip_atomic_load(&a.ctr[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __ballot(f != 0) != 0;
+}
 
 // true if key was not in the set (and is now)
 __device__ __forceinline__ bool set_insert(const SArgs& a, uint64_t key) {
@@ -317,7 +328,7 @@ __device__ __forceinline__ bool set_insert(const SArgs& a, uint64_t key) {
         }
         h = (h + 1) & a.mask;
     }
-    atomicOr(&a.ctr[2], 1ull);
+    atomicOr(&a.ctr[2], kFlagProbe);
     return false;
 }
 
@@ -334,6 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_sparse_seed(SArgs a) {
             const bool ins = ok && set_insert(a, key);
             const uint64_t pos = wave_append(ins, &a.ctr[0]);
             if (ins && pos < a.front_cap) a.front_out[pos] = key;
+            if (ins && pos >= a.ins_limit) atomicOr(&a.ctr[2], kFlagFull);
             const bool emit = ins && ((fin >> q) & 1) && (!a.target || bit_of(a.target, s));
             const uint64_t pp = wave_append(emit, &a.ctr[1]);
             if (emit && pp < a.pair_cap) a.pairs[pp] = ((uint64_t)s << 32) | s;
@@ -351,6 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_sparse_level(SArgs a) {
     const int lane = __lane_id();
     const uint32_t V = a.V;
     for (uint64_t b = gwave_base(); b < a.n_in; b += gstride()) {
+        if (run_over(a)) return;
         const uint64_t e = b + lane;
         uint64_t key = 0, m = 0, deg = 0, eprod = 0;
         uint32_t q = 0, v = 0;
@@ -376,6 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_sparse_level(SArgs a) {
         const uint64_t excl = incl - deg;
         const uint64_t total = __shfl(incl, 63, 64);
         for (uint64_t base = 0; base < total; base += 64) {
+            if (base && run_over(a)) return;
             const uint64_t item = base + lane;
             const int c = wave_owner(excl, item);
             const uint64_t ckey = __shfl(key, c, 64);
@@ -412,6 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_sparse_level(SArgs a) {
                 }
                 const uint64_t pos = wave_append(ins, &a.ctr[0]);
                 if (ins && pos < a.front_cap) a.front_out[pos] = (si << 32) | ((uint64_t)q2 * V + w);
+                if (ins && pos >= a.ins_limit) atomicOr(&a.ctr[2], kFlagFull);
                 const bool emit = ins && ((fin >> q2) & 1) && (!a.target || bit_of(a.target, w));
                 const uint64_t pp = wave_append(emit, &a.ctr[1]);
                 if (emit && pp < a.pair_cap) a.pairs[pp] = ((uint64_t)a.srcs[si] << 32) | w;
@@ -872,6 +887,7 @@ int sparse_run(Ctx& c, const rpq_nfa& nfa, const rpq::Csr& csr, const uint32_t* 
     a.pairs = pairs;
     a.pair_cap = T / 2;
     a.ctr = c.dctr;
+    a.ins_limit = T / 2;
     a.V = c.g->V;
     hipLaunchKernelGGL(k_sparse_seed, dim3(grid_for(n_src, 16384)), dim3(kBlock), 0, c.s, a);
     RPQ_LAUNCH_CHECK();
@@ -892,6 +908,7 @@ int sparse_run(Ctx& c, const rpq_nfa& nfa, const rpq::Csr& csr, const uint32_t* 
         a.front_in = cur;
         a.n_in = n_front;
         a.front_out = nxt;
+        a.ins_limit = T / 2 - inserted;   // inserted <= T / 2 here, or the loop would have ended
         hipLaunchKernelGGL(k_sparse_level, dim3(grid_for(n_front, 16384)), dim3(kBlock), 0, c.s, a);
         RPQ_LAUNCH_CHECK();
         RPQ_TRY(read_counters(c, 3));
@@ -916,8 +933,10 @@ int sparse_run(Ctx& c, const rpq_nfa& nfa, const rpq::Csr& csr, const uint32_t* 
     return RPQ_OK;
 }
 
+// t_cap: largest table to try (0 = no limit); past it the search returns RPQ_EOVERFLOW without
+// setting an error, and the caller evaluates the atom bit-parallel instead.
 int eval_sparse(Ctx& c, const rpq_nfa& nfa_fwd, bool reverse, const uint32_t* srcs, uint64_t n_src,
-                const uint64_t* target, uint64_t** keys, uint64_t* n) {
+                const uint64_t* target, uint64_t t_cap, uint64_t** keys, uint64_t* n) {
     rpq_nfa nfa;
     if (reverse) RPQ_TRY(rpq_nfa_reverse(&nfa_fwd, &nfa));
     else nfa = nfa_fwd;
@@ -927,7 +946,9 @@ int eval_sparse(Ctx& c, const rpq_nfa& nfa_fwd, bool reverse, const uint32_t* sr
     constexpr uint64_t kSlack = 1ull << 16;
     uint64_t T = 1ull << 16;
     while (T < 16 * n_src * (uint64_t)nfa.n_states && T < (1ull << 34)) T *= 2;
+    if (t_cap) t_cap = std::max(t_cap, T);
     for (;;) {
+        if (t_cap && T > t_cap) return RPQ_EOVERFLOW;
         if (T * 20 + kSlack > c.ar.free_bytes()) {
             c.ar.need = std::max<uint64_t>(c.ar.need, c.ar.top + T * 20 + kSlack + (1ull << 20));
             rpq::set_error("workspace exhausted (sparse search with %llu slots)", (unsigned long long)T);
@@ -1304,7 +1325,21 @@ int crpq_eval(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, const crp
                 RPQ_TRY(eval_dense(c, at.nfa, reverse, srcs, n_src, dom[dv], &keys, &nk));
                 sorted = true;
             } else {
-                RPQ_TRY(eval_sparse(c, at.nfa, reverse, srcs, n_src, dom[dv], &keys, &nk));
+                // Chosen by source count alone, the hash-set search is capped at about V/256 entries
+                // per source (a table of 2 * n_src * V / 256 slots): past that the atom's sources reach
+                // enough of the graph for the bit-parallel search to be cheaper, and it takes over.
+                const uint64_t cap = (flags & CRPQ_FORCE_SPARSE)
+                                         ? 0
+                                         : std::max<uint64_t>(1ull << 20, 2 * n_src * std::max<uint64_t>(1, g->V / 256));
+                const int rc = eval_sparse(c, at.nfa, reverse, srcs, n_src, dom[dv], cap, &keys, &nk);
+                if (rc == RPQ_EOVERFLOW) {
+                    strategy = CRPQ_STRATEGY_DENSE;
+                    res->atom_strategy[pick] = strategy | (reverse ? CRPQ_STRATEGY_REVERSED : 0u);
+                    RPQ_TRY(eval_dense(c, at.nfa, reverse, srcs, n_src, dom[dv], &keys, &nk));
+                    sorted = true;
+                } else {
+                    RPQ_TRY(rc);
+                }
             }
             if (nk >= 0xFFFFFFFFull) {
                 rpq::set_error("atom %d has %llu pairs; at most 2^32 - 2 are supported", pick, (unsigned long long)nk);

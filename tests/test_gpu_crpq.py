@@ -151,6 +151,31 @@ def test_workspace_grows_on_demand(rpq):
     g.close()
 
 
+def test_hash_set_search_over_many_sources_hands_over_to_bit_parallel(rpq):
+    # 150 directed a-cycles of 500 vertices: from every vertex, a* reaches its whole cycle.  x ranges
+    # over 70,000 vertices, more than the bit-parallel search takes by source count, so the hash-set
+    # search is tried first; at 500 reached vertices per source (above V/256) it passes its table cap
+    # and the atom is evaluated bit-parallel instead.  Closed form: each source pairs with its cycle.
+    n_cyc, L = 150, 500
+    V = n_cyc * L
+    v = np.arange(V, dtype=np.uint32)
+    nxt = ((v // L) * L + (v % L + 1) % L).astype(np.uint32)
+    g = rpq.rpq_graph_create(v, np.zeros(V, np.uint8), nxt, V, 1, names=["a"])
+    dom = synth.sample_sources(V, 70000, seed=11)
+    say("case: a* over 70,000 of 75,000 cycle vertices, auto / forced hash set / forced bit-parallel")
+    auto = rpq.crpq_eval(g, [(0, "a*", 1)], 2, domain=[dom, None])
+    assert auto.atom_strategy[0] == rpq.CRPQ_STRATEGY_DENSE
+    forced = rpq.crpq_eval(g, [(0, "a*", 1)], 2, domain=[dom, None], flags=rpq.CRPQ_FORCE_SPARSE)
+    assert forced.atom_strategy[0] == rpq.CRPQ_STRATEGY_SPARSE
+    dense = rpq.crpq_eval(g, [(0, "a*", 1)], 2, domain=[dom, None], flags=rpq.CRPQ_FORCE_DENSE)
+    xs = np.repeat(dom.astype(np.int64), L)
+    ys = (((dom.astype(np.int64) // L) * L)[:, None] + np.arange(L)[None, :]).ravel()
+    want = (xs.size, chain_hash(np.stack([xs, ys], axis=1)))
+    for r in (auto, forced, dense):
+        assert (r.count, r.hash) == want
+    g.close()
+
+
 def test_invalid_queries(rpq):
     el = synth.workload_graph("uniform_v1000_e5000_l4")
     g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
