@@ -1092,7 +1092,8 @@ int co_resident_blocks(unsigned* out) {
     }
     // up to four 256-thread blocks per CU: enough waves in flight for the level phases
     // while the grid barrier stays cheap
-    *out = (unsigned)(std::min(per_cu, 4) * n_cu);
+    *out = (unsigned)std::min<uint64_t>((uint64_t)std::min(per_cu, 4) * n_cu,
+                                        (uint64_t)rpqd::kBarMaxGroups * rpqd::kBarGroup);
     return RPQ_OK;
 }
 

@@ -200,17 +200,28 @@ __device__ __forceinline__ void decode_item(const uint32_t* __restrict__ row_ptr
 }  // namespace rpqd
 
 // ---- grid-wide barrier for persistent kernels (device) ----
-// Sense-reversing barrier over all workgroups of a co-resident grid.  Waits are
-// bounded by the 100 MHz constant clock: after `timeout_ticks` a waiting
-// workgroup raises *abort and every workgroup returns from the barrier with
-// false, so a grid that is not fully resident can never hang the device.
+// Two-level barrier over all workgroups of a co-resident grid.  Workgroups arrive in groups of
+// kBarGroup on counters of their own (one 128-byte line each), and only the last arrival of a
+// group goes on to the top-level counter, so no counter takes more than kBarGroup atomics per
+// barrier where a flat barrier would serialise one per workgroup.  The counters only grow:
+// barrier number g (from 0) completes when a group counter reaches (g + 1) * its group size and
+// the top counter (g + 1) * the number of groups; the generation word counts completed barriers
+// and is what waiters watch.  Waits are bounded by the 100 MHz constant clock: after
+// `timeout_ticks` a waiting workgroup raises abort and every workgroup returns from the barrier
+// with false, so a grid that is not fully resident can never hang the device.  All counters start
+// at zero (the host clears the block before each launch).
 namespace rpqd {
 
+constexpr unsigned int kBarGroup = 32;       // workgroups per arrival group
+constexpr unsigned int kBarMaxGroups = 64;   // so at most 2,048 workgroups
+constexpr unsigned int kBarLine = 32;        // words per 128-byte line
+
 struct GridSync {
-    unsigned int count;
-    unsigned int generation;
+    unsigned int count;        // group completions, summed over barriers
+    unsigned int generation;   // completed barriers
     unsigned int abort;
-    unsigned int pad;
+    unsigned int pad[kBarLine - 3];
+    unsigned int group[kBarMaxGroups * kBarLine];   // arrivals of group i at group[i * kBarLine]
 };
 
 __device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned int n_blocks, uint64_t timeout_ticks) {
@@ -224,10 +235,19 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned int n_blocks
         int ok = 1;
         const unsigned int gen = __hip_atomic_load(&gs->generation, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();   // release (also keeps the generation read before the arrival)
-        const unsigned int arrived =
-            __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == n_blocks - 1) {
-            __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int grp = blockIdx.x / kBarGroup;
+        const unsigned int in_grp = min(kBarGroup, n_blocks - grp * kBarGroup);
+        const unsigned int n_grp = (n_blocks + kBarGroup - 1) / kBarGroup;
+        bool last = false;
+        const unsigned int a_grp =
+            __hip_atomic_fetch_add(&gs->group[grp * kBarLine], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (a_grp == (gen + 1) * in_grp) {
+            // the group is complete: its last arrival carries it to the top level
+            const unsigned int a_top =
+                __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+            last = a_top == (gen + 1) * n_grp;
+        }
+        if (last) {
             __hip_atomic_store(&gs->generation, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const uint64_t t0 = wall_clock64();
