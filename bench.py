@@ -57,6 +57,8 @@ def parse_args():
     ap.add_argument("--sync-every", type=int, default=0)
     ap.add_argument("--chunk-edges", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="batched form: keep the default plan")
+    ap.add_argument("--batched-plan", default="",
+                    help="batched form: WIDTH:CHUNK, a fixed plan instead of the autotuner's (profiling runs)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline leg (0 disables it)")
     ap.add_argument("--traffic-file", default="",
@@ -453,13 +455,18 @@ def main():
     g.release_workspace()
     torch.cuda.empty_cache()
     if args.only in ("", "batched"):
-        b = rpq.rpq_batch_create(g)
+        plan_opts = None
+        if args.batched_plan:
+            w_, h_ = (int(x) for x in args.batched_plan.split(":"))
+            plan_opts = dict(batch_width=w_, chunk_edges=h_)
+        b = rpq.rpq_batch_create(g, opts=plan_opts)
         for q in queries:
             b.add(rpq.rpq_nfa_compile(q, el.names), src_dev, per_source=True)
         tuned = None
-        if not args.no_autotune:
+        if not args.no_autotune and plan_opts is None:
             print("bench: autotuning the batch", file=sys.stderr, flush=True)
             tuned = b.autotune()
+        plan_chunk = (tuned or {}).get("chunk_edges") or (plan_opts or {}).get("chunk_edges") or 16
         for i in range(args.warmup):
             print("bench: batched warmup %d" % i, file=sys.stderr, flush=True)
             b.run()
@@ -510,7 +517,9 @@ def main():
                           frac=round(achieved / HBM_PEAK_GBPS, 5),
                           traffic=load_traffic(traffic_file, "k_batch",
                                                ["paper_2602_20748_amd/csrc/batch.hip",
-                                                "paper_2602_20748_amd/csrc/internal.h"], traffic_tag),
+                                                "paper_2602_20748_amd/csrc/internal.h"],
+                                               "%s|plan=%d:%d" % (traffic_tag, st["batch_width"], plan_chunk)),
+                          traffic_tag="%s|plan=%d:%d" % (traffic_tag, st["batch_width"], plan_chunk),
                           kernel="k_batch", avg_launch_ms=round(kms, 3), launches=args.steps,
                           alg_bytes_per_launch=round(alg, 1),
                           counters={k: v // max(1, args.steps) for k, v in tally.items()}))
