@@ -4,8 +4,9 @@
 // The queries are cut into units (a query's sources, at most W per unit; a
 // single-source query is one unit).  G slots each own a unit's bitmaps, sized
 // for the largest automaton of the batch: Vis/Next [Qmax][V][K] words, a
-// touch bitmap, Ans [V][K] and a one-bit-per-vertex summary of non-empty Ans
-// rows.  The persistent kernel repeats
+// touch bitmap, a bitmap of the rows the unit has visited, Ans [V][K] and a
+// one-bit-per-vertex summary of non-empty Ans rows.  The persistent kernel
+// repeats
 //
 //   expand -> compact -> decide -> (retire) -> refill/seed -> finalize
 //
@@ -104,6 +105,7 @@ struct BArgs {
     uint64_t* vis;
     uint64_t* next;
     uint64_t* touch;
+    uint64_t* ever;          // [G][slot_stride bits]: row touched at some level of the slot's unit
     uint64_t* ans;
     uint64_t* summ;          // [G][V/64 rounded up]: bit v set when Ans row v is non-empty
     uint32_t* ids0;
@@ -305,10 +307,40 @@ __device__ void phase_compact(const BArgs& a, int p, uint32_t iter) {
     for (uint64_t w0 = gwave(a) * 64; w0 < n_words; w0 += gwaves(a) * 64) {
         const uint64_t wi = w0 + lane;
         uint64_t tw = wi < n_words ? xld(a.touch + wi) : 0;
+        const uint32_t slot = (uint32_t)(wi / words_per_slot);
+        uint64_t first = 0;   // rows touched for the first time in their unit
         if (tw) {
             a.touch[wi] = 0;
-            const uint32_t slot = (uint32_t)(wi / words_per_slot);
             if (ld32(&a.slots[slot].alive) != iter) st32(&a.slots[slot].alive, iter);
+            const uint64_t ev = xld(a.ever + wi);
+            first = tw & ~ev;
+            if (first) a.ever[wi] = ev | tw;
+        }
+        // first-visit log (the rows whose Vis the slot's retirement clears).  A wave's words
+        // usually lie in one slot: then one counter update serves the wave
+        const uint32_t fc = (uint32_t)__popcll(first);
+        const uint64_t fmask = __ballot(fc != 0);
+        if (fmask) {
+            const uint32_t s0 = __shfl(slot, __ffsll((long long)fmask) - 1, 64);
+            unsigned long long li = 0;
+            if (__ballot(fc != 0 && slot != s0) == 0) {
+                const uint32_t fincl = rpqd::wave_incl_scan_u32(fc);
+                const uint32_t ftot = __shfl(fincl, 63, 64);
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(&a.slots[s0].log_n, (unsigned long long)ftot);
+                base = __shfl(base, 0, 64);
+                li = base + fincl - fc;
+            } else if (fc) {
+                li = atomicAdd(&a.slots[slot].log_n, (unsigned long long)fc);
+            }
+            const uint64_t lbase = (wi - (uint64_t)slot * words_per_slot) * 64;
+            uint32_t* log = a.logs + (uint64_t)slot * a.slot_stride;
+            while (first) {
+                const int bt = __ffsll((long long)first) - 1;
+                first &= first - 1;
+                if (li < a.slot_stride) log[li] = (uint32_t)(lbase + bt);
+                ++li;
+            }
         }
         const uint32_t c = (uint32_t)__popcll(tw);
         const uint32_t incl = rpqd::wave_incl_scan_u32(c);
@@ -481,9 +513,12 @@ __device__ void phase_retire_prefix(const BArgs& a, uint32_t n_ret) {
 template <int K>
 __device__ void phase_retire_clear(const BArgs& a, uint32_t n_ret) {
     const int lane = threadIdx.x & 63;
-    // Vis rows from the per-slot log
+    // Vis rows from the per-slot log, and the slot's first-visit bits
     for (uint32_t r = 0; r < n_ret; ++r) {
         const uint32_t slot = ld32(&a.retiring[r]);
+        const uint64_t wps = a.slot_stride / 64;
+        for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < wps; i += (uint64_t)a.n_blocks * kBlock)
+            a.ever[(uint64_t)slot * wps + i] = 0;
         const uint64_t n = min((uint64_t)ld(&a.slots[slot].log_n), a.slot_stride);
         const uint32_t* log = a.logs + (uint64_t)slot * a.slot_stride;
         for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)a.n_blocks * kBlock) {
@@ -585,22 +620,30 @@ __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
                 init &= init - 1;
                 row = (uint64_t)slot * a.slot_stride + (uint64_t)q * a.V + s;
                 or_relaxed(&a.next[row * K + (j >> 6)], 1ull << (j & 63));
+                or_relaxed(&a.ever[row >> 6], 1ull << (row & 63));
             }
             const uint64_t m = __ballot(take);
-            unsigned long long base = 0;
+            unsigned long long base = 0, lbase = 0;
             if (lane == 0) base = atomicAdd(&a.ctl->list_cnt[np], (unsigned long long)__popcll(m));
+            // a seeded row is new to its unit: it opens the slot's first-visit log (W is a multiple
+            // of 64, so the wave's positions lie in one slot)
+            if (lane == 0 && m) lbase = atomicAdd(&a.slots[i0 / a.W].log_n, (unsigned long long)__popcll(m));
             base = __shfl(base, 0, 64);
+            lbase = __shfl(lbase, 0, 64);
             const unsigned long long pos = base + __popcll(m & rpqd::lanemask_lt());
+            const unsigned long long li = lbase + __popcll(m & rpqd::lanemask_lt());
             if (take) {
                 if (pos < a.list_cap) ids[pos] = (uint32_t)row;
                 else atomicOr(&a.ctl->err, 1ull);
+                if (li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = (uint32_t)(row - (uint64_t)slot * a.slot_stride);
             }
         }
     }
 }
 
 // ------------------------------------------------------------------------------------------------
-// finalize: list p^1 -> frontier rows, Vis (with first-visit log), Ans (+ summary), slices of heavy entries.
+// finalize: list p^1 -> frontier rows, Vis, Ans (+ summary), slices of heavy entries.  First visits are
+// logged earlier, by the compaction (and the seeding) that put the rows on the list.
 // Word phase: groups of K lanes per row; row phase: lane per row (as in the plain form).
 // ------------------------------------------------------------------------------------------------
 template <int K>
@@ -611,7 +654,6 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
     if (n == 0) return;
     const int lane = threadIdx.x & 63;
     const int grp = lane / K, k = lane % K;
-    const uint64_t gmask = (K == 64) ? ~0ull : (((1ull << K) - 1) << (grp * K));
     const uint32_t* ids = np ? a.ids1 : a.ids0;
     uint64_t* rows = np ? a.rows1 : a.rows0;
     Desc* dout = np ? a.desc1 : a.desc0;
@@ -636,18 +678,16 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
             if ((nfa->final >> q) & 1) my_ans = slot * V + v;
         }
         const uint32_t n_here = (uint32_t)min<uint64_t>(64, n - e0);
-        uint32_t my_info = 0;   // new source bits of this lane's row | 1 << 31 if Vis was non-empty
+        uint32_t my_pc = 0;   // new source bits of this lane's row
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
             uint32_t r[kUnroll], an[kUnroll];
-            uint64_t nk[kUnroll], vk[kUnroll];
+            uint64_t nk[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t idx = j + u * GS + grp;
                 r[u] = __shfl(row32, idx & 63, 64);
                 an[u] = __shfl(my_ans, idx & 63, 64);
-                const bool ok = idx < n_here;
-                nk[u] = ok ? xld(a.next + (uint64_t)r[u] * K + k) : 0;
-                vk[u] = ok ? xld(a.vis + (uint64_t)r[u] * K + k) : 0;
+                nk[u] = idx < n_here ? xld(a.next + (uint64_t)r[u] * K + k) : 0;
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -657,7 +697,7 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
                     rows[(e0 + idx) * K + k] = nk[u];
                     if (nk[u]) {
                         a.next[(uint64_t)r[u] * K + k] = 0;
-                        a.vis[(uint64_t)r[u] * K + k] = vk[u] | nk[u];
+                        or_relaxed(a.vis + (uint64_t)r[u] * K + k, nk[u]);
                         pc = (uint32_t)__popcll(nk[u]);
                         ++t_fwords;
                         if (an[u] != 0xFFFFFFFFu) or_relaxed(a.ans + (uint64_t)an[u] * K + k, nk[u]);
@@ -665,31 +705,13 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
                 }
 #pragma unroll
                 for (int o = K / 2; o >= 1; o >>= 1) pc += __shfl_xor(pc, o, 64);
-                const uint32_t info = pc | ((__ballot(vk[u] != 0) & gmask) ? 0x80000000u : 0u);
                 const uint32_t rel = (uint32_t)lane - (j + u * GS);
-                const uint32_t got = __shfl(info, (rel % GS) * K, 64);
-                if (rel < (uint32_t)GS) my_info = got;
-            }
-        }
-        // first-visit log: rows whose Vis was empty and that gained bits.  The list is slot-major, so
-        // the appending lanes of a wave usually share a slot: then one counter update serves the wave
-        const bool first = active && !(my_info >> 31) && (my_info & 0x7FFFFFFFu);
-        const uint64_t fmask = __ballot(first);
-        if (fmask) {
-            const uint32_t s0 = __shfl(slot, __ffsll((long long)fmask) - 1, 64);
-            if (__ballot(first && slot != s0) == 0) {
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(&a.slots[s0].log_n, (unsigned long long)__popcll(fmask));
-                base = __shfl(base, 0, 64);
-                const unsigned long long li = base + __popcll(fmask & rpqd::lanemask_lt());
-                if (first && li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = lrow;
-            } else if (first) {
-                const unsigned long long li = atomicAdd(&a.slots[slot].log_n, 1ull);
-                if (li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = lrow;
+                const uint32_t got = __shfl(pc, (rel % GS) * K, 64);
+                if (rel < (uint32_t)GS) my_pc = got;
             }
         }
         if (active) {
-            const uint32_t pc = my_info & 0x7FFFFFFFu;
+            const uint32_t pc = my_pc;
             ++t_frows;
             if (my_ans != 0xFFFFFFFFu && pc)
                 or_relaxed(&a.summ[(uint64_t)slot * a.summ_words + v / 64], 1ull << (v & 63));
@@ -862,7 +884,8 @@ struct HostQuery {
 struct Layout {
     uint32_t K, W, G, Qmax, H, nchunks, n_units;
     uint64_t slot_stride, summ_words, list_cap, desc_cap, stage_keys;
-    uint64_t off_ctl, off_nfas, off_queries, off_qout, off_units, off_slots, off_vis, off_next, off_touch, off_ans,
+    uint64_t off_ctl, off_nfas, off_queries, off_qout, off_units, off_slots, off_vis, off_next, off_touch, off_ever,
+        off_ans,
         off_summ, off_ids[2], off_rows[2], off_desc[2], off_logs, off_retiring, off_partial, off_srcbase, off_stage,
         off_utotal, off_ustart, off_uprefix, off_scan_tmp, total;
 };
@@ -955,9 +978,9 @@ int plan(rpq_batch* b) {
            2 * (2 * (uint64_t)x.Qmax * max_succ * g->E / x.H + 2) * sizeof(Desc) > bitmap_bytes / 4)
         x.H *= 2;
     const uint64_t desc_per_slot = 2 * (uint64_t)x.Qmax * max_succ * g->E / x.H + 2;
-    // per slot: Vis + Next, touch bits, Ans, summary, first-visit log, and its share of the two
-    // frontier lists (row id + K-word row per entry) and of the two slice buffers
-    const uint64_t per_slot = x.slot_stride * x.K * 8 * 2 + x.slot_stride / 8 + (uint64_t)g->V * x.K * 8 +
+    // per slot: Vis + Next, touch and first-visit bits, Ans, summary, first-visit log, and its share
+    // of the two frontier lists (row id + K-word row per entry) and of the two slice buffers
+    const uint64_t per_slot = x.slot_stride * x.K * 8 * 2 + x.slot_stride / 4 + (uint64_t)g->V * x.K * 8 +
                               x.summ_words * 8 + x.slot_stride * 4 + 2 * x.slot_stride * (4 + x.K * 8) +
                               2 * desc_per_slot * sizeof(Desc);
     uint64_t G = b->opts.slots;
@@ -995,6 +1018,7 @@ int plan(rpq_batch* b) {
     x.off_vis = take(G * x.slot_stride * x.K * 8);
     x.off_next = take(G * x.slot_stride * x.K * 8);
     x.off_touch = take(G * x.slot_stride / 8);
+    x.off_ever = take(G * x.slot_stride / 8);
     x.off_ans = take(G * (uint64_t)g->V * x.K * 8);
     x.off_summ = take(G * x.summ_words * 8);
     for (int p = 0; p < 2; ++p) {
@@ -1034,6 +1058,7 @@ BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
     a.vis = reinterpret_cast<uint64_t*>(ws + x.off_vis);
     a.next = reinterpret_cast<uint64_t*>(ws + x.off_next);
     a.touch = reinterpret_cast<uint64_t*>(ws + x.off_touch);
+    a.ever = reinterpret_cast<uint64_t*>(ws + x.off_ever);
     a.ans = reinterpret_cast<uint64_t*>(ws + x.off_ans);
     a.summ = reinterpret_cast<uint64_t*>(ws + x.off_summ);
     a.ids0 = reinterpret_cast<uint32_t*>(ws + x.off_ids[0]);
@@ -1110,6 +1135,7 @@ int enqueue_run(rpq_batch* b, char* ws, hipStream_t s) {
     RPQ_TRY(rpq::fill_u64(a.vis, (uint64_t)x.G * x.slot_stride * x.K, 0, s));
     RPQ_TRY(rpq::fill_u64(a.next, (uint64_t)x.G * x.slot_stride * x.K, 0, s));
     RPQ_TRY(rpq::fill_u64(a.touch, (uint64_t)x.G * x.slot_stride / 64, 0, s));
+    RPQ_TRY(rpq::fill_u64(a.ever, (uint64_t)x.G * x.slot_stride / 64, 0, s));
     RPQ_TRY(rpq::fill_u64(a.ans, (uint64_t)x.G * b->g->V * x.K, 0, s));
     RPQ_TRY(rpq::fill_u64(a.summ, (uint64_t)x.G * x.summ_words, 0, s));
     RPQ_TRY(rpq::fill_u64(a.unit_total, std::max<uint32_t>(1, x.n_units), 0, s));
