@@ -497,12 +497,12 @@ def main():
         K = st["row_words"]
         # dominant kernel of the batched form: the persistent kernel (one launch per step).
         # Algorithmic bytes = expansion (as in the plain form) + finalize (per row: 4 B id,
-        # 8K B next read, 8K B visited read, 8K B frontier-row write, 12 B label mask and slot;
-        # per non-zero word: 16 B next clear + visited write; 16 B per descriptor written)
+        # 8K B next read, 8K B frontier-row write, 12 B label mask and slot; per non-zero word:
+        # 8 B next clear + 16 B visited OR; 16 B per descriptor written)
         # + compaction (8 B per touch word scanned per iteration, 4 B per row id).
         exp = (4 * tally["edge_items"] + 16 * tally["descriptors"] + 8 * K * tally["descriptors"]
                + 16 * tally["word_reads"] + 8 * tally["word_updates"])
-        fin = tally["finalized_rows"] * (4 + 24 * K + 12) + 16 * tally["finalized_words"] + 16 * tally["descriptors"]
+        fin = tally["finalized_rows"] * (4 + 16 * K + 12) + 24 * tally["finalized_words"] + 16 * tally["descriptors"]
         cmp_ = 8 * tally["iterations"] * st["touch_words"] + 4 * tally["finalized_rows"]
         alg = (exp + fin + cmp_) / max(1, args.steps)
         kms = kernel_ms / max(1, args.steps)
