@@ -600,8 +600,8 @@ __global__ __launch_bounds__(1024) void k_group_finish(unsigned long long* __res
 struct Layout {
     uint32_t K, W, G, Q, L, V, H, nchunks, chunk_v, sync_every;
     uint64_t list_cap, desc_cap;
-    uint64_t off_counters, off_nfa, off_vis, off_next, off_touch, off_ans, off_ids[2], off_rows[2], off_desc[2],
-        off_acc, off_partial, off_srcbase, total;
+    uint64_t off_counters, off_nfa, off_vis, off_next, off_touch, off_ans, off_ans2, off_ids[2], off_rows[2],
+        off_desc[2], off_acc, off_partial, off_srcbase, total;
 };
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -738,6 +738,9 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     x.off_next = take(G * bitmap_bytes);
     x.off_touch = take((G * QV + 63) / 64 * 8);
     x.off_ans = take(G * (uint64_t)x.V * x.K * 8);
+    // a second Ans bitmap when there is more than one group: a group's extraction then runs on a
+    // second stream while the next group's levels fill the other bitmap
+    x.off_ans2 = units > G ? take(G * (uint64_t)x.V * x.K * 8) : x.off_ans;
     for (int p = 0; p < 2; ++p) {
         x.off_ids[p] = take(x.list_cap * 4);
         x.off_rows[p] = take(x.list_cap * x.K * 8);
@@ -898,6 +901,48 @@ int launch_finalize(const Args& a, int p, uint64_t n_rows, uint32_t level, hipSt
     RPQ_LAUNCH_CHECK();
     return RPQ_OK;
 }
+
+// A second stream for extraction (one per host thread and device, created on first use and kept
+// for the thread's lifetime) and the events that order its work against the caller's stream.  The
+// destructor drains the side stream, so no work of a call outlives it on any return path.  Without
+// a side stream (creation failed) everything runs on the caller's stream, in the same order.
+struct SideStream {
+    static constexpr int kMaxDevices = 64;
+    hipStream_t stream = nullptr;
+    hipEvent_t leveled = nullptr;
+    hipEvent_t extracted[2] = {nullptr, nullptr};
+
+    explicit SideStream(bool want) {
+        if (!want) return;
+        static thread_local hipStream_t per_device[kMaxDevices] = {};
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
+        if (!per_device[dev] && hipStreamCreateWithFlags(&per_device[dev], hipStreamNonBlocking) != hipSuccess) {
+            per_device[dev] = nullptr;
+            return;
+        }
+        if (hipEventCreateWithFlags(&leveled, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&extracted[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&extracted[1], hipEventDisableTiming) != hipSuccess) {
+            destroy_events();
+            return;
+        }
+        stream = per_device[dev];
+    }
+    ~SideStream() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        destroy_events();
+    }
+    void destroy_events() {
+        if (leveled) (void)hipEventDestroy(leveled);
+        for (hipEvent_t& e : extracted)
+            if (e) (void)hipEventDestroy(e);
+        leveled = nullptr;
+        extracted[0] = extracted[1] = nullptr;
+    }
+    SideStream(const SideStream&) = delete;
+    SideStream& operator=(const SideStream&) = delete;
+};
 
 template <int K>
 int launch_extract(const Args& a, bool write, const uint32_t* sources, uint64_t n_sources, uint64_t group_base,
@@ -1066,13 +1111,24 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     uint32_t* partial = want_pairs ? reinterpret_cast<uint32_t*>(ws + x.off_partial) : nullptr;
     uint64_t* srcbase = want_pairs ? reinterpret_cast<uint64_t*>(ws + x.off_srcbase) : nullptr;
     uint64_t levels_total = 0, max_depth = 0;
+    // Extraction of group g runs on a second stream (xs) while the levels of group g + 1 run on
+    // `stream` into the other Ans bitmap: the level kernels are bound by memory, extraction by its
+    // instruction stream.  Events order each bitmap's reuse and the final join.
+    uint64_t* const ans_buf[2] = {reinterpret_cast<uint64_t*>(ws + x.off_ans),
+                                  reinterpret_cast<uint64_t*>(ws + x.off_ans2)};
+    const bool overlap = n_groups > 1 && x.off_ans2 != x.off_ans;
+    SideStream side(overlap);
+    hipStream_t xs = side.stream ? side.stream : stream;
     for (uint64_t grp = 0; grp < n_groups; ++grp) {
         const uint64_t gbase = grp * per_group;
         const uint64_t n_here = std::min<uint64_t>(per_group, n_sources - gbase);
         const uint32_t G_eff = (uint32_t)((n_here + x.W - 1) / x.W);
+        const int buf = side.stream ? (int)(grp & 1) : 0;
+        a.ans = ans_buf[buf];
+        // the bitmap's previous group must be extracted before it is cleared for this one
+        if (side.stream && grp >= 2) RPQ_HIP(hipStreamWaitEvent(stream, side.extracted[buf], 0));
         RPQ_TRY(rpq::fill_u64(a.vis, (uint64_t)G_eff * x.Q * x.V * x.K, 0, stream));
         RPQ_TRY(rpq::fill_u64(a.ans, (uint64_t)G_eff * x.V * x.K, 0, stream));
-        RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(acc), (uint64_t)G_eff * x.W * 2, 0, stream));
         hipLaunchKernelGGL(k_seed, dim3((unsigned)(((uint64_t)G_eff * x.W + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                            stream, a, sources, n_sources, gbase, G_eff, x.W, x.K);
         RPQ_LAUNCH_CHECK();
@@ -1108,17 +1164,28 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
         const uint64_t lv = stage[C_LASTLEVEL];   // levels with a non-empty frontier, seeds included
         levels_total += lv;
         if (lv > 0 && lv - 1 > max_depth) max_depth = lv - 1;
+        if (side.stream) {
+            RPQ_HIP(hipEventRecord(side.leveled, stream));
+            RPQ_HIP(hipStreamWaitEvent(xs, side.leveled, 0));
+        }
+        RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(acc), (uint64_t)G_eff * x.W * 2, 0, xs));
         RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_extract<KK>(a, false, sources, n_sources, gbase, G_eff, x.W, x.nchunks,
-                                                       x.chunk_v, acc, partial, nullptr, nullptr, 0, 0, stream)));
-        hipLaunchKernelGGL(k_group_finish, dim3(1), dim3(1024), 0, stream, a.counters, acc, partial, srcbase,
+                                                       x.chunk_v, acc, partial, nullptr, nullptr, 0, 0, xs)));
+        hipLaunchKernelGGL(k_group_finish, dim3(1), dim3(1024), 0, xs, a.counters, acc, partial, srcbase,
                            (flags & RPQ_PER_SOURCE) ? res->per_source : nullptr, n_sources, gbase,
                            (uint64_t)G_eff * x.W, x.nchunks);
         RPQ_LAUNCH_CHECK();
         if (want_pairs) {
             RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_extract<KK>(a, true, sources, n_sources, gbase, G_eff, x.W, x.nchunks,
                                                            x.chunk_v, acc, partial, srcbase, res->pairs,
-                                                           res->pair_offset, res->capacity, stream)));
+                                                           res->pair_offset, res->capacity, xs)));
         }
+        if (side.stream) RPQ_HIP(hipEventRecord(side.extracted[buf], xs));
+    }
+    if (side.stream) {
+        // join: everything the side stream did happens before the totals are read on `stream`
+        RPQ_HIP(hipEventRecord(side.leveled, xs));
+        RPQ_HIP(hipStreamWaitEvent(stream, side.leveled, 0));
     }
     RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
     RPQ_HIP(hipStreamSynchronize(stream));
