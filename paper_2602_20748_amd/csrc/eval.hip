@@ -477,7 +477,16 @@ __global__ void k_check_sources(const uint32_t* __restrict__ s, uint64_t n, uint
 // ------------------------------------------------------------------------------------------------
 // extraction
 // ------------------------------------------------------------------------------------------------
-// One wave per (slot, word k, vertex chunk); lane i owns source 64k+i of the slot.
+// Answer words each lane loads per 64-vertex group: four adjacent words (two 16-byte loads) where K
+// allows.  Neighbouring lanes read rows one row (K words) apart, so every lane makes its own memory
+// request; loading four words per request instead of one cuts the requests per byte fourfold,
+// which is what bounds this kernel when most answer words are zero.
+template <int K>
+constexpr int kExtractWords() { return K >= 4 ? 4 : (K >= 2 ? 2 : 1); }
+
+// One wave per (slot, block of kExtractWords consecutive words, vertex chunk); for word k of the
+// block, lane i owns source 64k + i of the slot and walks the non-zero vertex words in ascending
+// vertex order.
 template <int K, bool WRITE>
 __global__ __launch_bounds__(kBlock) void k_extract(Args a, const uint32_t* __restrict__ sources,
                                                     uint64_t n_sources, uint64_t group_base, uint32_t G,
@@ -487,50 +496,83 @@ __global__ __launch_bounds__(kBlock) void k_extract(Args a, const uint32_t* __re
                                                     const uint64_t* __restrict__ srcbase,
                                                     uint64_t* __restrict__ pairs, uint64_t pair_off,
                                                     uint64_t capacity) {
+    constexpr int KP = kExtractWords<K>();
+    constexpr int NKP = K / KP;
     const int lane = threadIdx.x & 63;
     const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
-    const uint64_t total = (uint64_t)G * K * nchunks;
+    const uint64_t total = (uint64_t)G * NKP * nchunks;
     const uint32_t V = a.V;
     for (uint64_t wv = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); wv < total; wv += n_waves) {
         const uint32_t chunk = (uint32_t)(wv % nchunks);
-        const uint32_t k = (uint32_t)((wv / nchunks) % K);
-        const uint32_t slot = (uint32_t)(wv / ((uint64_t)nchunks * K));
-        const uint32_t j = k * 64 + lane;
-        const uint64_t si = (uint64_t)slot * W + j;
-        const uint64_t gi = group_base + si;
-        const bool valid = gi < n_sources;
-        const uint64_t s = valid ? (sources ? sources[gi] : gi) : 0;
+        const uint32_t kp = (uint32_t)((wv / nchunks) % NKP);
+        const uint32_t slot = (uint32_t)(wv / ((uint64_t)nchunks * NKP));
         const uint32_t vbeg = chunk * chunk_v;
         const uint32_t vend = min(V, vbeg + chunk_v);
-        uint64_t cnt = 0, h = 0;
-        uint64_t cursor = 0;
-        if (WRITE && valid) cursor = srcbase[si] + partial[si * nchunks + chunk];
+        bool valid[KP];
+        uint64_t skey[KP], cnt[KP], h[KP], cursor[KP];
+#pragma unroll
+        for (int u = 0; u < KP; ++u) {
+            const uint64_t si = (uint64_t)slot * W + (uint64_t)(kp * KP + u) * 64 + lane;
+            const uint64_t gi = group_base + si;
+            valid[u] = gi < n_sources;
+            skey[u] = (valid[u] ? (sources ? (uint64_t)sources[gi] : gi) : 0) << 32;
+            cnt[u] = h[u] = cursor[u] = 0;
+            if (WRITE && valid[u]) cursor[u] = srcbase[si] + partial[si * nchunks + chunk];
+        }
         for (uint32_t v0 = vbeg; v0 < vend; v0 += 64) {
             const uint32_t vv = v0 + lane;
-            uint64_t word = vv < vend ? a.ans[((uint64_t)slot * V + vv) * K + k] : 0;
-            if (a.target && word && !((a.target[vv >> 6] >> (vv & 63)) & 1)) word = 0;
-            uint64_t any = __ballot(word != 0);
-            while (any) {
-                const int jj = __ffsll((long long)any) - 1;
-                any &= any - 1;
-                const uint64_t wj = __shfl(word, jj, 64);
-                if (valid && ((wj >> lane) & 1)) {
-                    const uint64_t key = (s << 32) | (uint64_t)(v0 + jj);
-                    if (WRITE) {
-                        if (cursor >= pair_off && cursor - pair_off < capacity) pairs[cursor - pair_off] = key;
-                        ++cursor;
-                    } else {
-                        ++cnt;
-                        h += rpqd::mix64(key);
+            uint64_t word[KP];
+            if (vv < vend) {
+                const uint64_t* p = a.ans + ((uint64_t)slot * V + vv) * K + (uint64_t)kp * KP;
+                if constexpr (KP >= 2) {
+#pragma unroll
+                    for (int u = 0; u < KP; u += 2) {
+                        const ulonglong2 w2 = *reinterpret_cast<const ulonglong2*>(p + u);
+                        word[u] = w2.x;
+                        word[u + 1] = w2.y;
+                    }
+                } else {
+                    word[0] = p[0];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < KP; ++u) word[u] = 0;
+            }
+            if (a.target && vv < vend && !((a.target[vv >> 6] >> (vv & 63)) & 1)) {
+#pragma unroll
+                for (int u = 0; u < KP; ++u) word[u] = 0;
+            }
+#pragma unroll
+            for (int u = 0; u < KP; ++u) {
+                uint64_t any = __ballot(word[u] != 0);
+                while (any) {
+                    const int jj = __ffsll((long long)any) - 1;
+                    any &= any - 1;
+                    const uint64_t wj = __shfl(word[u], jj, 64);
+                    if (valid[u] && ((wj >> lane) & 1)) {
+                        const uint64_t key = skey[u] | (uint64_t)(v0 + jj);
+                        if (WRITE) {
+                            if (cursor[u] >= pair_off && cursor[u] - pair_off < capacity)
+                                pairs[cursor[u] - pair_off] = key;
+                            ++cursor[u];
+                        } else {
+                            ++cnt[u];
+                            h[u] += rpqd::mix64(key);
+                        }
                     }
                 }
             }
         }
-        if (!WRITE && valid) {
-            if (partial) partial[si * nchunks + chunk] = (uint32_t)cnt;
-            if (cnt) {
-                atomicAdd(&acc[2 * si], (unsigned long long)cnt);
-                atomicAdd(&acc[2 * si + 1], (unsigned long long)h);
+        if (!WRITE) {
+#pragma unroll
+            for (int u = 0; u < KP; ++u) {
+                if (!valid[u]) continue;
+                const uint64_t si = (uint64_t)slot * W + (uint64_t)(kp * KP + u) * 64 + lane;
+                if (partial) partial[si * nchunks + chunk] = (uint32_t)cnt[u];
+                if (cnt[u]) {
+                    atomicAdd(&acc[2 * si], (unsigned long long)cnt[u]);
+                    atomicAdd(&acc[2 * si + 1], (unsigned long long)h[u]);
+                }
             }
         }
     }
@@ -949,7 +991,7 @@ int launch_extract(const Args& a, bool write, const uint32_t* sources, uint64_t 
                    uint32_t G, uint32_t W, uint32_t nchunks, uint32_t chunk_v, unsigned long long* acc,
                    uint32_t* partial, const uint64_t* srcbase, uint64_t* pairs, uint64_t off, uint64_t cap,
                    hipStream_t s) {
-    const uint64_t waves = (uint64_t)G * K * nchunks;
+    const uint64_t waves = (uint64_t)G * (K / kExtractWords<K>()) * nchunks;
     const unsigned grid = (unsigned)std::min<uint64_t>((waves + kWaves - 1) / kWaves, 16384);
     if (write)
         hipLaunchKernelGGL((k_extract<K, true>), dim3(grid), dim3(kBlock), 0, s, a, sources, n_sources, group_base, G,
