@@ -21,8 +21,8 @@ def gpu_available():
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests fail loudly on a GPU machine whose library is missing; on a box
-    # without a GPU they are skipped so that the CPU suite stays runnable.
+    # GPU tests fail loudly on a machine with a GPU whose library is missing; on a
+    # machine without a GPU they are skipped so that the CPU suite stays runnable.
     if gpu_available():
         return
     skip = pytest.mark.skip(reason="no GPU visible")
