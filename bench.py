@@ -73,6 +73,8 @@ def parse_args():
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-mixes", action="store_true",
                     help="skip the batched-vs-plain comparison on many-query mixes")
+    ap.add_argument("--crpq", action="store_true",
+                    help="time the two CRPQs on the full typed social graph (1M persons, 10M messages, 16,384 tags)")
     ap.add_argument("--serve", action="store_true",
                     help="serving measurement instead of the throughput step: Poisson streams of mixed "
                          "requests at each --qps rate (prints one JSON line of its own)")
@@ -85,6 +87,56 @@ def parse_args():
     ap.add_argument("--serve-max-requests", type=int, default=4000,
                     help="serving: cap on requests per rate (keeps the FIFO comparison bounded)")
     return ap.parse_args()
+
+
+def crpq_main():
+    """The information-propagation CRPQ (m -hasTag-> t, m -hasCreator-> u, m -replyOf*-> p, t the most
+    frequent tag) and the 3-cycle of knows.knows* over seeded person samples, on the full typed social
+    graph; wall time of one call after a warm-up call, graph resident."""
+    import numpy as np
+    import torch
+
+    import paper_2602_20748_amd as rpq
+    import synth
+
+    print("bench: generating the social graph", file=sys.stderr, flush=True)
+    el = synth.workload_graph("social_p1m_m10m_t16k")
+    t = time.perf_counter()
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, vertex_label=el.vertex_label,
+                             flags=rpq.RPQ_BUILD_IN_CSR, names=el.names)
+    torch.cuda.synchronize()
+    ingest_ms = (time.perf_counter() - t) * 1e3
+    n_person, n_msg = 1_000_000, 10_000_000
+    q1 = [(0, "hasTag", 1), (0, "hasCreator", 2), (0, "replyOf*", 3)]
+    kw = dict(binding=[None, n_person + n_msg, None, None], vertex_label=[1, 2, 0, 1])
+    cyc = [(0, "knows.knows*", 1), (1, "knows.knows*", 2), (2, "knows.knows*", 0)]
+    rng = np.random.default_rng(4004)
+    s128 = np.sort(rng.choice(n_person, size=128, replace=False)).astype(np.uint32)
+    s1024 = np.sort(rng.choice(n_person, size=1024, replace=False)).astype(np.uint32)
+    cases = [("information propagation, count + checksum", lambda: rpq.crpq_eval(g, q1, 4, **kw)),
+             ("information propagation, sorted tuples",
+              lambda: rpq.crpq_eval(g, q1, 4, tuples=True, capacity=1 << 24, **kw)),
+             ("3-cycle of knows.knows*, 128 persons, sorted tuples",
+              lambda: rpq.crpq_eval(g, cyc, 3, domain=[s128] * 3, vertex_label=[0] * 3, tuples=True)),
+             ("3-cycle of knows.knows*, 1,024 persons, count + checksum",
+              lambda: rpq.crpq_eval(g, cyc, 3, domain=[s1024] * 3, vertex_label=[0] * 3))]
+    out = []
+    for name, f in cases:
+        print("bench: crpq %s" % name, file=sys.stderr, flush=True)
+        f()   # warm-up: sizes the workspace
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        out.append(dict(case=name, ms=round((time.perf_counter() - t) * 1e3, 2), count=r.count,
+                        hash="%016x" % r.hash, atom_strategies=r.atom_strategy, atom_pairs=r.atom_pairs,
+                        join_rows=r.join_rows))
+    print(json.dumps({"metric": "CRPQ wall time (typed social graph)", "value": out[0]["ms"], "unit": "ms",
+                      "n_gpus": 1, "higher_is_better": False, "dtype": "u32", "data": "synthetic (seeded)",
+                      "config": {"workload": "social_p1m_m10m_t16k: %d vertices, %d distinct edges" % (
+                          el.n_vertices, g.info()["n_edges"])},
+                      "ingest_ms": round(ingest_ms, 1), "cases": out}), flush=True)
+    g.close()
 
 
 def serve_main(args):
@@ -363,6 +415,10 @@ def main():
     if args.serve:
         rpq.load_library()
         serve_main(args)
+        return
+    if args.crpq:
+        rpq.load_library()
+        crpq_main()
         return
     rpq.load_library()
     spec = synth.WORKLOADS[args.workload]
