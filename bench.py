@@ -20,7 +20,7 @@ where batching is meant to pay (256 single-source queries; 128 single-source
 
 Metric: product-graph edges per second (per source, the product edges
 examined, counted on the Glushkov automaton), with distinct pairs per second.
-Prints one JSON line.  --gpus > 1 is not supported by this single-GPU build.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
 --serve measures serving latency instead (its own JSON line).
 """
 from __future__ import annotations
@@ -397,7 +397,7 @@ def mixes(g, el, seed):
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (one MI355X); --gpus %d is not supported"
+        print("bench.py: the benchmark runs on exactly one GPU (one MI355X); --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

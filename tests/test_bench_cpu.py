@@ -1,0 +1,43 @@
+"""CPU checks of bench.py's host logic: the single-GPU guard and the rule that measured HBM
+traffic is reported only for the kernel source and workload it was measured on."""
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=300)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_traffic_only_for_the_measured_source_and_workload(tmp_path):
+    src = tmp_path / "kernel.hip"
+    src.write_bytes(b"kernel source v1")
+    sha = hashlib.sha256(b"kernel source v1").hexdigest()
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"k_x": {"sources_sha256": sha, "tag": "wl|all|a*", "bytes_per_launch": 1234}}))
+    rel = os.path.relpath(str(src), bench.ROOT)
+    assert bench.load_traffic(str(f), "k_x", [rel], "wl|all|a*") == 1234
+    assert bench.load_traffic(str(f), "k_x", [rel], "wl|64|a*") is None        # another workload
+    assert bench.load_traffic(str(f), "k_y", [rel], "wl|all|a*") is None       # another kernel
+    assert bench.load_traffic(str(tmp_path / "none.json"), "k_x", [rel], "wl|all|a*") is None
+    src.write_bytes(b"kernel source v2")                                       # the kernel changed
+    assert bench.load_traffic(str(f), "k_x", [rel], "wl|all|a*") is None
+
+
+def test_committed_traffic_files_name_their_workload():
+    pdir = os.path.join(ROOT, "profiles")
+    for name in os.listdir(pdir):
+        if name.startswith("traffic_") and name.endswith(".json"):
+            d = json.load(open(os.path.join(pdir, name)))
+            for kernel, ent in d.items():
+                assert ent["tag"].startswith(name[len("traffic_"):-len(".json")] + "|"), (name, kernel)
+                assert len(ent["sources_sha256"]) == 64 and ent["bytes_per_launch"] > 0
