@@ -21,7 +21,10 @@ where batching is meant to pay (256 single-source queries; 128 single-source
 Metric: product-graph edges per second (per source, the product edges
 examined, counted on the Glushkov automaton), with distinct pairs per second.
 Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
---serve measures serving latency instead (its own JSON line).
+--workload / --sources / --queries pick another graph, a seeded source sample and other queries
+(e.g. R-MAT scale 23 from 65,536 sources); --batched-plan WIDTH:CHUNK fixes the batched plan for
+profiling runs.  --serve measures serving latency instead, and --crpq times the CRPQs on the
+full typed social graph (each its own JSON line).
 """
 from __future__ import annotations
 
