@@ -236,7 +236,10 @@ int rpq_eval_workspace_size(rpq_graph_t g, const rpq_nfa* nfa, uint64_t n_source
  *   aligned, owned by the caller; its contents on entry do not matter.
  * Sources are processed in units of batch_width sources, concurrency units at a
  * time; every unit runs its level-synchronous search to the fixpoint (no hop
- * bound).  Synchronises the stream before returning.
+ * bound).  Synchronises the stream before returning.  When the sources take more
+ * than one group of units, each group's extraction runs on a second stream the
+ * library keeps per host thread (created on first use), ordered against `stream`
+ * by events; all of it is complete when the call returns.
  * Errors: RPQ_EINVAL, RPQ_ENOMEM (workspace too small), RPQ_EOVERFLOW,
  * RPQ_EUNSUPPORTED (RPQ_REVERSE on a graph without in-CSR), RPQ_EDEVICE.
  */
