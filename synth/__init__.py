@@ -92,6 +92,19 @@ def uniform_graph(n_vertices: int, n_edges: int, n_labels: int, seed: int) -> Ed
     return EdgeList(n_vertices, n_labels, src, lab, dst, label_names(n_labels))
 
 
+def _threads() -> int:
+    import os
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _pcg64_at(state: dict, draws: int) -> np.random.Generator:
+    """A generator whose PCG64 stream starts `draws` 64-bit outputs after `state`."""
+    bg = np.random.PCG64()
+    bg.state = state
+    bg.advance(draws)
+    return np.random.Generator(bg)
+
+
 def rmat_graph(scale: int, edge_factor: int = 16, probs: Sequence[float] = (0.57, 0.19, 0.19, 0.05),
                n_labels: int = 8, zipf_s: float = 1.1, seed: int = 0,
                chunk: int = 1 << 22) -> EdgeList:
@@ -103,34 +116,61 @@ def rmat_graph(scale: int, edge_factor: int = 16, probs: Sequence[float] = (0.57
     and d.  Vertex ids are then relabelled by a seeded random permutation (as
     Graph500 does) so that id order carries no locality.  Labels are drawn
     Zipf(zipf_s) with label 0 the most frequent.  Duplicates are kept.
+
+    The draws form one PCG64 stream of ``default_rng(seed)``: for each chunk of
+    edges, one uniform double per edge and level (level-major within the
+    chunk), then the permutation, then one uniform per edge for its label.
+    Chunks are drawn on several threads, each from its own generator advanced
+    to the chunk's position in that stream, so the bytes do not depend on the
+    thread count.
     """
+    from concurrent.futures import ThreadPoolExecutor
     rng = np.random.default_rng(seed)
+    state0 = rng.bit_generator.state
     n = 1 << scale
     m = edge_factor * n
     cum = np.cumsum(np.asarray(probs, dtype=np.float64))
     cum[-1] = 1.0
+    # quadrant = number of cumulative bounds <= u: c or d (>= 2) sets the source bit, b or d
+    # (1 or 3) the destination bit
+    c0, c1, c2 = cum[0], cum[1], cum[2]
     src = np.empty(m, dtype=np.uint32)
     dst = np.empty(m, dtype=np.uint32)
-    for lo in range(0, m, chunk):
+
+    def draw_chunk(lo: int) -> None:
         hi = min(m, lo + chunk)
+        g = _pcg64_at(state0, lo * scale)
+        u = np.empty(hi - lo, dtype=np.float64)
         s = np.zeros(hi - lo, dtype=np.uint32)
         d = np.zeros(hi - lo, dtype=np.uint32)
         for level in range(scale):
-            u = rng.random(hi - lo)
-            quad = np.searchsorted(cum, u, side="right")
-            bit = np.uint32(1 << (scale - 1 - level))
-            s |= np.where(quad >= 2, bit, np.uint32(0)).astype(np.uint32)
-            d |= np.where((quad == 1) | (quad == 3), bit, np.uint32(0)).astype(np.uint32)
+            g.random(out=u)
+            shift = np.uint32(scale - 1 - level)
+            sbit = u >= c1
+            s |= sbit.astype(np.uint32) << shift
+            d |= (((u >= c0) & ~sbit) | (u >= c2)).astype(np.uint32) << shift
         src[lo:hi] = s
         dst[lo:hi] = d
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(draw_chunk, range(0, m, chunk)))
+    rng = _pcg64_at(state0, m * scale)
     perm = rng.permutation(n).astype(np.uint32)
     src = perm[src]
     dst = perm[dst]
     lab = np.empty(m, dtype=np.uint8)
-    p = zipf_probs(n_labels, zipf_s)
-    for lo in range(0, m, chunk):
+    cdf = np.cumsum(zipf_probs(n_labels, zipf_s))
+    cdf /= cdf[-1]
+    state1 = rng.bit_generator.state
+
+    def draw_labels(lo: int) -> None:
+        # one uniform per edge, mapped through the Zipf CDF (what Generator.choice does with p=)
         hi = min(m, lo + chunk)
-        lab[lo:hi] = rng.choice(n_labels, size=hi - lo, p=p).astype(np.uint8)
+        u = _pcg64_at(state1, lo).random(hi - lo)
+        lab[lo:hi] = np.searchsorted(cdf, u, side="right").astype(np.uint8)
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(draw_labels, range(0, m, chunk)))
     return EdgeList(n, n_labels, src, lab, dst, label_names(n_labels))
 
 
