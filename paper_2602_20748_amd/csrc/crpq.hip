@@ -1130,11 +1130,10 @@ int sparse_eval(rpq_graph_t g, const rpq_nfa* nfa_in, const uint32_t* sources, u
 
 }  // namespace rpq
 
-extern "C" {
+namespace {
 
-int crpq_eval(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, const crpq_vars* vars, uint32_t flags,
-              void* workspace, uint64_t workspace_bytes, crpq_result* res, hipStream_t stream) {
-    rpq::clear_error();
+int crpq_eval_body(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, const crpq_vars* vars, uint32_t flags,
+                   void* workspace, uint64_t workspace_bytes, crpq_result* res, hipStream_t stream) {
     if (!g || !res || !vars || (n_atoms && !atoms)) {
         rpq::set_error("graph, result, vars and atoms must not be NULL");
         return RPQ_EINVAL;
@@ -1602,6 +1601,21 @@ int crpq_eval(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, const crp
     if (want_tuples && n_free == 0) res->written = std::min<uint64_t>(res->count, res->capacity);
     return RPQ_OK;
 #undef CRPQ_STEP
+}
+
+}  // namespace
+
+extern "C" {
+
+int crpq_eval(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, const crpq_vars* vars, uint32_t flags,
+              void* workspace, uint64_t workspace_bytes, crpq_result* res, hipStream_t stream) {
+    rpq::clear_error();
+    const int rc = crpq_eval_body(g, atoms, n_atoms, vars, flags, workspace, workspace_bytes, res, stream);
+    // a failing call may leave kernels of its own queued on the stream (an intermediate that did
+    // not fit is found after earlier steps were launched): drain them, so that the caller may reuse
+    // or release the workspace as soon as the call returns
+    if (rc != RPQ_OK) (void)hipStreamSynchronize(stream);
+    return rc;
 }
 
 }  // extern "C"

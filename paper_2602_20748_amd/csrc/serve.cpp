@@ -219,6 +219,9 @@ void worker_main(rpq_server* s) {
         lk.unlock();
         uint64_t needed = 0;
         int rc = have_stream ? run_job(s, j, s->pool + off, stream, &needed) : RPQ_EDEVICE;
+        // nothing of this request may still run on its workspace once the segment goes back to the
+        // pool (the calls drain their stream on every return; this keeps the rule local too)
+        if (have_stream) (void)hipStreamSynchronize(stream);
         const double end = s->now_ms();
         lk.lock();
         s->alloc->release(off, std::max<uint64_t>(j->need, kAlign));
