@@ -153,7 +153,7 @@ def test_rmat18_sampled_sources(rpq, rmat18, regex):
     check_against_oracle(rpq, g, og, regex, sources=src)
 
 
-@pytest.mark.parametrize("regex", ["a.b*.c", "(a.b)*", "a*"])
+@pytest.mark.parametrize("regex", ["a*", "a.b*", "(a|b).c*", "a.b*.c", "(a.b)*"])
 def test_rmat18_all_pairs_per_source_at_samples(rpq, rmat18, regex):
     import torch
     el, g, og = rmat18
