@@ -72,7 +72,8 @@ def _load():
             lib.oracle_rpq_eval.restype = ctypes.c_int
             lib.oracle_rpq_eval.argtypes = [ctypes.c_uint32, _u64p, _u32p, _u32p, ctypes.c_uint32,
                                             ctypes.c_uint32, _u8p, _u32p, _u32p, _u32p, _u8p, _u32p,
-                                            ctypes.c_uint64, _u64p, ctypes.c_uint64, _u64p, _u64p]
+                                            ctypes.c_uint64, _u64p, ctypes.c_uint64, _u64p, _u64p,
+                                            ctypes.c_uint64]
             _lib = lib
     return _lib
 
@@ -163,7 +164,11 @@ def _flatten(nfa: EpsNFA):
             np.ascontiguousarray(cl.reshape(-1)), fin)
 
 
-def _run(g: OracleGraph, flat, start, S, sources: np.ndarray, want_pairs: bool, cap: int):
+_UNBOUNDED = 0xFFFFFFFFFFFFFFFF
+
+
+def _run(g: OracleGraph, flat, start, S, sources: np.ndarray, want_pairs: bool, cap: int,
+         max_len: int = _UNBOUNDED):
     t_off, t_lab, t_to, cl, fin = flat
     n = sources.shape[0]
     per = np.zeros((max(n, 1), 2), dtype=np.uint64)
@@ -173,18 +178,23 @@ def _run(g: OracleGraph, flat, start, S, sources: np.ndarray, want_pairs: bool, 
         g.n_vertices, _ptr(g.off, _u64p), _ptr(g.lab, _u32p), _ptr(g.dst, _u32p), S, start,
         _ptr(fin, _u8p), _ptr(t_off, _u32p), _ptr(t_lab, _u32p), _ptr(t_to, _u32p), _ptr(cl, _u8p),
         _ptr(sources, _u32p), n, _ptr(pairs, _u64p) if want_pairs else None, cap if want_pairs else 0,
-        _ptr(per, _u64p), _ptr(totals, _u64p))
+        _ptr(per, _u64p), _ptr(totals, _u64p), max_len)
     if rc != 0:
         raise MemoryError("oracle ran out of memory")
     return pairs, per[:n], totals
 
 
 def rpq(g: OracleGraph, regex, sources=None, automaton: str = "glushkov", pairs: bool = True,
-        threads: int = 1, max_pairs: int = 1 << 26) -> OracleResult:
+        threads: int = 1, max_pairs: int = 1 << 26, max_length: Optional[int] = None) -> OracleResult:
     """Evaluate one RPQ from the given sources (default: every vertex).
 
     Sources must be distinct; results are emitted in the given source order
-    (ascending keys when sources are ascending)."""
+    (ascending keys when sources are ascending).  max_length = k keeps only
+    walks of at most k edges (a length-bounded RPQ, the extension named in the
+    paper's conclusion); None means walks of any length (Definition 1)."""
+    ml = _UNBOUNDED if max_length is None else int(max_length)
+    if ml < 0:
+        raise ValueError("max_length must be >= 0")
     nfa = regex if isinstance(regex, EpsNFA) else compile_automaton(regex, g.names, automaton)
     flat = _flatten(nfa)
     if sources is None:
@@ -198,13 +208,13 @@ def rpq(g: OracleGraph, regex, sources=None, automaton: str = "glushkov", pairs:
 
     def job(chunk):
         if not pairs:
-            return _run(g, flat, nfa.start, nfa.n_states, chunk, False, 0)
+            return _run(g, flat, nfa.start, nfa.n_states, chunk, False, 0, ml)
         # first pass sizes the pair buffer exactly
-        _, per, _t = _run(g, flat, nfa.start, nfa.n_states, chunk, False, 0)
+        _, per, _t = _run(g, flat, nfa.start, nfa.n_states, chunk, False, 0, ml)
         need = int(per[:, 0].sum()) if chunk.size else 0
         if need > max_pairs:
             raise MemoryError("oracle result larger than max_pairs")
-        return _run(g, flat, nfa.start, nfa.n_states, chunk, True, need)
+        return _run(g, flat, nfa.start, nfa.n_states, chunk, True, need, ml)
 
     if threads == 1:
         outs = [job(chunks[0])]

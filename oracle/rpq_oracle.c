@@ -13,15 +13,24 @@
  * graph and the automaton, one visited set of (vertex, state) pairs per
  * source; a pair (s, y) is recorded whenever a final state is reached at y.
  * A zero-length walk counts: if the closure of the start state holds a final
- * state, (s, s) is in the result.  Walks, not simple paths; no hop bound.
+ * state, (s, s) is in the result.  Walks, not simple paths; no hop bound
+ * unless one is asked for.
+ *
+ * Length-bounded RPQs (the extension the paper's conclusion names: a length
+ * constraint enforced by controlling the traversal depth): with max_len = k
+ * only walks of at most k edges count.  The search is breadth-first, so a
+ * product pair first reached at depth d has a walk of exactly d edges and none
+ * shorter; pairs at depth k are recorded but not expanded.
  *
  * Result keys are (s << 32) | y, emitted per source in ascending y.  The
  * checksum of a key is one SplitMix64 output (Steele, Lea, Flood, OOPSLA
  * 2014) for state = key; sums are taken modulo 2^64.
  *
- * Product edges examined: for each dequeued (v, q), each labelled transition
- * (q, l, p) and each edge (v, l, w) counts one.  On an epsilon-free automaton
- * this is the sum over reached (v, q) of sum_l deg_l(v) * |delta(q, l)|.
+ * Product edges examined: for each dequeued (v, q) that is expanded, each
+ * labelled transition (q, l, p) and each edge (v, l, w) counts one.  On an
+ * epsilon-free automaton this is the sum over expanded (v, q) of
+ * sum_l deg_l(v) * |delta(q, l)| (every reached pair is expanded unless a
+ * length bound stops it).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -122,6 +131,7 @@ static int vpush(vec64* v, uint64_t x)
  *                            capacity are counted but not written
  *   per_source[2*i+0/1]      count and checksum of source i
  *   totals[0..4)             count, checksum, product edges, max hops
+ * max_len: the longest walk (in edges) that counts; UINT64_MAX for none.
  * Returns 0, or -1 when memory runs out.
  */
 int oracle_rpq_eval(uint32_t n_vertices, const uint64_t* g_off, const uint32_t* g_lab,
@@ -129,7 +139,7 @@ int oracle_rpq_eval(uint32_t n_vertices, const uint64_t* g_off, const uint32_t* 
                     const uint8_t* is_final, const uint32_t* t_off, const uint32_t* t_label,
                     const uint32_t* t_to, const uint8_t* eps_closure, const uint32_t* sources,
                     uint64_t n_sources, uint64_t* pairs, uint64_t pairs_cap,
-                    uint64_t* per_source, uint64_t* totals)
+                    uint64_t* per_source, uint64_t* totals, uint64_t max_len)
 {
     const uint64_t S = n_states;
     uint8_t* seen = (uint8_t*)calloc((size_t)n_vertices * S, 1);
@@ -154,6 +164,7 @@ int oracle_rpq_eval(uint32_t n_vertices, const uint64_t* g_off, const uint32_t* 
             if (head == level_end) { ++hops; level_end = queue.n; }
             const uint64_t pv = queue.a[head++];
             const uint32_t v = (uint32_t)(pv / S), q = (uint32_t)(pv % S);
+            if (hops >= max_len) continue;   /* its walks already have max_len edges */
             for (uint32_t t = t_off[q]; t < t_off[q + 1]; ++t) {
                 const uint32_t l = t_label[t], p = t_to[t];
                 uint64_t e = label_lower(g_lab, g_off[v], g_off[v + 1], l);

@@ -68,6 +68,10 @@ MUTANTS = [
     ("hop count off by one",
      [(C, "uint64_t head = 0, level_end = queue.n, hops = 0;",
        "uint64_t head = 0, level_end = queue.n, hops = 1;")]),
+    ("length bound off by one",
+     [(C, "if (hops >= max_len) continue;", "if (hops > max_len) continue;")]),
+    ("length bound ignored",
+     [(C, "if (hops >= max_len) continue;", "")]),
     ("duplicate edges kept",
      [(C, "if (i > b && key[i] == key[i - 1]) continue;", "")]),
     ("adjacency stores the source as the target",

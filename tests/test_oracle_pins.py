@@ -264,16 +264,17 @@ def test_composition_and_union_laws():
 # brute force on tiny graphs: every walk, Python's re as the acceptor
 # ------------------------------------------------------------------------------------------------
 
-def brute_force(n, edges, text, n_states):
+def brute_force(n, edges, text, n_states, max_len=None):
     """All walks of length <= n * n_states - 1 (a shortest accepting product
-    walk never repeats a (vertex, state) pair), label words tested with
-    re.fullmatch after mapping labels to letters."""
+    walk never repeats a (vertex, state) pair), or of length <= max_len when
+    given, label words tested with re.fullmatch after mapping labels to
+    letters."""
     pat = re.compile(text.replace(".", ""))
     out = set()
     by_src = {}
     for (s, l, d) in edges:
         by_src.setdefault(s, []).append((l, d))
-    bound = n * n_states - 1
+    bound = n * n_states - 1 if max_len is None else max_len
     for s in range(n):
         frontier = {(s, "")}
         seen_all = set(frontier)
@@ -541,3 +542,121 @@ def test_crpq_matches_bruteforce_tiny():
         got = crpq(g, atoms, k, binding=binding, var_label=var_label, neq=neq)
         want = crpq_bruteforce(g, atoms, k, binding=binding, var_label=var_label, neq=neq)
         assert got == want, (atoms, binding, var_label, neq)
+
+
+# ------------------------------------------------------------------------------------------------
+# length-bounded RPQs: only walks of at most k edges count (the extension the paper's conclusion
+# names, enforced by the traversal depth)
+# ------------------------------------------------------------------------------------------------
+
+def test_length_bound_brute_force_tiny_graphs():
+    rng = np.random.default_rng(2025)
+    checked = 0
+    while checked < 120:
+        n = int(rng.integers(1, 5))
+        m = int(rng.integers(0, 8))
+        L = int(rng.integers(1, 4))
+        src, lab, dst = random_graph(rng, n, m, L)
+        tree = random_tree(rng, L, max_depth=3)
+        q = leaf_count(tree) + 1
+        if q > 4:
+            continue
+        edges = set(zip(src.tolist(), lab.tolist(), dst.tolist()))
+        text = to_text(tree, NAMES[:L])
+        g = OracleGraph(n, src, lab, dst, L, NAMES[:L])
+        k = int(rng.integers(0, 6))
+        want = brute_force(n, edges, text, q, max_len=k)
+        for automaton in ("glushkov", "thompson"):
+            r = rpq(g, text, automaton=automaton, max_length=k)
+            assert rel_of(r) == want, (text, k)
+            assert r.max_hops <= k
+        checked += 1
+
+
+def bounded_union_of_powers(M, lo, hi):
+    """Union of the Boolean powers M^lo .. M^hi (empty when hi < lo)."""
+    n = M.shape[0]
+    Mi = M.astype(np.int64)
+    P = np.eye(n, dtype=np.int64)
+    for _ in range(lo):
+        P = ((P @ Mi) > 0).astype(np.int64)
+    out = np.zeros((n, n), dtype=bool)
+    for _ in range(lo, hi + 1):
+        out |= P > 0
+        P = ((P @ Mi) > 0).astype(np.int64)
+    return out
+
+
+def compose(A, B):
+    return (A.astype(np.int64) @ B.astype(np.int64)) > 0
+
+
+def test_length_bound_closed_forms_by_matrix_powers():
+    # R_k(a*) = A^0 | ... | A^k; R_k(a.b*) = A . (B^0 | ... | B^(k-1));
+    # R_k((a.b)*) = union of (AB)^j for 2j <= k; R_k(a.b*.c) = A . (B^0 | ... | B^(k-2)) . C
+    rng = np.random.default_rng(43)
+    for trial in range(20):
+        n = int(rng.integers(1, 30))
+        src, lab, dst = random_graph(rng, n, 3 * n, 3)
+        g = OracleGraph(n, src, lab, dst, 3, ["a", "b", "c"])
+        A, B, C = label_mats(n, 3, zip(src.tolist(), lab.tolist(), dst.tolist()))
+        AB = compose(A, B)
+        for k in range(0, 7):
+            forms = {
+                "a*": bounded_union_of_powers(A, 0, k),
+                "a.b*": compose(A, bounded_union_of_powers(B, 0, k - 1)),
+                "(a.b)*": bounded_union_of_powers(AB, 0, k // 2),
+                "a.b*.c": compose(compose(A, bounded_union_of_powers(B, 0, k - 2)), C),
+            }
+            for q, M in forms.items():
+                assert rel_of(rpq(g, q, max_length=k)) == mat_to_set(M), (trial, q, k)
+
+
+def test_length_bound_product_edges_closed_form_for_a_star():
+    # Glushkov a*: (s, 0) at depth 0 and (w, 1) at w's first-reach distance d >= 1; a pair is
+    # expanded (its a-edges examined) only when its depth is below k
+    rng = np.random.default_rng(47)
+    for trial in range(12):
+        n = int(rng.integers(1, 40))
+        src, lab, dst = random_graph(rng, n, 2 * n, 1)
+        g = OracleGraph(n, src, lab, dst, 1, ["a"])
+        A = label_mats(n, 1, zip(src.tolist(), lab.tolist(), dst.tolist()))[0]
+        deg = A.sum(axis=1).astype(np.int64)
+        # dist[s, w] = first d >= 1 with w in A^d(s), from Boolean powers
+        dist = np.full((n, n), -1, dtype=np.int64)
+        P = np.eye(n, dtype=np.int64)
+        for d in range(1, n + 1):
+            P = ((P @ A.astype(np.int64)) > 0).astype(np.int64)
+            dist[(P > 0) & (dist < 0)] = d
+        for k in (0, 1, 2, 3, 5):
+            want = 0
+            for s_ in range(n):
+                if k >= 1:
+                    want += int(deg[s_])
+                    want += int(deg[(dist[s_] >= 1) & (dist[s_] <= k - 1)].sum())
+            assert rpq(g, "a*", max_length=k).product_edges == want, (trial, k)
+
+
+def test_length_bound_monotone_and_reaches_the_unbounded_result():
+    el = synth.uniform_graph(200, 700, 3, seed=8)
+    g = OracleGraph.from_edgelist(el)
+    for q in ("a.b*", "(a|b).c*", "(a.b)*", "a?.c"):
+        full = rpq(g, q)
+        prev = set()
+        for k in range(0, full.max_hops + 2):
+            r = rpq(g, q, max_length=k)
+            cur = rel_of(r)
+            assert prev <= cur, (q, k)
+            prev = cur
+        assert cur == rel_of(full)
+        # the pairs are complete at the deepest level; its pairs are expanded (their edges examined,
+        # finding nothing new) only when the bound lies beyond it
+        at = rpq(g, q, max_length=full.max_hops)
+        assert (at.count, at.hash) == (full.count, full.hash)
+        assert at.product_edges <= full.product_edges
+        big = rpq(g, q, max_length=full.max_hops + 1)
+        assert (big.count, big.hash, big.product_edges) == (full.count, full.hash, full.product_edges)
+        # zero-length walks only at k = 0: (s, s) for every s exactly when the empty word is accepted
+        z = rel_of(rpq(g, q, max_length=0))
+        nullable = re.fullmatch(q.replace(".", ""), "") is not None
+        assert z == ({(v, v) for v in range(200)} if nullable else set())
