@@ -15,6 +15,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
   backtracking join over the query variables in their declared order, with
   the vertex-label condition, constants, optional explicit domains and
   distinctness filters (Section 8.1 uses the latter in two queries).
+* :func:`crpq_forward` evaluates the same definition for queries whose atoms
+  all point from an earlier-declared variable to a later one, evaluating each
+  atom only from the values its source variable takes (anchored queries on
+  large graphs).
 * :func:`mix64` is the per-key checksum (one SplitMix64 output).
 """
 from __future__ import annotations
@@ -32,7 +36,7 @@ import numpy as np
 from . import automata
 from .automata import EpsNFA, glushkov, parse, thompson
 
-__all__ = ["OracleGraph", "OracleResult", "rpq", "crpq", "crpq_bruteforce", "mix64",
+__all__ = ["OracleGraph", "OracleResult", "rpq", "crpq", "crpq_forward", "crpq_bruteforce", "mix64",
            "compile_automaton", "build_library", "automata"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -373,3 +377,71 @@ def crpq_hash(tuples: Sequence[Tuple[int, ...]]) -> int:
             m = mix64(m ^ int(x))
         h = (h + m) & 0xFFFFFFFFFFFFFFFF
     return h
+
+
+def crpq_forward(g: OracleGraph, atoms: Sequence[Tuple[int, str, int]], n_vars: int, binding=None,
+                 var_label=None, neq: Sequence[Tuple[int, int]] = (), var_domain=None, threads: int = 1,
+                 max_pairs: int = 1 << 28, max_rows: int = 1 << 24) -> List[Tuple[int, ...]]:
+    """Definition 2 for queries in which every atom x -rho-> y has x declared no later than y
+    (chains, forks and triangles anchored at a constant, for instance).
+
+    The variables are bound one at a time in declared order, keeping every partial assignment
+    that satisfies the conditions on the bound variables.  An atom's pair set is needed only
+    from the values its source variable takes in those assignments, so it is evaluated (with
+    :func:`rpq`) from exactly those sources; the result is the same tuple set as :func:`crpq`,
+    without evaluating atoms from every vertex of a free variable's domain."""
+    for (x, _, y) in atoms:
+        if x > y:
+            raise ValueError("crpq_forward needs every atom's source variable declared first")
+    doms = _domains(g, n_vars, binding, var_label, var_domain)
+    succ: List[Dict[int, np.ndarray]] = [dict() for _ in atoms]
+
+    def targets_from(ai, values):
+        # R(rho_ai) from every value not evaluated yet, split per source
+        need = sorted(set(values) - succ[ai].keys())
+        if not need:
+            return
+        res = rpq(g, atoms[ai][1], sources=np.array(need, dtype=np.uint32), threads=threads,
+                  max_pairs=max_pairs)
+        k = res.pairs.astype(np.uint64)
+        s = (k >> np.uint64(32)).astype(np.int64)
+        t = (k & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        bounds = np.searchsorted(s, np.array(need, dtype=np.int64), side="left")
+        ends = np.searchsorted(s, np.array(need, dtype=np.int64), side="right")
+        for v, b, e in zip(need, bounds, ends):
+            succ[ai][v] = t[b:e]
+
+    rows: List[Tuple[int, ...]] = [()]
+    for i in range(n_vars):
+        into = [ai for ai, (x, _, y) in enumerate(atoms) if y == i and x < i]
+        loops = [ai for ai, (x, _, y) in enumerate(atoms) if x == i and y == i]
+        for ai in into:
+            targets_from(ai, {r[atoms[ai][0]] for r in rows})
+        dom_i = doms[i]
+        cand_rows = []
+        for r in rows:
+            cand = None
+            for ai in into:
+                c = succ[ai][r[atoms[ai][0]]]
+                cand = c if cand is None else np.intersect1d(cand, c)
+            cand = dom_i if cand is None else np.intersect1d(cand, dom_i)
+            cand_rows.append(cand)
+        if loops:
+            vals = set()
+            for c in cand_rows:
+                vals.update(int(v) for v in c)
+            for ai in loops:
+                targets_from(ai, vals)
+        new_rows: List[Tuple[int, ...]] = []
+        for r, cand in zip(rows, cand_rows):
+            for v in cand.tolist():
+                if any(not np.isin(v, succ[ai][v]).item() for ai in loops):
+                    continue
+                if any((a == i and b < i and r[b] == v) or (b == i and a < i and r[a] == v) for (a, b) in neq):
+                    continue
+                new_rows.append(r + (v,))
+        if len(new_rows) > max_rows:
+            raise MemoryError("crpq_forward: more than max_rows partial assignments")
+        rows = new_rows
+    free = [i for i in range(n_vars) if not (binding is not None and binding[i] is not None and binding[i] >= 0)]
+    return sorted({tuple(r[j] for j in free) for r in rows})

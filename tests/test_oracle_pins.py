@@ -544,6 +544,33 @@ def test_crpq_matches_bruteforce_tiny():
         assert got == want, (atoms, binding, var_label, neq)
 
 
+def test_crpq_forward_matches_bruteforce_tiny():
+    """The source-restricted join (atoms evaluated only from the values their source variable
+    takes) against every assignment checked directly, on queries whose atoms point forward in
+    the declared order: anchored chains, forks and triangles, self-loops, labels, inequalities."""
+    rng = np.random.default_rng(43)
+    shapes = [[(0, 1), (1, 2)], [(0, 1), (0, 1)], [(0, 1), (1, 2), (0, 2)], [(0, 1), (1, 1)],
+              [(0, 0), (0, 1)], [(0, 2)]]
+    for trial in range(60):
+        n = int(rng.integers(1, 7))
+        src, lab, dst = random_graph(rng, n, 2 * n + 3, 3)
+        vl = rng.integers(0, 2, size=n).astype(np.uint8)
+        g = OracleGraph(n, src, lab, dst, 3, NAMES[:3], vl)
+        shape = shapes[trial % len(shapes)]
+        k = 1 + max(max(x, y) for x, y in shape)
+        atoms = [(x, to_text(random_tree(rng, 3, max_depth=2), NAMES), y) for x, y in shape]
+        binding = [None] * k
+        if rng.random() < 0.6:
+            binding[0] = int(rng.integers(0, n))
+        var_label = [int(x) if rng.random() < 0.25 else None for x in rng.integers(0, 2, size=k)]
+        neq = [(0, k - 1)] if (k > 1 and rng.random() < 0.3) else []
+        got = oracle.crpq_forward(g, atoms, k, binding=binding, var_label=var_label, neq=neq)
+        want = crpq_bruteforce(g, atoms, k, binding=binding, var_label=var_label, neq=neq)
+        assert got == want, (atoms, binding, var_label, neq)
+    with pytest.raises(ValueError):
+        oracle.crpq_forward(g, [(1, "a", 0)], 2)
+
+
 # ------------------------------------------------------------------------------------------------
 # length-bounded RPQs: only walks of at most k edges count (the extension the paper's conclusion
 # names, enforced by the traversal depth)
