@@ -30,6 +30,14 @@
  *   - Inputs are validated before any traversal kernel runs; invalid input
  *     yields RPQ_EINVAL and leaves outputs untouched.
  *   - A graph handle may be used from one host thread at a time.
+ *   - Device memory: only rpq_graph_create allocates it (the graph); every other
+ *     call works in caller-owned device buffers (workspaces, outputs).  Host-side
+ *     runtime objects created after rpq_graph_create: rpq_eval keeps, per host
+ *     thread, a 4 KB pinned staging buffer for counter reads and a second stream
+ *     for extraction (both created on the thread's first use, kept until the
+ *     process ends); rpq_batch_create pins a small control block; rpq_batch_run
+ *     creates a capture stream, two timing events and the executable graph of
+ *     its batch; rpq_serve_start creates one stream per worker thread.
  */
 #ifndef RPQ_H
 #define RPQ_H
@@ -99,7 +107,7 @@ typedef struct {
  * flags: RPQ_BUILD_IN_CSR or 0.
  * On success *out receives a handle that owns its device memory until
  * rpq_graph_destroy.  The input arrays are not retained.  Allocates device
- * memory (the only entry point besides rpq_batch_create that does).
+ * memory (the only entry point that does).
  * Errors: RPQ_EINVAL for out-of-range ids or sizes, RPQ_ENOMEM, RPQ_EDEVICE.
  */
 int rpq_graph_create(const uint32_t* src, const uint8_t* label, const uint32_t* dst,
@@ -178,6 +186,14 @@ int rpq_nfa_reverse(const rpq_nfa* in, rpq_nfa* out);
                                  the sources reach, not with V * states * sources (for few
                                  sources on a large graph).  Same results; levels counts the
                                  search's non-empty frontiers. */
+#define RPQ_LENGTH_BOUND 32u  /* length-bounded RPQ (the extension named in the paper's conclusion,
+                                 Section 10: a length constraint enforced by the traversal depth):
+                                 only walks of at most opts->max_length edges count.  The search
+                                 stops after depth max_length; a product vertex first reached at
+                                 depth d has a walk of exactly d edges and none shorter, so (x, y)
+                                 is a result iff some final state is reached at y within the bound.
+                                 product_edges counts the edges of expanded product vertices only
+                                 (those at depth < max_length). */
 
 /* Tuning knobs; zero fields take defaults (the autotuner's choice when one is cached). */
 typedef struct {
@@ -189,6 +205,9 @@ typedef struct {
     uint32_t chunk_edges;    /* items (edge x successor state) per expansion work slice: entries
                                 with more items are cut into slices of this size (0 = 16, raised
                                 while the slice buffers would exceed a quarter of a unit's bitmaps) */
+    uint32_t max_length;     /* with RPQ_LENGTH_BOUND: the longest walk (in edges) that counts;
+                                0 keeps only zero-length walks */
+    uint32_t reserved;       /* must be 0 */
 } rpq_eval_opts;
 
 /*
@@ -286,7 +305,8 @@ typedef struct {
                                     retire extract, retire keys, retire clear, refill+seed, finalize */
 } rpq_batch_info;
 
-/* Create an empty batch over graph g (host object; no device memory). opts may be NULL. */
+/* Create an empty batch over graph g (host object with a small pinned control block; no device
+ * memory). opts may be NULL. */
 int rpq_batch_create(rpq_graph_t g, const rpq_batch_opts* opts, rpq_batch_t* out);
 
 /* Destroy a batch and its captured graph. */
@@ -305,6 +325,13 @@ int rpq_batch_destroy(rpq_batch_t b);
 int rpq_batch_add(rpq_batch_t b, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources,
                   uint32_t flags, uint64_t* pairs, uint64_t capacity, uint64_t* per_source,
                   uint32_t* query_id);
+
+/*
+ * Make query query_id of the batch length-bounded (as RPQ_LENGTH_BOUND in rpq_eval): only walks
+ * of at most max_length edges count.  Call before the first run.  Errors: RPQ_EINVAL for an
+ * unknown query or a batch that already ran.
+ */
+int rpq_batch_bound_length(rpq_batch_t b, uint32_t query_id, uint32_t max_length);
 
 /* Device workspace bytes the batch needs (fixes the unit/slot plan). */
 int rpq_batch_workspace_size(rpq_batch_t b, uint64_t* bytes);

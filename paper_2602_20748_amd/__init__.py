@@ -24,6 +24,7 @@ __all__ = [
     "rpq_graph_export_csr", "rpq_eval_workspace_size", "rpq_eval", "EvalResult", "Graph", "Nfa", "EvalOpts",
     "RPQ_OK", "RPQ_EINVAL", "RPQ_ENOMEM", "RPQ_EOVERFLOW", "RPQ_EDEVICE", "RPQ_EUNSUPPORTED",
     "RPQ_BUILD_IN_CSR", "RPQ_PAIRS", "RPQ_PER_SOURCE", "RPQ_ALL_SOURCES", "RPQ_REVERSE", "RPQ_SPARSE",
+    "RPQ_LENGTH_BOUND", "rpq_batch_bound_length",
     "RPQ_MAX_STATES", "RPQ_MAX_LABELS", "EXPORTED_SYMBOLS", "rpq_profile_enable", "rpq_profile_read",
     "Batch", "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size",
     "rpq_batch_run", "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune",
@@ -37,7 +38,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 RPQ_OK, RPQ_EINVAL, RPQ_ENOMEM, RPQ_EOVERFLOW, RPQ_EDEVICE, RPQ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RPQ_BUILD_IN_CSR = 1
-RPQ_PAIRS, RPQ_PER_SOURCE, RPQ_ALL_SOURCES, RPQ_REVERSE, RPQ_SPARSE = 1, 2, 4, 8, 16
+RPQ_PAIRS, RPQ_PER_SOURCE, RPQ_ALL_SOURCES, RPQ_REVERSE, RPQ_SPARSE, RPQ_LENGTH_BOUND = 1, 2, 4, 8, 16, 32
 RPQ_MAX_STATES, RPQ_MAX_LABELS = 32, 64
 
 _STATUS = {0: "RPQ_OK", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM", -3: "RPQ_EOVERFLOW", -4: "RPQ_EDEVICE",
@@ -69,7 +70,8 @@ class GraphInfo(ctypes.Structure):
 
 class EvalOpts(ctypes.Structure):
     _fields_ = [("batch_width", ctypes.c_uint32), ("concurrency", ctypes.c_uint32),
-                ("sync_every", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32)]
+                ("sync_every", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32),
+                ("max_length", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Profile(ctypes.Structure):
@@ -160,7 +162,7 @@ EXPORTED_SYMBOLS = [
     "rpq_graph_export_csr", "rpq_nfa_compile", "rpq_nfa_reverse", "rpq_eval_workspace_size", "rpq_eval",
     "rpq_profile_enable", "rpq_profile_read",
     "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size", "rpq_batch_run",
-    "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune",
+    "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune", "rpq_batch_bound_length",
     "crpq_eval", "rpq_serve_start", "rpq_serve_submit", "rpq_serve_poll", "rpq_serve_wait", "rpq_serve_clock_ms",
     "rpq_serve_stats", "rpq_serve_stop",
 ]
@@ -202,6 +204,7 @@ def load_library():
         "rpq_batch_add": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), vp, u64, u32, vp, u64, vp,
                                          ctypes.POINTER(u32)]),
         "rpq_batch_workspace_size": (ctypes.c_int, [vp, ctypes.POINTER(u64)]),
+        "rpq_batch_bound_length": (ctypes.c_int, [vp, u32, u32]),
         "rpq_batch_run": (ctypes.c_int, [vp, vp, u64, vp]),
         "rpq_batch_result": (ctypes.c_int, [vp, u32, ctypes.POINTER(_Result)]),
         "rpq_batch_stats": (ctypes.c_int, [vp, ctypes.POINTER(BatchInfo)]),
@@ -411,16 +414,22 @@ def rpq_eval_workspace_size(g: Graph, nfa: Nfa, n_sources: int, flags: int, opts
 
 def rpq_eval(g: Graph, nfa: Nfa, sources=None, flags: int = 0, opts=None, pairs=None, capacity: Optional[int] = None,
              pair_offset: int = 0, per_source=None, workspace=None, stream=None,
-             allow_overflow: bool = False) -> EvalResult:
+             allow_overflow: bool = False, max_length: Optional[int] = None) -> EvalResult:
     """Evaluate one RPQ.
 
     sources: CUDA/numpy uint32 ids (strictly ascending) or None with RPQ_ALL_SOURCES.
     pairs: a CUDA int64 tensor to receive keys (capacity = its length), or
       True to allocate one of exactly the needed size (two passes), or None.
     per_source: a CUDA int64 tensor [n, 2], or True to allocate one.
+    max_length: only walks of at most this many edges count (RPQ_LENGTH_BOUND).
     """
     torch = _torch()
     lib = load_library()
+    if max_length is not None:
+        opts = dict(opts or {}) if not isinstance(opts, EvalOpts) else {k: getattr(opts, k) for k, _ in
+                                                                          EvalOpts._fields_}
+        opts["max_length"] = int(max_length)
+        flags |= RPQ_LENGTH_BOUND
     if sources is None:
         flags |= RPQ_ALL_SOURCES
         src_t = None
@@ -434,7 +443,7 @@ def rpq_eval(g: Graph, nfa: Nfa, sources=None, flags: int = 0, opts=None, pairs=
     if per_source is not None:
         flags |= RPQ_PER_SOURCE
     if pairs is True:
-        first = rpq_eval(g, nfa, src_t, flags & ~RPQ_PAIRS, opts, None, None, 0, per_source, workspace, stream)
+        first = rpq_eval(g, nfa, src_t, flags & ~RPQ_PAIRS, o, None, None, 0, per_source, workspace, stream)
         pairs = torch.empty(max(first.count - pair_offset, 1), dtype=torch.int64, device="cuda")
         capacity = max(first.count - pair_offset, 0)
     if pairs is not None:
@@ -505,8 +514,12 @@ class Batch:
             load_library().rpq_batch_destroy(self.handle)
         self.handle = None
 
-    def add(self, nfa: Nfa, sources=None, pairs_capacity: Optional[int] = None, per_source: bool = False) -> int:
-        return rpq_batch_add(self, nfa, sources, pairs_capacity, per_source)
+    def add(self, nfa: Nfa, sources=None, pairs_capacity: Optional[int] = None, per_source: bool = False,
+            max_length: Optional[int] = None) -> int:
+        qid = rpq_batch_add(self, nfa, sources, pairs_capacity, per_source)
+        if max_length is not None:
+            rpq_batch_bound_length(self, qid, max_length)
+        return qid
 
     def run(self, stream=None) -> None:
         rpq_batch_run(self, stream=stream)
@@ -566,6 +579,11 @@ def rpq_batch_add(b: Batch, nfa: Nfa, sources=None, pairs_capacity: Optional[int
                                         ctypes.byref(qid)))
     b.outputs.append((pairs, ps[:n] if ps is not None else None))
     return int(qid.value)
+
+
+def rpq_batch_bound_length(b: Batch, qid: int, max_length: int) -> None:
+    """Only walks of at most max_length edges count for query qid (before the first run)."""
+    _check(load_library().rpq_batch_bound_length(b.handle, int(qid), int(max_length)))
 
 
 def rpq_batch_workspace_size(b: Batch) -> int:

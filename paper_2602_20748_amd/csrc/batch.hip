@@ -62,7 +62,8 @@ struct BQuery {
     uint64_t capacity;
     uint64_t stage_off;        // first staging key of this query
     uint32_t first_unit, n_units;
-    uint32_t flags, pad;
+    uint32_t flags;
+    uint32_t max_len;          // length bound: the deepest depth recorded (0xFFFFFFFF = none)
 };
 
 struct BQueryOut {
@@ -647,7 +648,7 @@ __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
 // Word phase: groups of K lanes per row; row phase: lane per row (as in the plain form).
 // ------------------------------------------------------------------------------------------------
 template <int K>
-__device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_t& t_fwords) {
+__device__ void phase_finalize(const BArgs& a, int p, uint32_t iter, uint64_t& t_frows, uint64_t& t_fwords) {
     constexpr int GS = 64 / K;
     const int np = p ^ 1;
     const uint64_t n = min((uint64_t)ld(&a.ctl->list_cnt[np]), a.list_cap);
@@ -667,6 +668,9 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
         uint64_t eprod = 0, work = 0;
         const BNfa* nfa = a.nfas;
         uint32_t my_ans = 0xFFFFFFFFu;   // Ans row of a final-state entry, else none
+        // at the depth bound of a length-bounded query a row is recorded (Vis, Ans) but gets an
+        // empty frontier row and no work: it is never expanded
+        bool stop = false;
         if (active) {
             row32 = xld(ids + e);
             slot = row32 / stride;
@@ -676,17 +680,19 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
             qid = ld32(&a.slots[slot].query);
             nfa = a.nfas + qid;
             if ((nfa->final >> q) & 1) my_ans = slot * V + v;
+            stop = iter - ld32(&a.slots[slot].start_iter) >= a.queries[qid].max_len;
         }
         const uint32_t n_here = (uint32_t)min<uint64_t>(64, n - e0);
         uint32_t my_pc = 0;   // new source bits of this lane's row
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
-            uint32_t r[kUnroll], an[kUnroll];
+            uint32_t r[kUnroll], an[kUnroll], sp[kUnroll];
             uint64_t nk[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t idx = j + u * GS + grp;
                 r[u] = __shfl(row32, idx & 63, 64);
                 an[u] = __shfl(my_ans, idx & 63, 64);
+                sp[u] = __shfl((uint32_t)stop, idx & 63, 64);
                 nk[u] = idx < n_here ? xld(a.next + (uint64_t)r[u] * K + k) : 0;
             }
 #pragma unroll
@@ -694,7 +700,7 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
                 const uint32_t idx = j + u * GS + grp;
                 uint32_t pc = 0;
                 if (idx < n_here) {
-                    rows[(e0 + idx) * K + k] = nk[u];
+                    rows[(e0 + idx) * K + k] = sp[u] ? 0 : nk[u];
                     if (nk[u]) {
                         a.next[(uint64_t)r[u] * K + k] = 0;
                         or_relaxed(a.vis + (uint64_t)r[u] * K + k, nk[u]);
@@ -715,7 +721,7 @@ __device__ void phase_finalize(const BArgs& a, int p, uint64_t& t_frows, uint64_
             ++t_frows;
             if (my_ans != 0xFFFFFFFFu && pc)
                 or_relaxed(&a.summ[(uint64_t)slot * a.summ_words + v / 64], 1ull << (v & 63));
-            const uint64_t m = a.lmask[v] & nfa->qlab[q];
+            const uint64_t m = stop ? 0 : (a.lmask[v] & nfa->qlab[q]);
             work = m ? rpqd::entry_work(a.row_ptr, L, nfa->delta, v, q, m) : 0;
             eprod = (uint64_t)pc * work;
         }
@@ -815,7 +821,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
         if (ld(&a.ctl->n_running) == 0) break;
         phase_seed<K>(a, p, iter);
         BAR(6);
-        phase_finalize<K>(a, p, t_frows, t_fwords);
+        phase_finalize<K>(a, p, iter, t_frows, t_fwords);
         BAR(7);
         p ^= 1;
         if (blockIdx.x == 0 && threadIdx.x == 0) st64(&a.ctl->iterations, iter);
@@ -876,6 +882,7 @@ struct HostQuery {
     const uint32_t* sources;
     uint64_t n_sources;
     uint32_t flags;
+    uint32_t max_len = 0xFFFFFFFFu;
     uint64_t* pairs;
     uint64_t capacity;
     uint64_t* per_source;
@@ -1260,6 +1267,24 @@ int rpq_batch_add(rpq_batch_t b, const rpq_nfa* nfa, const uint32_t* sources, ui
     return RPQ_OK;
 }
 
+int rpq_batch_bound_length(rpq_batch_t b, uint32_t query_id, uint32_t max_length) {
+    rpq::clear_error();
+    if (!b) {
+        rpq::set_error("NULL argument");
+        return RPQ_EINVAL;
+    }
+    if (b->frozen) {
+        rpq::set_error("batch already ran; create a new batch to bound a query");
+        return RPQ_EINVAL;
+    }
+    if (query_id >= b->queries.size()) {
+        rpq::set_error("unknown query %u", query_id);
+        return RPQ_EINVAL;
+    }
+    b->queries[query_id].max_len = max_length;
+    return RPQ_OK;
+}
+
 int rpq_batch_workspace_size(rpq_batch_t b, uint64_t* bytes) {
     rpq::clear_error();
     if (!b || !bytes) {
@@ -1333,6 +1358,7 @@ int rpq_batch_run(rpq_batch_t b, void* workspace, uint64_t workspace_bytes, hipS
             d.n_units = (uint32_t)((h.n_sources + x.W - 1) / x.W);
             ufirst += d.n_units;
             d.flags = h.flags;
+            d.max_len = h.max_len;
         }
         RPQ_HIP(hipMemcpy(ws + x.off_nfas, nf.data(), sizeof(BNfa) * nq, hipMemcpyHostToDevice));
         RPQ_HIP(hipMemcpy(ws + x.off_queries, qs.data(), sizeof(BQuery) * nq, hipMemcpyHostToDevice));

@@ -854,7 +854,7 @@ int eval_dense(Ctx& c, const rpq_nfa& nfa, bool reverse, const uint32_t* srcs, u
 // the error) when T was too small.
 int sparse_run(Ctx& c, const rpq_nfa& nfa, const rpq::Csr& csr, const uint32_t* srcs, uint64_t n_src,
                const uint64_t* target, uint64_t T, uint64_t** keys, uint64_t* n, uint64_t* eprod = nullptr,
-               uint64_t* levels = nullptr) {
+               uint64_t* levels = nullptr, uint64_t max_len = ~0ull) {
     SNfa h;
     to_snfa(nfa, c.g->L, &h);
     const uint64_t out_mark = c.ar.top;
@@ -899,7 +899,8 @@ int sparse_run(Ctx& c, const rpq_nfa& nfa, const rpq::Csr& csr, const uint32_t* 
     uint64_t n_levels = n_front ? 1 : 0;
     // a first-reach distance in the product graph is below Q * V
     const uint64_t level_bound = (uint64_t)nfa.n_states * c.g->V + 2;
-    for (uint64_t level = 0; !over && n_front > 0; ++level) {
+    // level l expands depth l; a length bound k leaves depth k recorded but unexpanded
+    for (uint64_t level = 0; !over && n_front > 0 && level < max_len; ++level) {
         if (level > level_bound) {
             rpq::set_error("sparse search found no fixpoint");
             return RPQ_EDEVICE;
@@ -1021,7 +1022,7 @@ int sparse_workspace_size(rpq_graph_t g, const rpq_nfa* nfa, uint64_t n_sources,
 }
 
 int sparse_eval(rpq_graph_t g, const rpq_nfa* nfa_in, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
-                void* workspace, uint64_t workspace_bytes, rpq_result* res, hipStream_t stream) {
+                uint64_t max_len, void* workspace, uint64_t workspace_bytes, rpq_result* res, hipStream_t stream) {
     RPQ_TRY(check_nfa(g, *nfa_in));
     const bool reverse = (flags & RPQ_REVERSE) != 0;
     if (reverse && !g->has_in) {
@@ -1088,7 +1089,8 @@ int sparse_eval(rpq_graph_t g, const rpq_nfa* nfa_in, const uint32_t* sources, u
                 rpq::set_error("workspace exhausted (sparse search with %llu slots)", (unsigned long long)T);
                 return RPQ_ENOMEM;
             }
-            const int rc = sparse_run(c, nfa, csr, srcs, n_sources, nullptr, T, &keys, &nk, &eprod, &levels);
+            const int rc =
+                sparse_run(c, nfa, csr, srcs, n_sources, nullptr, T, &keys, &nk, &eprod, &levels, max_len);
             if (rc == RPQ_OK) break;
             if (rc != RPQ_ENOMEM) return rc;
             T *= 2;

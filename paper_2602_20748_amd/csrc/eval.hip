@@ -326,10 +326,11 @@ __global__ __launch_bounds__(kBlock) void k_compact(Args a, int p, uint64_t n_ro
 //               counts the new source bits of the row;
 //   row phase   lane i takes row i: counts the items of its item space (the product edges each of
 //               its new source bits will examine); the slices of rows with more than H items are
-//               written by the whole wave.
+//               written by the whole wave.  With count_work == 0 (the last depth of a
+//               length-bounded search) the rows are recorded but not prepared for expansion.
 // ------------------------------------------------------------------------------------------------
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
+__global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_work) {
     constexpr int GS = 64 / K;
     __shared__ uint32_t s_delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];
     __shared__ uint64_t s_qlab[RPQ_MAX_STATES];
@@ -394,9 +395,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p) {
                 if (rel < (uint32_t)GS) my_pc = got;
             }
         }
-        // row phase: product edges; entries of more than H items are cut into slices
+        // row phase: product edges; entries of more than H items are cut into slices.  At the
+        // depth bound of a length-bounded query the entries are recorded but never expanded: no
+        // product edges, no slices.
         uint64_t work = 0;
-        if (active) {
+        if (active && count_work) {
             const uint64_t m = a.lmask[v] & s_qlab[q];
             work = m ? rpqd::entry_work(a.row_ptr, a.L, s_delta, v, q, m) : 0;
             eprod += (uint64_t)my_pc * work;
@@ -641,6 +644,7 @@ __global__ __launch_bounds__(1024) void k_group_finish(unsigned long long* __res
 // ------------------------------------------------------------------------------------------------
 struct Layout {
     uint32_t K, W, G, Q, L, V, H, nchunks, chunk_v, sync_every;
+    uint64_t max_len;   // deepest level finalized: the length bound, or no bound (UINT64_MAX)
     uint64_t list_cap, desc_cap;
     uint64_t off_counters, off_nfa, off_vis, off_next, off_touch, off_ans, off_ans2, off_ids[2], off_rows[2],
         off_desc[2], off_acc, off_partial, off_srcbase, total;
@@ -737,6 +741,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     }
     const bool auto_chunk = !(o && o->chunk_edges);
     x.sync_every = (o && o->sync_every) ? o->sync_every : 4;
+    x.max_len = (flags & RPQ_LENGTH_BOUND) ? (uint64_t)o->max_length : ~0ull;
     const uint64_t units = std::max<uint64_t>(1, (n_sources + x.W - 1) / x.W);
     const uint64_t QV = (uint64_t)x.Q * x.V;
     const uint64_t bitmap_bytes = QV * x.K * 8;
@@ -902,7 +907,7 @@ Profiler& profiler() {
 }
 
 template <int K>
-int launch_level(const Args& a, int p, uint64_t n_rows, uint32_t level, hipStream_t s) {
+int launch_level(const Args& a, int p, uint64_t n_rows, uint32_t level, int count_work, hipStream_t s) {
     Profiler& pr = profiler();
     const bool on = pr.on;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
@@ -918,7 +923,7 @@ int launch_level(const Args& a, int p, uint64_t n_rows, uint32_t level, hipStrea
     if (e1) RPQ_HIP(hipEventRecord(e1, s));
     hipLaunchKernelGGL(k_compact, dim3(LevelGrids<K>::get().compact), dim3(kBlock), 0, s, a, p, n_rows, level);
     RPQ_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_finalize<K>, dim3(LevelGrids<K>::get().finalize), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL(k_finalize<K>, dim3(LevelGrids<K>::get().finalize), dim3(kBlock), 0, s, a, p, count_work);
     RPQ_LAUNCH_CHECK();
     if (e2) RPQ_HIP(hipEventRecord(e2, s));
     if (on && e0 && e1 && e2) {
@@ -936,10 +941,10 @@ void profile_resolve() {
 }
 
 template <int K>
-int launch_finalize(const Args& a, int p, uint64_t n_rows, uint32_t level, hipStream_t s) {
+int launch_finalize(const Args& a, int p, uint64_t n_rows, uint32_t level, int count_work, hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(LevelGrids<K>::get().compact), dim3(kBlock), 0, s, a, p, n_rows, level);
     RPQ_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_finalize<K>, dim3(LevelGrids<K>::get().finalize), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL(k_finalize<K>, dim3(LevelGrids<K>::get().finalize), dim3(kBlock), 0, s, a, p, count_work);
     RPQ_LAUNCH_CHECK();
     return RPQ_OK;
 }
@@ -1021,8 +1026,16 @@ int prepare(rpq_graph_t g, const rpq_nfa* nfa_in, uint64_t n_sources, uint32_t f
         rpq::set_error("graph is NULL");
         return RPQ_EINVAL;
     }
-    if (flags & ~(RPQ_PAIRS | RPQ_PER_SOURCE | RPQ_ALL_SOURCES | RPQ_REVERSE | RPQ_SPARSE)) {
+    if (flags & ~(RPQ_PAIRS | RPQ_PER_SOURCE | RPQ_ALL_SOURCES | RPQ_REVERSE | RPQ_SPARSE | RPQ_LENGTH_BOUND)) {
         rpq::set_error("unknown flags 0x%x", flags);
+        return RPQ_EINVAL;
+    }
+    if ((flags & RPQ_LENGTH_BOUND) && !opts) {
+        rpq::set_error("RPQ_LENGTH_BOUND needs opts->max_length");
+        return RPQ_EINVAL;
+    }
+    if (opts && opts->reserved) {
+        rpq::set_error("rpq_eval_opts.reserved must be 0");
         return RPQ_EINVAL;
     }
     RPQ_TRY(validate_nfa(g, nfa_in));
@@ -1061,7 +1074,12 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
              const rpq_eval_opts* opts, void* workspace, uint64_t workspace_bytes, rpq_result* res,
              hipStream_t stream) {
     rpq::clear_error();
-    return rpq::eval_impl(g, nfa, sources, n_sources, flags, opts, nullptr, workspace, workspace_bytes, res, stream);
+    const int rc =
+        rpq::eval_impl(g, nfa, sources, n_sources, flags, opts, nullptr, workspace, workspace_bytes, res, stream);
+    // a failing call may leave kernels of its own queued on the stream: drain them, so that the
+    // caller may reuse or release the workspace as soon as the call returns
+    if (rc != RPQ_OK && rc != RPQ_EOVERFLOW) (void)hipStreamSynchronize(stream);
+    return rc;
 }
 
 }  // extern "C"
@@ -1098,12 +1116,21 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
         return RPQ_EINVAL;
     }
     res->workspace_needed = 0;
+    if ((flags & RPQ_LENGTH_BOUND) && !opts) {
+        rpq::set_error("RPQ_LENGTH_BOUND needs opts->max_length");
+        return RPQ_EINVAL;
+    }
     if (flags & RPQ_SPARSE) {
         if (target) {
             rpq::set_error("internal: a result filter is not supported with RPQ_SPARSE");
             return RPQ_EINVAL;
         }
-        return sparse_eval(g, nfa, sources, n_sources, flags, workspace, workspace_bytes, res, stream);
+        if (flags & ~(RPQ_PAIRS | RPQ_PER_SOURCE | RPQ_ALL_SOURCES | RPQ_REVERSE | RPQ_SPARSE | RPQ_LENGTH_BOUND)) {
+            rpq::set_error("unknown flags 0x%x", flags);
+            return RPQ_EINVAL;
+        }
+        const uint64_t max_len = (flags & RPQ_LENGTH_BOUND) ? (uint64_t)opts->max_length : ~0ull;
+        return sparse_eval(g, nfa, sources, n_sources, flags, max_len, workspace, workspace_bytes, res, stream);
     }
     rpq_nfa eff;
     DevNfa dn;
@@ -1176,20 +1203,25 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
         RPQ_LAUNCH_CHECK();
         const uint64_t n_rows = (uint64_t)G_eff * x.Q * x.V;
         RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(a.counters) + C_LASTLEVEL, 1, 0, stream));
-        RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_finalize<KK>(a, 0, n_rows, 0, stream)));
-        uint32_t level = 1;
+        // list and slice counts start at zero (a length-bounded group ends with a frontier left)
+        RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(a.counters) + C_LIST, 4, 0, stream));
+        RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_finalize<KK>(a, 0, n_rows, 0, x.max_len > 0, stream)));
+        uint64_t level = 1;
         int p = 1;
         // a first-reach distance in the product graph is below Q * V, so the
         // fixpoint arrives within Q * V + 1 levels; more means a defect
         const uint64_t level_bound = (uint64_t)x.Q * x.V + 2;
         uint64_t launched = 0;
-        for (;;) {
-            for (uint32_t s = 0; s < x.sync_every; ++s) {
-                RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_level<KK>(a, p, n_rows, level, stream)));
+        // level l expands depth l - 1 and finalizes depth l; a length bound k stops after level k
+        while (level <= x.max_len) {
+            uint32_t n_launch = 0;
+            for (; n_launch < x.sync_every && level <= x.max_len; ++n_launch) {
+                RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_level<KK>(a, p, n_rows, (uint32_t)level, level < x.max_len,
+                                                              stream)));
                 p ^= 1;
                 ++level;
             }
-            launched += x.sync_every;
+            launched += n_launch;
             RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
             RPQ_HIP(hipStreamSynchronize(stream));
             if (profiler().on) profile_resolve();
@@ -1202,6 +1234,10 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
                 rpq::set_error("no fixpoint after %llu levels", (unsigned long long)launched);
                 return RPQ_EDEVICE;
             }
+        }
+        if (launched == 0) {   // a bound of 0: only the seeds' zero-length walks
+            RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
+            RPQ_HIP(hipStreamSynchronize(stream));
         }
         const uint64_t lv = stage[C_LASTLEVEL];   // levels with a non-empty frontier, seeds included
         levels_total += lv;

@@ -90,8 +90,9 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
 uint64_t* host_stage();
 
 // The per-source hash-set search (RPQ_SPARSE) behind rpq_eval, and its starting workspace.
+// max_len: the length bound of RPQ_LENGTH_BOUND (deepest level recorded), or UINT64_MAX.
 int sparse_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
-                void* workspace, uint64_t workspace_bytes, rpq_result* res, hipStream_t stream);
+                uint64_t max_len, void* workspace, uint64_t workspace_bytes, rpq_result* res, hipStream_t stream);
 int sparse_workspace_size(rpq_graph_t g, const rpq_nfa* nfa, uint64_t n_sources, uint32_t flags, uint64_t* bytes);
 
 inline int bits_for(uint64_t max_value) {   // bits needed to represent values <= max_value

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(rpq.Nfa) == 16 + 4 * 32 * 64
-    assert ctypes.sizeof(rpq.EvalOpts) == 16
+    assert ctypes.sizeof(rpq.EvalOpts) == 24
 
 
 # ctypes mirror -> C struct of include/rpq.h
