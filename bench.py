@@ -1,30 +1,31 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the RPQ hot path on one MI355X.
 
-Workload (default): R-MAT scale 18 (262,144 vertices, 4,194,304 drawn edges,
-8 labels Zipf(1.1), seed 18) with five all-pairs queries: a*, a.b*, (a|b).c*,
-a.b*.c, (a.b)*.  One step evaluates all five from all 262,144 sources to the
-fixpoint and returns count, checksum and per-source (count, checksum).  The
-graph is built, and resident in HBM, before timing.
+Default workload: R-MAT scale 23 (8,388,608 vertices, 134,217,728 drawn edges,
+16 labels Zipf(1.1), seed 23), the largest graph.  One step evaluates the five
+Table 2 query shapes a*, a.b*, (a|b).c*, a.b*.c and (a.b)* to the fixpoint
+from a seeded sample of 65,536 sources (all pairs would take hours per step),
+with count, checksum and per-source (count, checksum).  The graph is built,
+and resident in HBM, before timing.
 
-Two forms of the same step are timed:
-  plain    one rpq_eval per query (query compile, traversal, extraction);
-  batched  the five queries in one rpq_batch: one persistent kernel in one
-           captured graph launch, unit width/slots/chunk chosen by the native
-           autotuner during warm-up.
-`value` is the product-graph edges per second of --form (default plain, the
-one-launch-per-query form this workload is defined on);
-both forms are reported.  Beside them, batched vs plain is also measured
-where batching is meant to pay (256 single-source queries; 128 single-source
-+ 128 slice queries, generated regexes) -- skip with --no-mixes.
+Legs of the default line:
+  plain    one rpq_eval per query (query compile, traversal, extraction); its
+           K timed steps give `value` (product-graph edges per second) and the
+           roofline of the level expansion, the dominant kernel;
+  batched  256 single-source queries (generated regexes) in one persistent,
+           graph-captured launch against the same queries as plain launches;
+  serving  a short serving run on the same resident graph: a burst (capacity)
+           and one Poisson rate of the mixed request stream, p50/p99 latency,
+           served edges/s against the same requests run one at a time.
+--workload rmat18_l8 gives the all-pairs R-MAT 18 step instead (plain and
+batched forms of the five queries plus the batched-vs-plain mixes).
+--mix times the 256-query batch on R-MAT scale 22 (autotuned) against its
+plain launches; --serve runs the full serving sweep; --crpq times the CRPQs on
+the full typed social graph (each prints one JSON line of its own).
 
 Metric: product-graph edges per second (per source, the product edges
 examined, counted on the Glushkov automaton), with distinct pairs per second.
-Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
---workload / --sources / --queries pick another graph, a seeded source sample and other queries
-(e.g. R-MAT scale 23 from 65,536 sources); --batched-plan WIDTH:CHUNK fixes the batched plan for
-profiling runs.  --serve measures serving latency instead, and --crpq times the CRPQs on the
-full typed social graph (each its own JSON line).
+--gpus above 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -52,7 +53,7 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat18_l8")
+    ap.add_argument("--workload", default="rmat23_l16")
     ap.add_argument("--form", choices=["batched", "plain"], default="plain",
                     help="which form's throughput is `value` (both are measured)")
     ap.add_argument("--batch-width", type=int, default=0, help="plain form: unit width (0 = default policy)")
@@ -66,8 +67,9 @@ def parse_args():
                     help="target CPU time of the oracle baseline leg (0 disables it)")
     ap.add_argument("--traffic-file", default="",
                     help="measured HBM bytes per launch of the dominant kernels (rocprofv3 --pmc), if present")
-    ap.add_argument("--sources", type=int, default=0,
-                    help="plain/batched forms: evaluate from this many seeded sampled sources (0 = all pairs)")
+    ap.add_argument("--sources", type=int, default=-1,
+                    help="plain/batched forms: evaluate from this many seeded sampled sources (0 = all pairs; "
+                         "default: the workload's sample size, all pairs where it has none)")
     ap.add_argument("--queries", default="",
                     help="comma-separated subset of the workload's queries (profiling runs only)")
     ap.add_argument("--only", choices=["", "plain", "batched"], default="",
@@ -76,6 +78,14 @@ def parse_args():
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-mixes", action="store_true",
                     help="skip the batched-vs-plain comparison on many-query mixes")
+    ap.add_argument("--mix", action="store_true",
+                    help="the 256-query batch on R-MAT scale 22 (generated regexes, half single-source, half "
+                         "4,096-source slices): autotuned batched run vs the plain launches")
+    ap.add_argument("--no-serve-leg", action="store_true", help="skip the serving leg of the default line")
+    ap.add_argument("--serve-leg", default="burst,10",
+                    help="serving leg of the default line: arrival rates ('burst' = all at once)")
+    ap.add_argument("--serve-leg-burst", type=int, default=64, help="serving leg: requests in the burst")
+    ap.add_argument("--serve-leg-seconds", type=float, default=8.0, help="serving leg: seconds per rate")
     ap.add_argument("--crpq", action="store_true",
                     help="time the two CRPQs on the full typed social graph (1M persons, 10M messages, 16,384 tags)")
     ap.add_argument("--serve", action="store_true",
@@ -142,33 +152,30 @@ def crpq_main():
     g.close()
 
 
-def serve_main(args):
-    """Serving: requests of synth.serve_requests arrive as a Poisson stream at each rate; latency is
-    scheduled arrival -> completion.  The same requests then run one at a time (plain FIFO, no
-    overlap) for the edges/s comparison and to check that every result is the one it has alone."""
+def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib, max_requests, burst_requests):
+    """Requests of synth.serve_requests arrive as a Poisson stream at each rate ('burst': all at once,
+    the server's capacity); latency is scheduled arrival -> completion.  The same requests then run
+    one at a time (plain FIFO, no overlap) for the edges/s comparison and to check that every result
+    is the one it has alone.  Returns (points, every result identical to its result alone)."""
     import numpy as np
     import torch
 
     import paper_2602_20748_amd as rpq
     import synth
 
-    spec = synth.WORKLOADS[args.workload]
-    el = synth.workload_graph(args.workload)
-    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, flags=rpq.RPQ_BUILD_IN_CSR,
-                             names=el.names)
     ring = [torch.empty(1 << 20, dtype=torch.int64, device="cuda") for _ in range(64)]
     points = []
     identical = True
-    for tok in [x for x in args.qps.split(",") if x]:
-        burst = tok == "burst"   # every request arrives at once: the server's capacity
+    for tok in [x for x in rates.split(",") if x]:
+        burst = tok == "burst"
         qps = float("inf") if burst else float(tok)
-        n = int(args.serve_max_requests if burst else
-                min(args.serve_max_requests, qps * (args.serve_seconds + args.serve_warmup_seconds)))
-        reqs = synth.serve_requests(n, el.n_vertices, el.names, seed=spec["seed"] + 1000)
-        arrive = np.zeros(n) if burst else synth.poisson_arrivals(qps, n, seed=spec["seed"] + 3000) * 1e3
+        n = int(min(max_requests, burst_requests) if burst else
+                min(max_requests, qps * (seconds + warmup_seconds)))
+        reqs = synth.serve_requests(n, el.n_vertices, el.names, seed=seed + 1000)
+        arrive = np.zeros(n) if burst else synth.poisson_arrivals(qps, n, seed=seed + 3000) * 1e3
         nfa = [rpq.rpq_nfa_compile(r[1], el.names) if r[0] != "crpq" else None for r in reqs]
         print("bench: serving %d requests at %s QPS" % (n, tok), file=sys.stderr, flush=True)
-        srv = rpq.Server(g, int(args.serve_pool_gib * (1 << 30)), workers=args.serve_workers)
+        srv = rpq.Server(g, int(pool_gib * (1 << 30)), workers=workers)
         last_note = time.time()
 
         def wait(t):
@@ -211,7 +218,7 @@ def serve_main(args):
         srv.stop()
         del srv
         torch.cuda.empty_cache()   # the pool goes back before the FIFO replay allocates its workspaces
-        warm = t0 if burst else t0 + args.serve_warmup_seconds * 1e3
+        warm = t0 if burst else t0 + warmup_seconds * 1e3
         meas = [d for d in done if d["arrival_ms"] >= warm] or done
         lat = np.array([d["end_ms"] - d["arrival_ms"] for d in meas])
         span = (max(d["end_ms"] for d in meas) - min(d["arrival_ms"] for d in meas)) / 1e3
@@ -248,7 +255,7 @@ def serve_main(args):
                                           or [0.0])), 3) for k in kinds}
         fifo_kind = {k: round(1e3 * float(np.mean([t for r, t in zip(reqs, fifo_times) if r[0] == k] or [0.0])), 3)
                      for k in kinds}
-        points.append(dict(qps="burst" if burst else qps, requests=n, measured=len(meas), mix=kinds, workers=args.serve_workers,
+        points.append(dict(qps="burst" if burst else qps, requests=n, measured=len(meas), mix=kinds, workers=workers,
                            service_ms_by_kind=service, fifo_ms_by_kind=fifo_kind,
                            p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
                            completed_per_s=round(len(meas) / span, 2), served_edges_per_s=ep / span,
@@ -260,6 +267,21 @@ def serve_main(args):
         print("bench: %s" % json.dumps(points[-1]), file=sys.stderr, flush=True)
         g.release_workspace()
         torch.cuda.empty_cache()
+    return points, identical
+
+
+def serve_main(args):
+    """The serving sweep over --qps on its own JSON line."""
+    import paper_2602_20748_amd as rpq
+    import synth
+
+    spec = synth.WORKLOADS[args.workload]
+    el = synth.workload_graph(args.workload)
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, flags=rpq.RPQ_BUILD_IN_CSR,
+                             names=el.names)
+    points, identical = serve_points(g, el, spec["seed"], args.qps, args.serve_seconds, args.serve_warmup_seconds,
+                                     args.serve_workers, args.serve_pool_gib, args.serve_max_requests,
+                                     args.serve_max_requests)
     line = {
         "metric": "p99 latency (serving)", "value": points[-1]["p99_ms"] if points else None, "unit": "ms",
         "n_gpus": 1, "higher_is_better": False, "dtype": "u64", "data": "synthetic (seeded R-MAT; Poisson arrivals)",
@@ -287,7 +309,7 @@ def cpu_baseline(el, queries, budget_s):
     """The oracle as it stands, on the host cores, over a bounded source sample."""
     import oracle
     import synth
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    threads = host_cores()
     og = oracle.OracleGraph.from_edgelist(el)
     n = 32
     while True:
@@ -315,6 +337,32 @@ def cpu_baseline(el, queries, budget_s):
                 host_logical_cpus=os.cpu_count(),
                 sample="%d seeded sources (of %d) x %d queries, %.1f s, %d product edges; single thread: first %d "
                        "of them, %.1f s" % (n, el.n_vertices, len(queries), dt, eprod, src1.size, dt1))
+
+
+def host_cores():
+    """Logical CPUs this process may run on (its affinity set), i.e. every host core it is given."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+def expand_roofline(prof):
+    """Bytes per launch of the level expansion from its exact device tallies.
+
+    method: the unit of work the method defines (one product edge examined, bit-parallel over the
+      unit's sources): 4 B neighbour id per item, 16 B per work segment (the row offsets), 8 B per
+      frontier word read, one 8 B read of the target's visited word per item-word, and 8 B per OR
+      into the next frontier.
+    impl: what this kernel loads on purpose -- the same, with the next-frontier word read beside
+      the visited word (16 B per item-word instead of 8), a choice that skips ORs already done and
+      brings the OR's line into L2."""
+    launches = max(1, prof["expand_launches"])
+    base = 4 * prof["edge_items"] + 16 * prof["descriptors"] + 8 * prof["row_words"] + 8 * prof["word_updates"]
+    method = (base + 8 * prof["word_reads"]) / launches
+    impl = (base + 16 * prof["word_reads"]) / launches
+    avg_ms = prof["expand_ms"] / launches
+    return method, impl, avg_ms
 
 
 def host_cpu_model():
@@ -346,7 +394,7 @@ def load_traffic(path, kernel, source_files, tag):
         return None
 
 
-def mixes(g, el, seed):
+def mixes(g, el, seed, kinds=("single_source_256", "mixed_128_single_128_slices"), autotune=True):
     """Batched vs plain where batching is meant to pay: 256 single-source queries, and 128
     single-source queries with 128 all-pairs queries over 4,096-source slices (generated regexes,
     seeded).  Wall time of the plain launches one after the other vs one batched run (plan from the
@@ -358,7 +406,7 @@ def mixes(g, el, seed):
     import synth
 
     out = {}
-    for kind in ("single_source_256", "mixed_128_single_128_slices"):
+    for kind in kinds:
         mix = synth.rmat_query_mix(256, el.n_vertices, el.names, seed=seed + 1000, slice_width=4096)
         if kind.startswith("single"):
             rng = np.random.default_rng(seed + 2000)
@@ -380,7 +428,7 @@ def mixes(g, el, seed):
         b = rpq.rpq_batch_create(g)
         for nfa, (_, src) in zip(nfas, mix):
             b.add(nfa, src)
-        tuned = b.autotune()
+        tuned = b.autotune() if autotune else None
         b.run()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -395,6 +443,33 @@ def mixes(g, el, seed):
                                                             units=st["n_units"], tuned=tuned))
         b.close()
     return out
+
+
+def mix_main(args):
+    """The 256-query batch on R-MAT scale 22 (half single-source queries, half all-pairs over
+    4,096-source slices; generated regexes, 2-12 automaton states): the batched persistent launch,
+    plan from the autotuner, against the same queries as plain launches one after the other."""
+    import torch
+
+    import paper_2602_20748_amd as rpq
+    import synth
+
+    name = "rmat22_l16"
+    spec = synth.WORKLOADS[name]
+    print("bench: generating %s" % name, file=sys.stderr, flush=True)
+    el = synth.workload_graph(name)
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
+    out = mixes(g, el, spec["seed"], kinds=("mixed_128_single_128_slices",), autotune=not args.no_autotune)
+    m = out["mixed_128_single_128_slices"]
+    line = {"metric": "batched vs plain (256-query mix)", "value": m["batched_over_plain"], "unit": "x",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic (seeded R-MAT; no dataset)",
+            "config": {"workload": "%s: R-MAT scale 22, %d vertices, %d distinct edges, 16 labels; 256 generated "
+                                   "queries, 128 single-source + 128 over 4,096-source slices" % (
+                                       name, el.n_vertices, g.info()["n_edges"])},
+            "mix": m}
+    print(json.dumps(line), flush=True)
+    g.close()
+    torch.cuda.synchronize()
 
 
 def main():
@@ -415,15 +490,16 @@ def main():
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
         return
+    rpq.load_library()
     if args.serve:
-        rpq.load_library()
         serve_main(args)
         return
     if args.crpq:
-        rpq.load_library()
         crpq_main()
         return
-    rpq.load_library()
+    if args.mix:
+        mix_main(args)
+        return
     spec = synth.WORKLOADS[args.workload]
     queries = spec.get("queries", [])
     if args.queries:
@@ -431,13 +507,18 @@ def main():
     if not queries:
         print("bench.py: workload %s has no default queries; pass --queries" % args.workload, file=sys.stderr)
         sys.exit(2)
+    n_sample = spec.get("bench_sources", 0) if args.sources < 0 else args.sources
+    all_pairs = n_sample == 0
+    # the R-MAT 18 all-pairs step also times the batched form of the same five queries and the mixes;
+    # the sampled large-graph step times a single-source batch and a serving leg instead
+    full_legs = not args.only and not args.queries
     print("bench: generating %s" % args.workload, file=sys.stderr, flush=True)
     el = synth.workload_graph(args.workload)
-    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
+    serve_leg = full_legs and not all_pairs and not args.no_serve_leg
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels,
+                             flags=rpq.RPQ_BUILD_IN_CSR if serve_leg else 0, names=el.names)
     info = g.info()
-    src_host = None
-    if args.sources:
-        src_host = synth.sample_sources(el.n_vertices, args.sources, spec["seed"] + 1000)
+    src_host = None if all_pairs else synth.sample_sources(el.n_vertices, n_sample, spec["seed"] + 1000)
     src_dev = torch.from_numpy(src_host.view("int32").copy()).cuda() if src_host is not None else None
     n_src = el.n_vertices if src_host is None else int(src_host.size)
     traffic_tag = "%s|%s|%s" % (args.workload, "all" if src_host is None else n_src, ",".join(queries))
@@ -488,14 +569,11 @@ def main():
         secs = ev0.elapsed_time(ev1) / 1e3
         for q in queries:
             per_query[q]["ms"] = round(qtimes[q] * 1e3 / max(1, args.steps), 3)
-        # dominant kernel of the plain form: the level expansion.  Algorithmic bytes:
-        # 4 B per item + 16 B per segment + 8 B per frontier word read
-        # + 16 B per visited-word read (visited and next-frontier word) + 8 B per next-word OR (write)
-        launches = max(1, prof["expand_launches"])
-        alg = (4 * prof["edge_items"] + 16 * prof["descriptors"] + 8 * prof["row_words"]
-               + 16 * prof["word_reads"] + 8 * prof["word_updates"]) / launches
-        avg_ms = prof["expand_ms"] / launches
-        achieved = alg / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+        # dominant kernel of the plain form: the level expansion, timed by HIP events on the stream
+        # it is launched on; bytes from its exact tallies (expand_roofline)
+        method, impl, avg_ms = expand_roofline(prof)
+        achieved = method / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+        achieved_impl = impl / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
         forms["plain"] = dict(
             value=eprod / secs, ms_per_step=secs * 1e3 / args.steps, distinct_pairs_per_s=pairs / secs,
             per_query=per_query,
@@ -504,16 +582,20 @@ def main():
                           traffic=load_traffic(traffic_file, "k_expand",
                                                ["paper_2602_20748_amd/csrc/eval.hip"], traffic_tag),
                           kernel="k_expand", traffic_tag=traffic_tag,
+                          bytes_rule="method: 4 B/item + 16 B/segment + 8 B/frontier word + 8 B/visited-word "
+                                     "read + 8 B/OR",
                           avg_launch_ms=round(avg_ms, 5), launches=prof["expand_launches"],
-                          alg_bytes_per_launch=round(alg, 1),
+                          alg_bytes_per_launch=round(method, 1),
+                          impl_bytes_per_launch=round(impl, 1), achieved_impl=round(achieved_impl, 2),
+                          frac_impl=round(achieved_impl / HBM_PEAK_GBPS, 5),
                           finalize_avg_ms=round(prof["finalize_ms"] / max(1, prof["finalize_launches"]), 5),
-                          counters={k: prof[k] for k in ("edge_items", "descriptors", "row_words", "word_reads",
-                                                         "word_updates", "expand_ms", "finalize_ms")}))
+                          counters={k: prof[k] for k in ("expand_launches", "edge_items", "descriptors", "row_words",
+                                                         "word_reads", "word_updates", "expand_ms", "finalize_ms")}))
 
     # ------------------------------------------------------------------ batched form
     g.release_workspace()
     torch.cuda.empty_cache()
-    if args.only in ("", "batched"):
+    if args.only == "batched" or (full_legs and all_pairs):
         plan_opts = None
         if args.batched_plan:
             w_, h_ = (int(x) for x in args.batched_plan.split(":"))
@@ -555,12 +637,12 @@ def main():
         st = b.stats()
         K = st["row_words"]
         # dominant kernel of the batched form: the persistent kernel (one launch per step).
-        # Algorithmic bytes = expansion (as in the plain form) + finalize (per row: 4 B id,
-        # 8K B next read, 8K B frontier-row write, 12 B label mask and slot; per non-zero word:
-        # 8 B next clear + 16 B visited OR; 16 B per descriptor written)
+        # Method bytes = expansion (as in the plain form: one 8 B visited-word read per item-word)
+        # + finalize (per row: 4 B id, 8K B next read, 8K B frontier-row write, 12 B label mask and
+        # slot; per non-zero word: 8 B next clear + 16 B visited OR; 16 B per descriptor written)
         # + compaction (8 B per touch word scanned per iteration, 4 B per row id).
         exp = (4 * tally["edge_items"] + 16 * tally["descriptors"] + 8 * K * tally["descriptors"]
-               + 16 * tally["word_reads"] + 8 * tally["word_updates"])
+               + 8 * tally["word_reads"] + 8 * tally["word_updates"])
         fin = tally["finalized_rows"] * (4 + 16 * K + 12) + 24 * tally["finalized_words"] + 16 * tally["descriptors"]
         cmp_ = 8 * tally["iterations"] * st["touch_words"] + 4 * tally["finalized_rows"]
         alg = (exp + fin + cmp_) / max(1, args.steps)
@@ -585,16 +667,35 @@ def main():
         b.close()
 
     mix_results = None
-    if not args.no_mixes and not args.only and not args.queries:
+    if full_legs:
         g.release_workspace()
         torch.cuda.empty_cache()
-        mix_results = mixes(g, el, spec["seed"])
+        kinds = ("single_source_256", "mixed_128_single_128_slices") if all_pairs else ("single_source_256",)
+        if not args.no_mixes:
+            mix_results = mixes(g, el, spec["seed"], kinds=kinds)
+    serving = None
+    if serve_leg:
+        g.release_workspace()
+        torch.cuda.empty_cache()
+        points, identical = serve_points(g, el, spec["seed"], args.serve_leg, args.serve_leg_seconds, 2.0,
+                                         args.serve_workers, args.serve_pool_gib, args.serve_max_requests,
+                                         args.serve_leg_burst)
+        serving = dict(points=points, results_identical_to_alone=identical,
+                       p50_ms={str(p["qps"]): p["p50_ms"] for p in points},
+                       p99_ms={str(p["qps"]): p["p99_ms"] for p in points},
+                       served_edges_per_s={str(p["qps"]): p["served_edges_per_s"] for p in points},
+                       fifo_edges_per_s={str(p["qps"]): p["fifo_edges_per_s"] for p in points})
     form = args.form if args.form in forms else next(iter(forms))
     main_form = forms[form]
     cpu = None
     if args.cpu_baseline_seconds > 0:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(el, queries, args.cpu_baseline_seconds)
+    batched_over_plain = None
+    if "batched" in forms and "plain" in forms:
+        batched_over_plain = forms["batched"]["value"] / forms["plain"]["value"]
+    elif mix_results:
+        batched_over_plain = mix_results["single_source_256"]["batched_over_plain"]
     line = {
         "metric": "product-graph edges/sec",
         "value": main_form["value"],
@@ -612,13 +713,14 @@ def main():
                                " %s %s; %s form"
                                % (args.workload, describe_graph(spec), el.n_vertices, el.n_edges, info["n_edges"],
                                   el.n_labels, spec.get("zipf_s", 1.1),
-                                  "all-pairs" if src_host is None else "%d sampled sources," % n_src,
+                                  "all-pairs" if src_host is None else
+                                  "%d seeded sampled sources (seed %d)," % (n_src, spec["seed"] + 1000),
                                   ", ".join(queries), form),
                    "sources": n_src, "queries": queries, "form": form},
         "distinct_pairs_per_s": main_form["distinct_pairs_per_s"],
-        "batched_over_plain": (forms["batched"]["value"] / forms["plain"]["value"]
-                               if "batched" in forms and "plain" in forms else None),
+        "batched_over_plain": batched_over_plain,
         "batched_vs_plain_mixes": mix_results,
+        "serving": serving,
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "roofline"} for k, v in forms.items()},
         "roofline": main_form["roofline"],
         "roofline_other": {k: v["roofline"] for k, v in forms.items() if k != form},

@@ -400,8 +400,11 @@ WORKLOADS: Dict[str, dict] = {
     "rmat22_l16": dict(kind="rmat", scale=22, edge_factor=16, n_labels=16, zipf_s=1.1, seed=22),
     # typed social graph: 1M persons, 10M messages, 16,384 tags
     "social_p1m_m10m_t16k": dict(kind="social", seed=4),
-    # R-MAT scale 23 (8,388,608 vertices, 134,217,728 drawn edges), 16 labels Zipf(1.1)
-    "rmat23_l16": dict(kind="rmat", scale=23, edge_factor=16, n_labels=16, zipf_s=1.1, seed=23),
+    # R-MAT scale 23 (8,388,608 vertices, 134,217,728 drawn edges), 16 labels Zipf(1.1); the
+    # throughput step runs the five Table 2 query shapes from a seeded sample of 65,536 sources
+    # (all pairs at this scale take hours per step)
+    "rmat23_l16": dict(kind="rmat", scale=23, edge_factor=16, n_labels=16, zipf_s=1.1, seed=23,
+                       queries=["a*", "a.b*", "(a|b).c*", "a.b*.c", "(a.b)*"], bench_sources=65536),
 }
 
 

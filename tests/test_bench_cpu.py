@@ -41,3 +41,15 @@ def test_committed_traffic_files_name_their_workload():
             for kernel, ent in d.items():
                 assert ent["tag"].startswith(name[len("traffic_"):-len(".json")] + "|"), (name, kernel)
                 assert len(ent["sources_sha256"]) == 64 and ent["bytes_per_launch"] > 0
+
+
+def test_expand_roofline_counts_one_visited_word_read_per_item_word():
+    # tallies of one R-MAT 18 step (per launch): items, segments, frontier words, visited-word
+    # reads, ORs; the method's bytes charge 8 B per visited-word read, the kernel's own 16 B
+    prof = dict(expand_launches=2, expand_ms=2 * 1.4714, edge_items=2 * 13_070_000, descriptors=2 * 1_414_000,
+                row_words=2 * 45_260_000, word_reads=2 * 275_400_000, word_updates=2 * 56_380_000)
+    method, impl, avg_ms = bench.expand_roofline(prof)
+    assert method == 4 * 13_070_000 + 16 * 1_414_000 + 8 * 45_260_000 + 8 * 275_400_000 + 8 * 56_380_000
+    assert impl - method == 8 * 275_400_000
+    assert abs(avg_ms - 1.4714) < 1e-12
+    assert abs(method / (avg_ms / 1e3) / 8e12 - 0.2626) < 5e-4

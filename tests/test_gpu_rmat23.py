@@ -1,0 +1,148 @@
+"""GPU parity on the largest graph: R-MAT scale 23 (8,388,608 vertices, 134,217,728 drawn edges,
+16 labels Zipf(1.1), seed 23).
+
+The five Table 2 query shapes run at the library's default plan from the 65,536 seeded sources
+the benchmark times.  The oracle cannot follow 65,536 sources at this scale in a test, so the
+run's per-source (count, checksum) are compared with the oracle at 256 sampled sources, and the
+full sorted pairs of a run over 64 of those sources are compared key by key.  Per-source tallies
+must also add up to the run's totals (the count is additive, the checksum additive mod 2^64).
+Here rows reach states * vertices = 3.4e7 per unit, with row ids near the 32-bit bound the
+library checks."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+QUERIES = ["a*", "a.b*", "(a|b).c*", "a.b*.c", "(a.b)*"]
+N_BENCH_SOURCES = 65536
+N_SAMPLES = 256
+N_PAIR_SAMPLES = 64
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except (AttributeError, OSError):
+        return 8
+
+
+@pytest.fixture(scope="module")
+def rpq():
+    import torch
+    import paper_2602_20748_amd as m
+    assert torch.cuda.is_available()
+    m.load_library()
+    return m
+
+
+@pytest.fixture(scope="module")
+def w23(rpq):
+    say("case: generating rmat23_l16")
+    el = synth.workload_graph("rmat23_l16")
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, flags=rpq.RPQ_BUILD_IN_CSR,
+                             names=el.names)
+    say("case: oracle graph rmat23_l16")
+    og = oracle.OracleGraph.from_edgelist(el)
+    assert g.info()["n_edges"] == og.n_edges
+    src = synth.sample_sources(el.n_vertices, N_BENCH_SOURCES, synth.WORKLOADS["rmat23_l16"]["seed"] + 1000)
+    rng = np.random.default_rng(2323)
+    pos = np.sort(rng.choice(src.size, N_SAMPLES, replace=False))
+    yield el, g, og, src, pos
+    g.close()
+
+
+@pytest.mark.parametrize("regex", QUERIES)
+def test_rmat23_bench_sources_against_oracle(rpq, w23, regex):
+    el, g, og, src, pos = w23
+    nfa = rpq.rpq_nfa_compile(regex, el.names)
+    say("case: rmat23 %s from %d sources, default plan" % (regex, src.size))
+    res = rpq.rpq_eval(g, nfa, src, per_source=True)
+    ps = res.per_source.cpu().numpy().view(np.uint64)
+    assert int(ps[:, 0].sum(dtype=np.uint64)) == res.count
+    assert int(ps[:, 1].sum(dtype=np.uint64)) == res.hash   # wraps mod 2^64 like the checksum
+    samp = src[pos]
+    pair_pos, count_pos = pos[:N_PAIR_SAMPLES], pos[N_PAIR_SAMPLES:]
+    T = oracle_threads()
+    say("case: rmat23 %s oracle, full pairs from %d sampled sources" % (regex, pair_pos.size))
+    want = oracle.rpq(og, regex, sources=src[pair_pos], threads=T, max_pairs=1 << 28)
+    say("case: rmat23 %s oracle, tallies at %d more sampled sources" % (regex, count_pos.size))
+    want_c = oracle.rpq(og, regex, sources=src[count_pos], pairs=False, threads=T)
+    assert np.array_equal(ps[pair_pos], want.per_source), regex
+    assert np.array_equal(ps[count_pos], want_c.per_source), regex
+    say("case: rmat23 %s full pairs from the %d sampled sources" % (regex, pair_pos.size))
+    got = rpq.rpq_eval(g, nfa, src[pair_pos], pairs=True, per_source=True)
+    assert got.count == want.count and got.hash == want.hash, regex
+    assert got.product_edges == want.product_edges, regex
+    assert np.array_equal(got.pairs.cpu().numpy().view(np.uint64), want.pairs), regex
+    assert np.array_equal(got.per_source.cpu().numpy().view(np.uint64), want.per_source), regex
+    assert samp.size == N_SAMPLES
+
+
+def test_rmat23_served_stream_against_oracle(rpq, w23):
+    """20 requests of the serving stream (single-source RPQs, 4,096-source slices, anchored CRPQs)
+    served together on the resident graph.  Each result must equal its result alone; against the
+    oracle, single-source requests compare their keys (up to the 2^20-key buffer) with count and
+    checksum, slices their per-source tallies at 8 sampled sources (and totals that add up),
+    CRPQs their tuple count and checksum."""
+    import torch
+    el, g, og, _, _ = w23
+    reqs = synth.serve_requests(20, el.n_vertices, el.names, seed=synth.WORKLOADS["rmat23_l16"]["seed"] + 1000)
+    T = oracle_threads()
+    srv = rpq.Server(g, 96 << 30, workers=4)
+    subs = []
+    for i, r in enumerate(reqs):
+        say("case: rmat23 serve submit %d %s %s" % (i, r[0], r[1]))
+        if r[0] == "crpq":
+            subs.append((srv.submit_crpq(r[1], r[2], binding=r[3]), None, None))
+            continue
+        nfa = rpq.rpq_nfa_compile(r[1], el.names)
+        if r[0] == "rpq_single":
+            buf = torch.empty(1 << 20, dtype=torch.int64, device="cuda")
+            subs.append((srv.submit_rpq(nfa, r[2], flags=rpq.RPQ_SPARSE, pairs=buf), buf, None))
+        else:
+            ps = torch.zeros((r[2].size, 2), dtype=torch.int64, device="cuda")
+            subs.append((srv.submit_rpq(nfa, r[2], per_source=ps), None, ps))
+    done = [srv.wait(t) for t, _, _ in subs]
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    rng = np.random.default_rng(2324)
+    for i, (r, (t, buf, ps), d) in enumerate(zip(reqs, subs, done)):
+        say("case: rmat23 serve check %d %s %s" % (i, r[0], r[1]))
+        if r[0] == "crpq":
+            assert d["status"] == 0, (r, d)
+            alone = rpq.crpq_eval(g, r[1], r[2], binding=r[3])
+            assert (d["count"], d["hash"]) == (alone.count, alone.hash), r
+            tuples = oracle.crpq_forward(og, r[1], r[2], binding=r[3], threads=T)
+            assert (d["count"], d["hash"]) == (len(tuples), oracle.crpq_hash(tuples)), r
+            continue
+        nfa = rpq.rpq_nfa_compile(r[1], el.names)
+        if r[0] == "rpq_single":
+            assert d["status"] in (0, rpq.RPQ_EOVERFLOW), (r, d)
+            alone = rpq.rpq_eval(g, nfa, r[2], flags=rpq.RPQ_SPARSE)
+            assert (d["count"], d["hash"], d["product_edges"]) == (alone.count, alone.hash, alone.product_edges), r
+            w = oracle.rpq(og, r[1], sources=r[2], threads=T, max_pairs=1 << 28)
+            assert (d["count"], d["hash"], d["product_edges"]) == (w.count, w.hash, w.product_edges), r
+            n = min(d["count"], buf.numel())
+            assert np.array_equal(buf[:n].cpu().numpy().view(np.uint64), w.pairs[:n]), r
+        else:
+            assert d["status"] == 0, (r, d)
+            alone = rpq.rpq_eval(g, nfa, r[2])
+            assert (d["count"], d["hash"], d["product_edges"]) == (alone.count, alone.hash, alone.product_edges), r
+            got = ps.cpu().numpy().view(np.uint64)
+            assert int(got[:, 0].sum(dtype=np.uint64)) == d["count"]
+            assert int(got[:, 1].sum(dtype=np.uint64)) == d["hash"]
+            pos = np.sort(rng.choice(r[2].size, 8, replace=False))
+            w = oracle.rpq(og, r[1], sources=r[2][pos], pairs=False, threads=T)
+            assert np.array_equal(got[pos], w.per_source), r

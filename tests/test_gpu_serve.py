@@ -1,10 +1,13 @@
 """GPU tests of the serving loop (rpq_serve_*): every request's result in a mixed stream equals
-its result alone, requests overlap on the device, and memory pressure only changes the schedule."""
+the CPU oracle's (Definitions 1 and 2) and its result alone, requests overlap on the device, and
+memory pressure only changes the schedule."""
+import os
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -31,6 +34,34 @@ def rmat18(rpq):
                              names=el.names)
     yield el, g
     g.close()
+
+
+@pytest.fixture(scope="module")
+def og18(rmat18):
+    return oracle.OracleGraph.from_edgelist(rmat18[0])
+
+
+def oracle_threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except (AttributeError, OSError):
+        return 8
+
+
+def oracle_result(og, item):
+    """The oracle's (count, checksum, product edges or None, sorted keys or None) of one request:
+    full keys for single-source RPQs, count and checksum for slices, the tuple set of a CRPQ."""
+    T = oracle_threads()
+    if item[0] == "crpq":
+        _, atoms, nv, binding = item
+        tuples = oracle.crpq_forward(og, atoms, nv, binding=binding, threads=T)
+        return (len(tuples), oracle.crpq_hash(tuples), None, None)
+    kind, rx, src = item
+    if src.size == 1:
+        w = oracle.rpq(og, rx, sources=src, threads=T)
+        return (w.count, w.hash, w.product_edges, w.pairs)
+    w = oracle.rpq(og, rx, sources=src, pairs=False, threads=T)
+    return (w.count, w.hash, w.product_edges, None)
 
 
 def request_mix(rng, el, n):
@@ -83,13 +114,14 @@ def submit(rpq, srv, el, item):
     return srv.submit_rpq(nfa, src, flags=flags, pairs=buf), buf
 
 
-def check_mix(rpq, g, el, mix, alone, pool_bytes, workers):
+def check_mix(rpq, g, el, mix, alone, pool_bytes, workers, want=None):
+    """Serve the mix; every result must equal its result alone and, when given, the oracle's."""
     srv = rpq.Server(g, pool_bytes, workers=workers)
     sub = [submit(rpq, srv, el, it) for it in mix]
     done = [srv.wait(t) for t, _ in sub]
     st = srv.stats()
     srv.stop()
-    for it, (t, buf), d, a in zip(mix, sub, done, alone):
+    for i, (it, (t, buf), d, a) in enumerate(zip(mix, sub, done, alone)):
         # a pair buffer smaller than the result is filled and the request reports the overflow
         assert d["status"] == 0 or (d["status"] == rpq.RPQ_EOVERFLOW and it[0] != "crpq"
                                     and d["count"] > buf.numel()), (it, d)
@@ -99,6 +131,14 @@ def check_mix(rpq, g, el, mix, alone, pool_bytes, workers):
             assert (d["count"], d["hash"], d["product_edges"]) == a[:3], it
             n = min(d["count"], buf.numel())
             assert np.array_equal(buf[:n].cpu().numpy().view(np.uint64), a[3][:n]), it
+        if want is not None:
+            w = want[i]
+            assert (d["count"], d["hash"]) == (w[0], w[1]), ("oracle", it)
+            if w[2] is not None:
+                assert d["product_edges"] == w[2], ("oracle", it)
+            if w[3] is not None:
+                n = min(d["count"], buf.numel())
+                assert np.array_equal(buf[:n].cpu().numpy().view(np.uint64), w[3][:n]), ("oracle", it)
     assert st["completed"] == len(mix) and st["failed"] == 0 and st["pool_in_use"] == 0
     return done, st
 
@@ -112,7 +152,7 @@ def max_overlap(done):
     return best
 
 
-def test_results_in_the_mix_equal_alone(rpq, rmat18):
+def test_results_in_the_mix_equal_alone_and_oracle(rpq, rmat18, og18):
     el, g = rmat18
     rng = np.random.default_rng(505)
     mix = request_mix(rng, el, 40)
@@ -120,24 +160,29 @@ def test_results_in_the_mix_equal_alone(rpq, rmat18):
     for i, it in enumerate(mix):
         say("case: serve alone %d %s" % (i, it[:2]))
         alone.append(run_alone(rpq, g, el, it))
+    want = []
+    for i, it in enumerate(mix):
+        say("case: serve oracle %d %s" % (i, it[:2]))
+        want.append(oracle_result(og18, it))
     say("case: serve mix, 4 workers, 24 GiB pool")
-    done, st = check_mix(rpq, g, el, mix, alone, 24 << 30, 4)
+    done, st = check_mix(rpq, g, el, mix, alone, 24 << 30, 4, want)
     assert max_overlap(done) >= 2          # admitted requests ran at the same time
     assert all(d["end_ms"] >= d["start_ms"] >= d["arrival_ms"] for d in done)
 
 
-def test_memory_pressure_changes_only_the_schedule(rpq, rmat18):
+def test_memory_pressure_changes_only_the_schedule(rpq, rmat18, og18):
     el, g = rmat18
     rng = np.random.default_rng(506)
-    mix = [it for it in request_mix(rng, el, 25) if it[0] != "crpq"]
+    mix = request_mix(rng, el, 25)   # CRPQs included: they grow their workspace through the queue
     alone = [run_alone(rpq, g, el, it) for it in mix]
+    want = [oracle_result(og18, it) for it in mix]
     # the smallest pool that admits the largest single request: requests run one or two at a time,
     # and dense ones are split into fewer units in flight
     nfas = [rpq.rpq_nfa_compile(it[1], el.names) for it in mix]
     need = max(rpq.rpq_eval_workspace_size(g, n, 512, 0, dict(batch_width=64, concurrency=1))
                for n, it in zip(nfas, mix) if it[0] == "rpq_dense")
     say("case: serve under pressure, pool %d bytes" % need)
-    done, st = check_mix(rpq, g, el, mix, alone, int(need * 1.5), 4)
+    done, st = check_mix(rpq, g, el, mix, alone, int(need * 1.5), 4, want)
     assert st["pool_peak"] <= int(need * 1.5)
 
 
