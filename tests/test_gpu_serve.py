@@ -178,9 +178,9 @@ def test_memory_pressure_changes_only_the_schedule(rpq, rmat18, og18):
     want = [oracle_result(og18, it) for it in mix]
     # the smallest pool that admits the largest single request: requests run one or two at a time,
     # and dense ones are split into fewer units in flight
-    nfas = [rpq.rpq_nfa_compile(it[1], el.names) for it in mix]
-    need = max(rpq.rpq_eval_workspace_size(g, n, 512, 0, dict(batch_width=64, concurrency=1))
-               for n, it in zip(nfas, mix) if it[0] == "rpq_dense")
+    need = max(rpq.rpq_eval_workspace_size(g, rpq.rpq_nfa_compile(it[1], el.names), 512, 0,
+                                           dict(batch_width=64, concurrency=1))
+               for it in mix if it[0] == "rpq_dense")
     say("case: serve under pressure, pool %d bytes" % need)
     done, st = check_mix(rpq, g, el, mix, alone, int(need * 1.5), 4, want)
     assert st["pool_peak"] <= int(need * 1.5)
