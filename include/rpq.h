@@ -266,6 +266,28 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
              uint32_t flags, const rpq_eval_opts* opts, void* workspace, uint64_t workspace_bytes,
              rpq_result* result, hipStream_t stream);
 
+/* Size of the static device scratch used by rpq_eval_noalloc (per device, held until the
+ * process ends once the library's code is loaded on that device). */
+#define RPQ_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/*
+ * rpq_eval without any allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, flags and
+ * results as rpq_eval, minus the workspace: the call works in a file-scope device array of
+ * RPQ_NOALLOC_SCRATCH_BYTES bytes (one per device), and makes no hipMalloc, hipFree,
+ * hipHostMalloc, stream or event creation (counters are read through a pageable host buffer,
+ * extraction stays on `stream`, profiling is skipped).
+ * Plan: zero knobs in opts are narrowed until the workspace fits the scratch (fewer units in
+ * flight first, then narrower units); knobs the caller set are kept.
+ * The scratch keeps the last call's contents; every call clears what it needs.  Calls on one
+ * device share that device's scratch, so calls that overlap in time on one device (other host
+ * threads, other streams) race and give wrong results: serialise them.
+ * Errors: as rpq_eval; RPQ_ENOMEM (with result->workspace_needed) when even the narrowest plan
+ * needs more than RPQ_NOALLOC_SCRATCH_BYTES; RPQ_EUNSUPPORTED for RPQ_SPARSE.
+ */
+int rpq_eval_noalloc(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources,
+                     uint32_t flags, const rpq_eval_opts* opts, rpq_result* result, hipStream_t stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Batched evaluation: many queries in one persistent, graph-captured launch                  */
 /* ------------------------------------------------------------------------------------------ */

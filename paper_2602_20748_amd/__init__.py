@@ -21,7 +21,8 @@ from typing import List, Optional, Sequence
 __all__ = [
     "RpqError", "library_path", "load_library", "rpq_abi_version", "rpq_last_error", "rpq_nfa_compile",
     "rpq_nfa_reverse", "rpq_graph_create", "rpq_graph_destroy", "rpq_graph_info_get",
-    "rpq_graph_export_csr", "rpq_eval_workspace_size", "rpq_eval", "EvalResult", "Graph", "Nfa", "EvalOpts",
+    "rpq_graph_export_csr", "rpq_eval_workspace_size", "rpq_eval", "rpq_eval_noalloc", "EvalResult", "Graph",
+    "Nfa", "EvalOpts", "RPQ_NOALLOC_SCRATCH_BYTES",
     "RPQ_OK", "RPQ_EINVAL", "RPQ_ENOMEM", "RPQ_EOVERFLOW", "RPQ_EDEVICE", "RPQ_EUNSUPPORTED",
     "RPQ_BUILD_IN_CSR", "RPQ_PAIRS", "RPQ_PER_SOURCE", "RPQ_ALL_SOURCES", "RPQ_REVERSE", "RPQ_SPARSE",
     "RPQ_LENGTH_BOUND", "rpq_batch_bound_length",
@@ -40,6 +41,7 @@ RPQ_OK, RPQ_EINVAL, RPQ_ENOMEM, RPQ_EOVERFLOW, RPQ_EDEVICE, RPQ_EUNSUPPORTED = 0
 RPQ_BUILD_IN_CSR = 1
 RPQ_PAIRS, RPQ_PER_SOURCE, RPQ_ALL_SOURCES, RPQ_REVERSE, RPQ_SPARSE, RPQ_LENGTH_BOUND = 1, 2, 4, 8, 16, 32
 RPQ_MAX_STATES, RPQ_MAX_LABELS = 32, 64
+RPQ_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 _STATUS = {0: "RPQ_OK", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM", -3: "RPQ_EOVERFLOW", -4: "RPQ_EDEVICE",
            -5: "RPQ_EUNSUPPORTED"}
@@ -160,7 +162,7 @@ class ServerStats(ctypes.Structure):
 EXPORTED_SYMBOLS = [
     "rpq_last_error", "rpq_abi_version", "rpq_graph_create", "rpq_graph_destroy", "rpq_graph_info_get",
     "rpq_graph_export_csr", "rpq_nfa_compile", "rpq_nfa_reverse", "rpq_eval_workspace_size", "rpq_eval",
-    "rpq_profile_enable", "rpq_profile_read",
+    "rpq_eval_noalloc", "rpq_profile_enable", "rpq_profile_read",
     "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size", "rpq_batch_run",
     "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune", "rpq_batch_bound_length",
     "crpq_eval", "rpq_serve_start", "rpq_serve_submit", "rpq_serve_poll", "rpq_serve_wait", "rpq_serve_clock_ms",
@@ -198,6 +200,8 @@ def load_library():
                                                    ctypes.POINTER(u64)]),
         "rpq_eval": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), vp, u64, u32, ctypes.POINTER(EvalOpts), vp, u64,
                                     ctypes.POINTER(_Result), vp]),
+        "rpq_eval_noalloc": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), vp, u64, u32, ctypes.POINTER(EvalOpts),
+                                             ctypes.POINTER(_Result), vp]),
         "rpq_profile_enable": (ctypes.c_int, [ctypes.c_int]),
         "rpq_batch_create": (ctypes.c_int, [vp, ctypes.POINTER(BatchOpts), ctypes.POINTER(vp)]),
         "rpq_batch_destroy": (ctypes.c_int, [vp]),
@@ -469,6 +473,46 @@ def rpq_eval(g: Graph, nfa: Nfa, sources=None, flags: int = 0, opts=None, pairs=
             ws_bytes = int(res.workspace_needed)
             continue
         break
+    _check(rc, allow=(RPQ_EOVERFLOW,) if allow_overflow else ())
+    out_pairs = pairs[: res.written] if pairs is not None else None
+    return EvalResult(int(res.count), int(res.hash), int(res.product_edges), int(res.levels), int(res.max_depth),
+                      int(res.written), out_pairs, per_source, rc)
+
+
+def rpq_eval_noalloc(g: Graph, nfa: Nfa, sources=None, flags: int = 0, opts=None, pairs=None,
+                     capacity: Optional[int] = None, pair_offset: int = 0, per_source=None, stream=None,
+                     allow_overflow: bool = False, max_length: Optional[int] = None) -> EvalResult:
+    """rpq_eval in the library's static device scratch (no workspace, no allocation inside the
+    call).  Arguments as rpq_eval; pairs and per_source must be caller tensors or None."""
+    torch = _torch()
+    lib = load_library()
+    if max_length is not None:
+        opts = dict(opts or {}) if not isinstance(opts, EvalOpts) else {k: getattr(opts, k) for k, _ in
+                                                                          EvalOpts._fields_}
+        opts["max_length"] = int(max_length)
+        flags |= RPQ_LENGTH_BOUND
+    if sources is None:
+        flags |= RPQ_ALL_SOURCES
+        src_t = None
+        n = rpq_graph_info_get(g)["n_vertices"]
+    else:
+        src_t = _dev_u32(sources, torch)
+        n = src_t.numel()
+    o = _opts(opts)
+    if per_source is not None:
+        flags |= RPQ_PER_SOURCE
+    if pairs is not None:
+        flags |= RPQ_PAIRS
+        if capacity is None:
+            capacity = pairs.numel()
+    res = _Result()
+    res.pairs = pairs.data_ptr() if pairs is not None else None
+    res.capacity = int(capacity or 0)
+    res.per_source = per_source.data_ptr() if per_source is not None else None
+    res.pair_offset = int(pair_offset)
+    rc = lib.rpq_eval_noalloc(g.handle, ctypes.byref(nfa), src_t.data_ptr() if (src_t is not None and n) else None,
+                              n, flags, ctypes.byref(o) if o is not None else None, ctypes.byref(res),
+                              _stream(stream))
     _check(rc, allow=(RPQ_EOVERFLOW,) if allow_overflow else ())
     out_pairs = pairs[: res.written] if pairs is not None else None
     return EvalResult(int(res.count), int(res.hash), int(res.product_edges), int(res.levels), int(res.max_depth),

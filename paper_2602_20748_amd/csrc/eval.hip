@@ -722,7 +722,7 @@ uint32_t default_width(uint64_t n_sources, uint64_t QV) {
 }
 
 int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32_t flags,
-                const rpq_eval_opts* o, Layout* Lo) {
+                const rpq_eval_opts* o, bool single_ans, Layout* Lo) {
     Layout x;
     std::memset(&x, 0, sizeof x);
     x.Q = dn.Q;
@@ -787,7 +787,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     x.off_ans = take(G * (uint64_t)x.V * x.K * 8);
     // a second Ans bitmap when there is more than one group: a group's extraction then runs on a
     // second stream while the next group's levels fill the other bitmap
-    x.off_ans2 = units > G ? take(G * (uint64_t)x.V * x.K * 8) : x.off_ans;
+    x.off_ans2 = units > G && !single_ans ? take(G * (uint64_t)x.V * x.K * 8) : x.off_ans;
     for (int p = 0; p < 2; ++p) {
         x.off_ids[p] = take(x.list_cap * 4);
         x.off_rows[p] = take(x.list_cap * x.K * 8);
@@ -907,9 +907,10 @@ Profiler& profiler() {
 }
 
 template <int K>
-int launch_level(const Args& a, int p, uint64_t n_rows, uint32_t level, int count_work, hipStream_t s) {
+int launch_level(const Args& a, int p, uint64_t n_rows, uint32_t level, int count_work, bool may_profile,
+                 hipStream_t s) {
     Profiler& pr = profiler();
-    const bool on = pr.on;
+    const bool on = may_profile && pr.on;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
     if (on) {
         std::lock_guard<std::mutex> lk(pr.mu);
@@ -1021,7 +1022,7 @@ int launch_extract(const Args& a, bool write, const uint32_t* sources, uint64_t 
     }
 
 int prepare(rpq_graph_t g, const rpq_nfa* nfa_in, uint64_t n_sources, uint32_t flags, const rpq_eval_opts* opts,
-            rpq_nfa* eff, DevNfa* dn, Layout* lay) {
+            rpq_nfa* eff, DevNfa* dn, Layout* lay, bool single_ans = false) {
     if (!g) {
         rpq::set_error("graph is NULL");
         return RPQ_EINVAL;
@@ -1046,7 +1047,7 @@ int prepare(rpq_graph_t g, const rpq_nfa* nfa_in, uint64_t n_sources, uint32_t f
     if (flags & RPQ_REVERSE) RPQ_TRY(rpq_nfa_reverse(nfa_in, eff));
     else *eff = *nfa_in;
     to_dev_nfa(eff, g->L, dn);
-    return make_layout(g, *dn, n_sources, flags, opts, lay);
+    return make_layout(g, *dn, n_sources, flags, opts, single_ans, lay);
 }
 
 }  // namespace
@@ -1084,11 +1085,15 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
 
 }  // extern "C"
 
-namespace rpq {
+namespace {
 
-int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
+// The plain evaluation.  With noalloc the call creates nothing: counters are read into a
+// pageable stack buffer instead of the thread's pinned staging buffer, extraction stays on the
+// caller's stream (the layout then holds a single answer bitmap), and no profiling events are
+// recorded.
+int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
               const rpq_eval_opts* opts, const uint64_t* target, void* workspace, uint64_t workspace_bytes,
-              rpq_result* res, hipStream_t stream) {
+              rpq_result* res, hipStream_t stream, bool noalloc) {
     if (!res) {
         rpq::set_error("result is NULL");
         return RPQ_EINVAL;
@@ -1130,12 +1135,12 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
             return RPQ_EINVAL;
         }
         const uint64_t max_len = (flags & RPQ_LENGTH_BOUND) ? (uint64_t)opts->max_length : ~0ull;
-        return sparse_eval(g, nfa, sources, n_sources, flags, max_len, workspace, workspace_bytes, res, stream);
+        return rpq::sparse_eval(g, nfa, sources, n_sources, flags, max_len, workspace, workspace_bytes, res, stream);
     }
     rpq_nfa eff;
     DevNfa dn;
     Layout x;
-    RPQ_TRY(prepare(g, nfa, n_sources, flags, opts, &eff, &dn, &x));
+    RPQ_TRY(prepare(g, nfa, n_sources, flags, opts, &eff, &dn, &x, noalloc));
     if (!workspace || workspace_bytes < x.total) {
         rpq::set_error("workspace of %llu bytes is smaller than the %llu bytes needed",
                        (unsigned long long)workspace_bytes, (unsigned long long)x.total);
@@ -1153,7 +1158,8 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     char* ws = reinterpret_cast<char*>(workspace);
     Args a = make_args(g, flags, x, ws);
     a.target = target;
-    uint64_t* stage = rpq::host_stage();
+    uint64_t local_stage[C_NCOUNTERS];
+    uint64_t* stage = noalloc ? local_stage : rpq::host_stage();
     if (!stage) {
         rpq::set_error("pinned host staging memory is unavailable");
         return RPQ_EDEVICE;
@@ -1185,7 +1191,7 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     // instruction stream.  Events order each bitmap's reuse and the final join.
     uint64_t* const ans_buf[2] = {reinterpret_cast<uint64_t*>(ws + x.off_ans),
                                   reinterpret_cast<uint64_t*>(ws + x.off_ans2)};
-    const bool overlap = n_groups > 1 && x.off_ans2 != x.off_ans;
+    const bool overlap = n_groups > 1 && x.off_ans2 != x.off_ans && !noalloc;
     SideStream side(overlap);
     hipStream_t xs = side.stream ? side.stream : stream;
     for (uint64_t grp = 0; grp < n_groups; ++grp) {
@@ -1217,14 +1223,14 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
             uint32_t n_launch = 0;
             for (; n_launch < x.sync_every && level <= x.max_len; ++n_launch) {
                 RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_level<KK>(a, p, n_rows, (uint32_t)level, level < x.max_len,
-                                                              stream)));
+                                                              !noalloc, stream)));
                 p ^= 1;
                 ++level;
             }
             launched += n_launch;
             RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
             RPQ_HIP(hipStreamSynchronize(stream));
-            if (profiler().on) profile_resolve();
+            if (!noalloc && profiler().on) profile_resolve();
             if (stage[C_ERR] & (ERR_LIST | ERR_DESC)) {
                 rpq::set_error("internal capacity exceeded (flags 0x%llx)", (unsigned long long)stage[C_ERR]);
                 return RPQ_EDEVICE;
@@ -1267,7 +1273,7 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     }
     RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
     RPQ_HIP(hipStreamSynchronize(stream));
-    {
+    if (!noalloc) {
         Profiler& pr = profiler();
         std::lock_guard<std::mutex> lk(pr.mu);
         if (pr.on) {
@@ -1297,9 +1303,96 @@ int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     return RPQ_OK;
 }
 
+// Static scratch of the allocation-free entry point: a file-scope device array, one copy per
+// device, held until the process ends.  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress, once per device, and only that address is used.
+constexpr uint64_t kScratchBytes = RPQ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+void* scratch_address() {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        rpq::set_error("no current HIP device (or device id beyond %d)", kMaxDevices - 1);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            rpq::set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+            return nullptr;
+        }
+        addr[dev] = p;
+    }
+    return addr[dev];
+}
+
+}  // namespace
+
+namespace rpq {
+
+int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
+              const rpq_eval_opts* opts, const uint64_t* target, void* workspace, uint64_t workspace_bytes,
+              rpq_result* res, hipStream_t stream) {
+    return eval_core(g, nfa, sources, n_sources, flags, opts, target, workspace, workspace_bytes, res, stream,
+                     false);
+}
+
 }  // namespace rpq
 
 extern "C" {
+
+int rpq_eval_noalloc(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources,
+                     uint32_t flags, const rpq_eval_opts* opts, rpq_result* res, hipStream_t stream) {
+    rpq::clear_error();
+    if (flags & RPQ_SPARSE) {
+        rpq::set_error("rpq_eval_noalloc runs the bitmap search only; RPQ_SPARSE is not supported");
+        return RPQ_EUNSUPPORTED;
+    }
+    if (!res) {
+        rpq::set_error("result is NULL");
+        return RPQ_EINVAL;
+    }
+    if ((flags & RPQ_LENGTH_BOUND) && !opts) {
+        rpq::set_error("RPQ_LENGTH_BOUND needs opts->max_length");
+        return RPQ_EINVAL;
+    }
+    uint64_t n = n_sources;
+    if (g && (flags & RPQ_ALL_SOURCES) && n == 0) n = g->V;
+    // the plan: the caller's knobs, with the unset ones narrowed until the workspace fits the
+    // scratch (fewer units in flight first, then narrower units)
+    rpq_eval_opts o{};
+    if (opts) o = *opts;
+    rpq_nfa eff;
+    DevNfa dn;
+    Layout lay;
+    for (;;) {
+        RPQ_TRY(prepare(g, nfa, n, flags, &o, &eff, &dn, &lay, true));
+        if (lay.total <= kScratchBytes) break;
+        if (!(opts && opts->concurrency) && lay.G > 1) {
+            o.batch_width = lay.W;
+            o.concurrency = lay.G / 2;
+        } else if (!(opts && opts->batch_width) && lay.W > 64) {
+            o.batch_width = lay.W / 2;
+            o.concurrency = (opts && opts->concurrency) ? opts->concurrency : 0;
+        } else {
+            rpq::set_error("the evaluation needs %llu bytes of workspace; the static scratch holds %llu",
+                           (unsigned long long)lay.total, (unsigned long long)kScratchBytes);
+            res->workspace_needed = lay.total;
+            return RPQ_ENOMEM;
+        }
+    }
+    void* ws = scratch_address();
+    if (!ws) return RPQ_EDEVICE;
+    const int rc = eval_core(g, nfa, sources, n_sources, flags, &o, nullptr, ws, kScratchBytes, res, stream, true);
+    if (rc != RPQ_OK && rc != RPQ_EOVERFLOW) (void)hipStreamSynchronize(stream);
+    return rc;
+}
 
 int rpq_profile_enable(int on) {
     Profiler& pr = profiler();
