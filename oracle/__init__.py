@@ -70,6 +70,8 @@ def _load():
             lib = ctypes.CDLL(_LIB_PATH)
             lib.oracle_mix64.restype = ctypes.c_uint64
             lib.oracle_mix64.argtypes = [ctypes.c_uint64]
+            lib.oracle_hash_keys.restype = ctypes.c_uint64
+            lib.oracle_hash_keys.argtypes = [_u64p, ctypes.c_uint64]
             lib.oracle_graph_build.restype = ctypes.c_uint64
             lib.oracle_graph_build.argtypes = [ctypes.c_uint32, ctypes.c_uint64, _u32p, _u8p, _u32p,
                                                _u64p, _u32p, _u32p]
@@ -88,6 +90,12 @@ def _ptr(a: np.ndarray, t):
 
 def mix64(x: int) -> int:
     return int(_load().oracle_mix64(ctypes.c_uint64(int(x) & 0xFFFFFFFFFFFFFFFF)))
+
+
+def hash_keys(keys) -> int:
+    """Checksum of a key array: sum of mix64(key) modulo 2^64 (the result hash of a pair set)."""
+    a = np.ascontiguousarray(keys).view(np.uint64)
+    return int(_load().oracle_hash_keys(_ptr(a, _u64p), a.size))
 
 
 class OracleGraph:

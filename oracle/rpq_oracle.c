@@ -47,6 +47,14 @@ static uint64_t oracle_splitmix64_output(uint64_t state)
 
 uint64_t oracle_mix64(uint64_t x) { return oracle_splitmix64_output(x); }
 
+/* Checksum of a key sequence: the sum of mix64(key) modulo 2^64 (order-free). */
+uint64_t oracle_hash_keys(const uint64_t* keys, uint64_t n)
+{
+    uint64_t h = 0;
+    for (uint64_t i = 0; i < n; ++i) h += oracle_splitmix64_output(keys[i]);
+    return h;
+}
+
 static int cmp_u64(const void* a, const void* b)
 {
     uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;

@@ -120,6 +120,19 @@ def test_mix64_matches_published_splitmix64_outputs():
     assert mix64((2 * gamma) & 0xFFFFFFFFFFFFFFFF) == 0x06C45D188009454F
 
 
+def test_hash_keys_is_the_sum_of_the_published_outputs():
+    # keys 0, gamma, 2*gamma give the three published outputs; their checksum is their sum mod 2^64,
+    # whatever the order, and the empty sequence sums to 0
+    from oracle import hash_keys
+    gamma = 0x9E3779B97F4A7C15
+    want = (0xE220A8397B1DCDAF + 0x6E789E6AA1B965F4 + 0x06C45D188009454F) & 0xFFFFFFFFFFFFFFFF
+    keys = np.array([0, gamma, (2 * gamma) & 0xFFFFFFFFFFFFFFFF], dtype=np.uint64)
+    assert hash_keys(keys) == want
+    assert hash_keys(keys[::-1].copy()) == want
+    assert hash_keys(np.zeros(0, dtype=np.uint64)) == 0
+    assert hash_keys(np.array([5, 5], dtype=np.uint64)) == (2 * mix64(5)) & 0xFFFFFFFFFFFFFFFF
+
+
 # ------------------------------------------------------------------------------------------------
 # the paper's worked example (Section 1 footnote 1, Table 1, Sections 2.4, 3, 4)
 # ------------------------------------------------------------------------------------------------
