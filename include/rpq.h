@@ -62,7 +62,8 @@ typedef enum {
     RPQ_ENOMEM = -2,       /* workspace too small, or a device allocation failed */
     RPQ_EOVERFLOW = -3,    /* output capacity too small; see rpq_result */
     RPQ_EDEVICE = -4,      /* a HIP call failed; the message carries the HIP error string */
-    RPQ_EUNSUPPORTED = -5  /* valid request the library does not support (e.g. > 32 states) */
+    RPQ_EUNSUPPORTED = -5, /* valid request the library does not support (e.g. > 32 states) */
+    RPQ_ECANCELED = -6     /* the caller's pair sink asked rpq_eval_stream to stop */
 } rpq_status;
 
 /* Thread-local message describing the last failure on this thread ("" if none). */
@@ -287,6 +288,45 @@ int rpq_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_
  */
 int rpq_eval_noalloc(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources,
                      uint32_t flags, const rpq_eval_opts* opts, rpq_result* result, hipStream_t stream);
+
+/*
+ * Streaming result pairs (Section 6.1: the unified result buffer is split into chunks that are
+ * drained to host memory while the traversal goes on, alternating between two buffers so that the
+ * transfer of one overlaps the exploration that fills the other).
+ *
+ * Called once per chunk on the thread that called rpq_eval_stream, in ascending key order: the
+ * concatenation of every chunk is the sorted, distinct key sequence (src << 32) | dst of the whole
+ * result.  `keys` points into host_chunks and is valid only until the sink returns.  A non-zero
+ * return stops the evaluation (RPQ_ECANCELED).
+ */
+typedef int (*rpq_pair_sink)(const uint64_t* keys, uint64_t n_keys, void* user);
+
+typedef struct {
+    uint64_t* device_chunks;   /* device, 2 * chunk_keys keys, caller-owned */
+    uint64_t* host_chunks;     /* pinned host memory (hipHostMalloc or equivalent), 2 * chunk_keys
+                                  keys, caller-owned */
+    uint64_t chunk_keys;       /* keys per chunk, >= 1 */
+    rpq_pair_sink sink;
+    void* user;                /* passed to sink */
+} rpq_pair_stream;
+
+/*
+ * rpq_eval with the result keys streamed to host memory instead of written to one device
+ * buffer: there is no capacity limit and no second traversal.  Per group of units (see rpq_eval)
+ * the keys are counted, then written window by window into the two device chunks in turn; each
+ * chunk is copied to its host chunk on a copy stream and handed to the sink.  While the sink runs
+ * and the copies go on, the next window is extracted and the next group's levels run.
+ * Arguments as rpq_eval (RPQ_PAIRS is implied; result->pairs and capacity are ignored); size the
+ * workspace with rpq_eval_workspace_size(..., flags | RPQ_PAIRS, ...).  On return result->count,
+ * hash, per_source (with RPQ_PER_SOURCE) and written (keys delivered) are set.  Uses the thread's
+ * extraction stream (as rpq_eval) and a copy stream created per host thread on first use.
+ * Errors: as rpq_eval (RPQ_EOVERFLOW does not occur); RPQ_EINVAL for a NULL or empty stream
+ * description; RPQ_EUNSUPPORTED with RPQ_SPARSE; RPQ_ECANCELED when the sink returns non-zero (the
+ * keys delivered so far are in result->written; no work of the call is left on any stream).
+ */
+int rpq_eval_stream(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources,
+                    uint32_t flags, const rpq_eval_opts* opts, void* workspace, uint64_t workspace_bytes,
+                    const rpq_pair_stream* out, rpq_result* result, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Batched evaluation: many queries in one persistent, graph-captured launch                  */

@@ -21,9 +21,10 @@ from typing import List, Optional, Sequence
 __all__ = [
     "RpqError", "library_path", "load_library", "rpq_abi_version", "rpq_last_error", "rpq_nfa_compile",
     "rpq_nfa_reverse", "rpq_graph_create", "rpq_graph_destroy", "rpq_graph_info_get",
-    "rpq_graph_export_csr", "rpq_eval_workspace_size", "rpq_eval", "rpq_eval_noalloc", "EvalResult", "Graph",
+    "rpq_graph_export_csr", "rpq_eval_workspace_size", "rpq_eval", "rpq_eval_noalloc", "rpq_eval_stream",
+    "EvalResult", "Graph",
     "Nfa", "EvalOpts", "RPQ_NOALLOC_SCRATCH_BYTES",
-    "RPQ_OK", "RPQ_EINVAL", "RPQ_ENOMEM", "RPQ_EOVERFLOW", "RPQ_EDEVICE", "RPQ_EUNSUPPORTED",
+    "RPQ_OK", "RPQ_EINVAL", "RPQ_ENOMEM", "RPQ_EOVERFLOW", "RPQ_EDEVICE", "RPQ_EUNSUPPORTED", "RPQ_ECANCELED",
     "RPQ_BUILD_IN_CSR", "RPQ_PAIRS", "RPQ_PER_SOURCE", "RPQ_ALL_SOURCES", "RPQ_REVERSE", "RPQ_SPARSE",
     "RPQ_LENGTH_BOUND", "rpq_batch_bound_length",
     "RPQ_MAX_STATES", "RPQ_MAX_LABELS", "EXPORTED_SYMBOLS", "rpq_profile_enable", "rpq_profile_read",
@@ -37,6 +38,7 @@ __all__ = [
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
+RPQ_ECANCELED = -6
 RPQ_OK, RPQ_EINVAL, RPQ_ENOMEM, RPQ_EOVERFLOW, RPQ_EDEVICE, RPQ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RPQ_BUILD_IN_CSR = 1
 RPQ_PAIRS, RPQ_PER_SOURCE, RPQ_ALL_SOURCES, RPQ_REVERSE, RPQ_SPARSE, RPQ_LENGTH_BOUND = 1, 2, 4, 8, 16, 32
@@ -44,7 +46,7 @@ RPQ_MAX_STATES, RPQ_MAX_LABELS = 32, 64
 RPQ_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 _STATUS = {0: "RPQ_OK", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM", -3: "RPQ_EOVERFLOW", -4: "RPQ_EDEVICE",
-           -5: "RPQ_EUNSUPPORTED"}
+           -5: "RPQ_EUNSUPPORTED", -6: "RPQ_ECANCELED"}
 
 
 class RpqError(RuntimeError):
@@ -97,6 +99,14 @@ class BatchInfo(ctypes.Structure):
                 ("finalized_words", ctypes.c_uint64), ("touch_words", ctypes.c_uint64), ("row_words", ctypes.c_uint64),
                 ("last_run_ms", ctypes.c_double), ("last_kernel_ms", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 8)]
+
+
+PairSink = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64, ctypes.c_void_p)
+
+
+class _PairStream(ctypes.Structure):
+    _fields_ = [("device_chunks", ctypes.c_void_p), ("host_chunks", ctypes.c_void_p), ("chunk_keys", ctypes.c_uint64),
+                ("sink", PairSink), ("user", ctypes.c_void_p)]
 
 
 class _Result(ctypes.Structure):
@@ -162,7 +172,7 @@ class ServerStats(ctypes.Structure):
 EXPORTED_SYMBOLS = [
     "rpq_last_error", "rpq_abi_version", "rpq_graph_create", "rpq_graph_destroy", "rpq_graph_info_get",
     "rpq_graph_export_csr", "rpq_nfa_compile", "rpq_nfa_reverse", "rpq_eval_workspace_size", "rpq_eval",
-    "rpq_eval_noalloc", "rpq_profile_enable", "rpq_profile_read",
+    "rpq_eval_noalloc", "rpq_eval_stream", "rpq_profile_enable", "rpq_profile_read",
     "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size", "rpq_batch_run",
     "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune", "rpq_batch_bound_length",
     "crpq_eval", "rpq_serve_start", "rpq_serve_submit", "rpq_serve_poll", "rpq_serve_wait", "rpq_serve_clock_ms",
@@ -202,6 +212,8 @@ def load_library():
                                     ctypes.POINTER(_Result), vp]),
         "rpq_eval_noalloc": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), vp, u64, u32, ctypes.POINTER(EvalOpts),
                                              ctypes.POINTER(_Result), vp]),
+        "rpq_eval_stream": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), vp, u64, u32, ctypes.POINTER(EvalOpts), vp, u64,
+                                            ctypes.POINTER(_PairStream), ctypes.POINTER(_Result), vp]),
         "rpq_profile_enable": (ctypes.c_int, [ctypes.c_int]),
         "rpq_batch_create": (ctypes.c_int, [vp, ctypes.POINTER(BatchOpts), ctypes.POINTER(vp)]),
         "rpq_batch_destroy": (ctypes.c_int, [vp]),
@@ -477,6 +489,63 @@ def rpq_eval(g: Graph, nfa: Nfa, sources=None, flags: int = 0, opts=None, pairs=
     out_pairs = pairs[: res.written] if pairs is not None else None
     return EvalResult(int(res.count), int(res.hash), int(res.product_edges), int(res.levels), int(res.max_depth),
                       int(res.written), out_pairs, per_source, rc)
+
+
+def rpq_eval_stream(g: Graph, nfa: Nfa, sink, sources=None, flags: int = 0, opts=None, chunk_keys: int = 1 << 20,
+                    per_source=None, workspace=None, stream=None, max_length: Optional[int] = None) -> EvalResult:
+    """Evaluate one RPQ and stream its sorted keys to `sink(keys)`, a numpy uint64 view of one chunk
+    (valid only during the call; copy what you keep).  sink returns None/False to go on, True to stop
+    (RPQ_ECANCELED).  Chunk buffers: two device chunks (torch) and two pinned host chunks of
+    chunk_keys keys each, allocated here; the library allocates nothing for them.
+    Returns the EvalResult with written = keys delivered."""
+    import numpy as np
+    torch = _torch()
+    lib = load_library()
+    if max_length is not None:
+        opts = dict(opts or {}) if not isinstance(opts, EvalOpts) else {k: getattr(opts, k) for k, _ in
+                                                                          EvalOpts._fields_}
+        opts["max_length"] = int(max_length)
+        flags |= RPQ_LENGTH_BOUND
+    if sources is None:
+        flags |= RPQ_ALL_SOURCES
+        src_t = None
+        n = rpq_graph_info_get(g)["n_vertices"]
+    else:
+        src_t = _dev_u32(sources, torch)
+        n = src_t.numel()
+    o = _opts(opts)
+    if per_source is True:
+        per_source = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+    if per_source is not None:
+        flags |= RPQ_PER_SOURCE
+    need = ctypes.c_uint64()
+    _check(lib.rpq_eval_workspace_size(g.handle, ctypes.byref(nfa), n, flags | RPQ_PAIRS,
+                                       ctypes.byref(o) if o is not None else None, ctypes.byref(need)))
+    ws = workspace if workspace is not None else g.workspace(int(need.value))
+    dev_chunks = torch.empty(2 * int(chunk_keys), dtype=torch.int64, device="cuda")
+    host_chunks = torch.empty(2 * int(chunk_keys), dtype=torch.int64, pin_memory=True)
+    errors = []
+
+    def _cb(ptr, n_keys, _user):
+        try:
+            keys = np.ctypeslib.as_array(ptr, shape=(int(n_keys),))
+            return 1 if sink(keys) else 0
+        except BaseException as e:   # an exception stops the evaluation and is raised afterwards
+            errors.append(e)
+            return 1
+
+    cb = PairSink(_cb)
+    out = _PairStream(dev_chunks.data_ptr(), host_chunks.data_ptr(), int(chunk_keys), cb, None)
+    res = _Result()
+    res.per_source = per_source.data_ptr() if per_source is not None else None
+    rc = lib.rpq_eval_stream(g.handle, ctypes.byref(nfa), src_t.data_ptr() if (src_t is not None and n) else None, n,
+                             flags, ctypes.byref(o) if o is not None else None, ws.data_ptr(), ws.numel(),
+                             ctypes.byref(out), ctypes.byref(res), _stream(stream))
+    if errors:
+        raise errors[0]
+    _check(rc)
+    return EvalResult(int(res.count), int(res.hash), int(res.product_edges), int(res.levels), int(res.max_depth),
+                      int(res.written), None, per_source, rc)
 
 
 def rpq_eval_noalloc(g: Graph, nfa: Nfa, sources=None, flags: int = 0, opts=None, pairs=None,

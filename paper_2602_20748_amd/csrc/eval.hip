@@ -513,6 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_extract(Args a, const uint32_t* __re
         const uint32_t vend = min(V, vbeg + chunk_v);
         bool valid[KP];
         uint64_t skey[KP], cnt[KP], h[KP], cursor[KP];
+        bool in_window = !WRITE;
 #pragma unroll
         for (int u = 0; u < KP; ++u) {
             const uint64_t si = (uint64_t)slot * W + (uint64_t)(kp * KP + u) * 64 + lane;
@@ -520,8 +521,17 @@ __global__ __launch_bounds__(kBlock) void k_extract(Args a, const uint32_t* __re
             valid[u] = gi < n_sources;
             skey[u] = (valid[u] ? (sources ? (uint64_t)sources[gi] : gi) : 0) << 32;
             cnt[u] = h[u] = cursor[u] = 0;
-            if (WRITE && valid[u]) cursor[u] = srcbase[si] + partial[si * nchunks + chunk];
+            if (WRITE && valid[u]) {
+                // this source's keys in this vertex chunk are [cursor, end): partial holds the
+                // source's chunk prefixes, acc its total
+                const uint32_t* pp = partial + si * nchunks;
+                cursor[u] = srcbase[si] + pp[chunk];
+                const uint64_t end = srcbase[si] + (chunk + 1 < nchunks ? (uint64_t)pp[chunk + 1] : acc[2 * si]);
+                in_window |= end > pair_off && cursor[u] < pair_off + capacity;
+            }
         }
+        // a wave none of whose keys fall in the output window has nothing to write
+        if (WRITE && __ballot(in_window) == 0) continue;
         for (uint32_t v0 = vbeg; v0 < vend; v0 += 64) {
             const uint32_t vv = v0 + lane;
             uint64_t word[KP];
@@ -1021,6 +1031,190 @@ int launch_extract(const Args& a, bool write, const uint32_t* sources, uint64_t 
         default: rpq::set_error("bad batch width"); return RPQ_EINVAL; \
     }
 
+// A copy stream per host thread and device (created on first use, kept for the thread's lifetime).
+hipStream_t copy_stream() {
+    constexpr int kMaxDevices = 64;
+    static thread_local hipStream_t per_device[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    if (!per_device[dev] && hipStreamCreateWithFlags(&per_device[dev], hipStreamNonBlocking) != hipSuccess)
+        per_device[dev] = nullptr;
+    return per_device[dev];
+}
+
+// Host side of rpq_eval_stream.  A counted group's keys [next_key, end_key) are cut into windows of
+// at most chunk_keys keys; window i is extracted into device chunk i % 2 on the extraction stream,
+// copied to host chunk i % 2 on the copy stream, and handed to the sink once its copy is complete.
+// At most two windows are in flight, so a chunk is rewritten only after the sink has returned for
+// the window it held.  Windows are issued in key order and delivered in issue order.
+struct PairStreamer {
+    const rpq_pair_stream* ps = nullptr;
+    hipStream_t xs = nullptr, cs = nullptr;
+    hipEvent_t ext_done[2] = {nullptr, nullptr}, copied[2] = {nullptr, nullptr}, counted = nullptr;
+    uint64_t* gend = nullptr;   // pinned: key index at which the counted group ends
+    // the group whose windows are being issued
+    bool pending = false, end_known = false;
+    uint64_t next_key = 0, end_key = 0;
+    hipEvent_t group_done = nullptr;   // recorded on xs after the group's last window
+    Args ga;
+    const uint32_t* sources = nullptr;
+    uint64_t n_sources = 0, gbase = 0;
+    uint32_t G_eff = 0, K = 0, W = 0, nchunks = 0, chunk_v = 0;
+    unsigned long long* acc = nullptr;
+    uint32_t* partial = nullptr;
+    const uint64_t* srcbase = nullptr;
+    // windows issued and not yet delivered: a ring of two, oldest at head
+    int win_buf[2] = {0, 0};
+    uint64_t win_n[2] = {0, 0};
+    int head = 0, n_inflight = 0, next_buf = 0;
+    uint64_t delivered = 0;
+    uint64_t* written = nullptr;   // the caller's result->written, kept current
+
+    PairStreamer() = default;
+    PairStreamer(const PairStreamer&) = delete;
+    PairStreamer& operator=(const PairStreamer&) = delete;
+
+    int init(const rpq_pair_stream* p, hipStream_t extraction, uint64_t* pinned_slot, uint64_t* written_out) {
+        ps = p;
+        written = written_out;
+        xs = extraction;
+        cs = copy_stream();
+        if (!cs) cs = xs;
+        gend = pinned_slot;
+        for (int b = 0; b < 2; ++b) {
+            RPQ_HIP(hipEventCreateWithFlags(&ext_done[b], hipEventDisableTiming));
+            RPQ_HIP(hipEventCreateWithFlags(&copied[b], hipEventDisableTiming));
+        }
+        RPQ_HIP(hipEventCreateWithFlags(&counted, hipEventDisableTiming));
+        return RPQ_OK;
+    }
+    ~PairStreamer() {
+        // no work of the call outlives it, whatever the return path
+        if (cs) (void)hipStreamSynchronize(cs);
+        if (xs) (void)hipStreamSynchronize(xs);
+        for (hipEvent_t e : {ext_done[0], ext_done[1], copied[0], copied[1], counted})
+            if (e) (void)hipEventDestroy(e);
+    }
+
+    // The keys of a group whose count pass and per-source offsets are enqueued on xs; `done` is
+    // recorded on xs once its last window is issued.
+    int start_group(const Args& a, hipEvent_t done, const uint32_t* src, uint64_t n_src, uint64_t base, uint32_t G,
+                    uint32_t K_, uint32_t W_, uint32_t nch, uint32_t chv, unsigned long long* acc_,
+                    uint32_t* partial_, const uint64_t* srcbase_, const unsigned long long* pairbase) {
+        RPQ_HIP(hipMemcpyAsync(gend, pairbase, 8, hipMemcpyDeviceToHost, xs));
+        RPQ_HIP(hipEventRecord(counted, xs));
+        pending = true;
+        end_known = false;
+        next_key = end_key;   // this group's keys follow the previous group's
+        group_done = done;
+        ga = a;
+        sources = src;
+        n_sources = n_src;
+        gbase = base;
+        G_eff = G;
+        K = K_;
+        W = W_;
+        nchunks = nch;
+        chunk_v = chv;
+        acc = acc_;
+        partial = partial_;
+        srcbase = srcbase_;
+        return RPQ_OK;
+    }
+
+    int deliver_head() {
+        const int b = win_buf[head];
+        const uint64_t n = win_n[head];
+        head ^= 1;
+        --n_inflight;
+        if (ps->sink(ps->host_chunks + (uint64_t)b * ps->chunk_keys, n, ps->user) != 0) {
+            rpq::set_error("the pair sink stopped the evaluation after %llu keys", (unsigned long long)delivered);
+            return RPQ_ECANCELED;
+        }
+        delivered += n;
+        if (written) *written = delivered;
+        return RPQ_OK;
+    }
+
+    // hand every completed window to the sink; with wait, block for the oldest one first
+    int deliver(bool wait) {
+        while (n_inflight) {
+            const hipEvent_t e = copied[win_buf[head]];
+            if (wait) {
+                RPQ_HIP(hipEventSynchronize(e));
+                wait = false;
+            } else {
+                const hipError_t q = hipEventQuery(e);
+                if (q == hipErrorNotReady) break;
+                if (q != hipSuccess) {
+                    rpq::set_error("HIP error in hipEventQuery: %s", hipGetErrorString(q));
+                    return RPQ_EDEVICE;
+                }
+            }
+            RPQ_TRY(deliver_head());
+        }
+        return RPQ_OK;
+    }
+
+    int issue_window() {
+        const int b = next_buf;
+        next_buf ^= 1;
+        const uint64_t n = std::min<uint64_t>(ps->chunk_keys, end_key - next_key);
+        uint64_t* dev = ps->device_chunks + (uint64_t)b * ps->chunk_keys;
+        RPQ_DISPATCH_K(K, RPQ_TRY(launch_extract<KK>(ga, true, sources, n_sources, gbase, G_eff, W, nchunks, chunk_v,
+                                                     acc, partial, srcbase, dev, next_key, n, xs)));
+        RPQ_HIP(hipEventRecord(ext_done[b], xs));
+        RPQ_HIP(hipStreamWaitEvent(cs, ext_done[b], 0));
+        RPQ_HIP(hipMemcpyAsync(ps->host_chunks + (uint64_t)b * ps->chunk_keys, dev, n * 8, hipMemcpyDeviceToHost, cs));
+        RPQ_HIP(hipEventRecord(copied[b], cs));
+        const int slot = (head + n_inflight) & 1;
+        win_buf[slot] = b;
+        win_n[slot] = n;
+        ++n_inflight;
+        next_key += n;
+        return RPQ_OK;
+    }
+
+    // Deliver what is complete and issue what fits.  With finish, return only once every window of
+    // the pending group is issued: its Ans bitmap and per-source arrays may then be reused by work
+    // enqueued on xs after this point (or ordered after group_done).
+    int pump(bool finish) {
+        for (;;) {
+            RPQ_TRY(deliver(false));
+            if (!pending) return RPQ_OK;
+            if (!end_known) {
+                if (finish) {
+                    RPQ_HIP(hipEventSynchronize(counted));
+                } else {
+                    const hipError_t q = hipEventQuery(counted);
+                    if (q == hipErrorNotReady) return RPQ_OK;
+                    if (q != hipSuccess) {
+                        rpq::set_error("HIP error in hipEventQuery: %s", hipGetErrorString(q));
+                        return RPQ_EDEVICE;
+                    }
+                }
+                end_key = *gend;
+                end_known = true;
+            }
+            while (n_inflight < 2 && next_key < end_key) RPQ_TRY(issue_window());
+            if (next_key == end_key) {
+                if (group_done) RPQ_HIP(hipEventRecord(group_done, xs));
+                pending = false;
+                return RPQ_OK;
+            }
+            if (!finish) return RPQ_OK;
+            RPQ_TRY(deliver(true));
+        }
+    }
+
+    // every window issued and delivered
+    int drain() {
+        RPQ_TRY(pump(true));
+        while (n_inflight) RPQ_TRY(deliver(true));
+        return RPQ_OK;
+    }
+};
+
 int prepare(rpq_graph_t g, const rpq_nfa* nfa_in, uint64_t n_sources, uint32_t flags, const rpq_eval_opts* opts,
             rpq_nfa* eff, DevNfa* dn, Layout* lay, bool single_ans = false) {
     if (!g) {
@@ -1093,7 +1287,7 @@ namespace {
 // recorded.
 int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
               const rpq_eval_opts* opts, const uint64_t* target, void* workspace, uint64_t workspace_bytes,
-              rpq_result* res, hipStream_t stream, bool noalloc) {
+              rpq_result* res, hipStream_t stream, bool noalloc, const rpq_pair_stream* ps = nullptr) {
     if (!res) {
         rpq::set_error("result is NULL");
         return RPQ_EINVAL;
@@ -1112,7 +1306,7 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
         rpq::set_error("sources is NULL");
         return RPQ_EINVAL;
     }
-    if ((flags & RPQ_PAIRS) && res->capacity && !res->pairs) {
+    if (!ps && (flags & RPQ_PAIRS) && res->capacity && !res->pairs) {
         rpq::set_error("RPQ_PAIRS with a NULL pair buffer");
         return RPQ_EINVAL;
     }
@@ -1140,6 +1334,8 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     rpq_nfa eff;
     DevNfa dn;
     Layout x;
+    // streamed keys need the per-source offsets of the pairs layout
+    if (ps) flags |= RPQ_PAIRS;
     RPQ_TRY(prepare(g, nfa, n_sources, flags, opts, &eff, &dn, &x, noalloc));
     if (!workspace || workspace_bytes < x.total) {
         rpq::set_error("workspace of %llu bytes is smaller than the %llu bytes needed",
@@ -1151,7 +1347,7 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
         rpq::set_error("workspace must be 256-byte aligned");
         return RPQ_EINVAL;
     }
-    const bool want_pairs = (flags & RPQ_PAIRS) && res->pairs != nullptr;
+    const bool want_pairs = !ps && (flags & RPQ_PAIRS) && res->pairs != nullptr;
     res->written = res->count = res->hash = res->product_edges = res->levels = res->max_depth = 0;
     if (n_sources == 0) return RPQ_OK;
 
@@ -1183,8 +1379,8 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     const uint64_t per_group = (uint64_t)x.G * x.W;
     const uint64_t n_groups = (n_sources + per_group - 1) / per_group;
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws + x.off_acc);
-    uint32_t* partial = want_pairs ? reinterpret_cast<uint32_t*>(ws + x.off_partial) : nullptr;
-    uint64_t* srcbase = want_pairs ? reinterpret_cast<uint64_t*>(ws + x.off_srcbase) : nullptr;
+    uint32_t* partial = want_pairs || ps ? reinterpret_cast<uint32_t*>(ws + x.off_partial) : nullptr;
+    uint64_t* srcbase = want_pairs || ps ? reinterpret_cast<uint64_t*>(ws + x.off_srcbase) : nullptr;
     uint64_t levels_total = 0, max_depth = 0;
     // Extraction of group g runs on a second stream (xs) while the levels of group g + 1 run on
     // `stream` into the other Ans bitmap: the level kernels are bound by memory, extraction by its
@@ -1194,6 +1390,10 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     const bool overlap = n_groups > 1 && x.off_ans2 != x.off_ans && !noalloc;
     SideStream side(overlap);
     hipStream_t xs = side.stream ? side.stream : stream;
+    // streamed keys: windows of group g are extracted on xs while group g + 1's levels run; the
+    // group-end key index is read through the pinned staging buffer, past the counter words
+    PairStreamer st;
+    if (ps) RPQ_TRY(st.init(ps, xs, stage + 64, &res->written));
     for (uint64_t grp = 0; grp < n_groups; ++grp) {
         const uint64_t gbase = grp * per_group;
         const uint64_t n_here = std::min<uint64_t>(per_group, n_sources - gbase);
@@ -1229,6 +1429,7 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
             }
             launched += n_launch;
             RPQ_HIP(hipMemcpyAsync(stage, a.counters, C_NCOUNTERS * 8, hipMemcpyDeviceToHost, stream));
+            if (ps) RPQ_TRY(st.pump(false));   // the previous group's windows, while these levels run
             RPQ_HIP(hipStreamSynchronize(stream));
             if (!noalloc && profiler().on) profile_resolve();
             if (stage[C_ERR] & (ERR_LIST | ERR_DESC)) {
@@ -1252,6 +1453,9 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
             RPQ_HIP(hipEventRecord(side.leveled, stream));
             RPQ_HIP(hipStreamWaitEvent(xs, side.leveled, 0));
         }
+        // the previous group's windows read acc, partial and srcbase: all of them go on xs before
+        // this group's count pass overwrites those arrays
+        if (ps) RPQ_TRY(st.pump(true));
         RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(acc), (uint64_t)G_eff * x.W * 2, 0, xs));
         RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_extract<KK>(a, false, sources, n_sources, gbase, G_eff, x.W, x.nchunks,
                                                        x.chunk_v, acc, partial, nullptr, nullptr, 0, 0, xs)));
@@ -1264,8 +1468,15 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
                                                            x.chunk_v, acc, partial, srcbase, res->pairs,
                                                            res->pair_offset, res->capacity, xs)));
         }
-        if (side.stream) RPQ_HIP(hipEventRecord(side.extracted[buf], xs));
+        if (ps) {
+            RPQ_TRY(st.start_group(a, side.stream ? side.extracted[buf] : nullptr, sources, n_sources, gbase, G_eff,
+                                   x.K, x.W, x.nchunks, x.chunk_v, acc, partial, srcbase, a.counters + C_PAIRBASE));
+            RPQ_TRY(st.pump(false));
+        } else if (side.stream) {
+            RPQ_HIP(hipEventRecord(side.extracted[buf], xs));
+        }
     }
+    if (ps) RPQ_TRY(st.drain());
     if (side.stream) {
         // join: everything the side stream did happens before the totals are read on `stream`
         RPQ_HIP(hipEventRecord(side.leveled, xs));
@@ -1287,6 +1498,7 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
     }
     res->count = stage[C_COUNT];
     res->hash = stage[C_HASH];
+    if (ps) res->written = st.delivered;
     res->product_edges = stage[C_EPROD];
     res->levels = levels_total;
     res->max_depth = max_depth;
@@ -1391,6 +1603,24 @@ int rpq_eval_noalloc(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources,
     if (!ws) return RPQ_EDEVICE;
     const int rc = eval_core(g, nfa, sources, n_sources, flags, &o, nullptr, ws, kScratchBytes, res, stream, true);
     if (rc != RPQ_OK && rc != RPQ_EOVERFLOW) (void)hipStreamSynchronize(stream);
+    return rc;
+}
+
+int rpq_eval_stream(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources,
+                    uint32_t flags, const rpq_eval_opts* opts, void* workspace, uint64_t workspace_bytes,
+                    const rpq_pair_stream* out, rpq_result* res, hipStream_t stream) {
+    rpq::clear_error();
+    if (!out || !out->sink || !out->device_chunks || !out->host_chunks || out->chunk_keys == 0) {
+        rpq::set_error("the pair stream needs a sink, two device and two host chunks of chunk_keys >= 1 keys");
+        return RPQ_EINVAL;
+    }
+    if (flags & RPQ_SPARSE) {
+        rpq::set_error("rpq_eval_stream runs the bitmap search only; RPQ_SPARSE is not supported");
+        return RPQ_EUNSUPPORTED;
+    }
+    const int rc = eval_core(g, nfa, sources, n_sources, flags, opts, nullptr, workspace, workspace_bytes, res,
+                             stream, false, out);
+    if (rc != RPQ_OK) (void)hipStreamSynchronize(stream);
     return rc;
 }
 
