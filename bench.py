@@ -152,11 +152,15 @@ def crpq_main():
     g.close()
 
 
-def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib, max_requests, burst_requests):
+def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib, max_requests, burst_requests,
+                 resident_slots=0, resident_iters=0):
     """Requests of synth.serve_requests arrive as a Poisson stream at each rate ('burst': all at once,
     the server's capacity); latency is scheduled arrival -> completion.  The same requests then run
     one at a time (plain FIFO, no overlap) for the edges/s comparison and to check that every result
-    is the one it has alone.  Returns (points, every result identical to its result alone)."""
+    is the one it has alone.  With resident_slots, single-source RPQs run on the server's resident
+    engine (64-source units in one persistent batched kernel that takes arrivals between launches);
+    slices and CRPQs run on the worker streams.  Returns (points, every result identical to its
+    result alone)."""
     import numpy as np
     import torch
 
@@ -175,7 +179,8 @@ def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib,
         arrive = np.zeros(n) if burst else synth.poisson_arrivals(qps, n, seed=seed + 3000) * 1e3
         nfa = [rpq.rpq_nfa_compile(r[1], el.names) if r[0] != "crpq" else None for r in reqs]
         print("bench: serving %d requests at %s QPS" % (n, tok), file=sys.stderr, flush=True)
-        srv = rpq.Server(g, int(pool_gib * (1 << 30)), workers=workers)
+        srv = rpq.Server(g, int(pool_gib * (1 << 30)), workers=workers, resident_slots=resident_slots,
+                         resident_width=64, resident_max_units=1, resident_iters=resident_iters)
         last_note = time.time()
 
         def wait(t):
@@ -204,7 +209,7 @@ def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib,
             if r[0] == "crpq":
                 tickets.append(srv.submit_crpq(r[1], r[2], binding=r[3], arrival_ms=due))
             else:
-                fl = rpq.RPQ_SPARSE if r[0] == "rpq_single" else 0
+                fl = rpq.RPQ_SPARSE if (r[0] == "rpq_single" and not resident_slots) else 0
                 tickets.append(srv.submit_rpq(nfa[i], r[2], flags=fl, pairs=ring[i % len(ring)], arrival_ms=due))
             if time.time() - last_note > 10:
                 last_note = time.time()
@@ -215,6 +220,7 @@ def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib,
             if time.time() - last_note > 10:
                 last_note = time.time()
                 print("bench: completed %d / %d" % (len(done), n), file=sys.stderr, flush=True)
+        sst = srv.stats()
         srv.stop()
         del srv
         torch.cuda.empty_cache()   # the pool goes back before the FIFO replay allocates its workspaces
@@ -239,7 +245,7 @@ def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib,
                 ok = (a.count, a.hash) == (d["count"], d["hash"])
                 e = 0
             else:
-                fl = rpq.RPQ_SPARSE if r[0] == "rpq_single" else 0
+                fl = rpq.RPQ_SPARSE if (r[0] == "rpq_single" and not resident_slots) else 0
                 a = rpq.rpq_eval(g, nfa[i], r[2], flags=fl, pairs=ring[0], allow_overflow=True)
                 ok = (a.count, a.hash, a.product_edges) == (d["count"], d["hash"], d["product_edges"])
                 e = a.product_edges
@@ -256,6 +262,9 @@ def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib,
         fifo_kind = {k: round(1e3 * float(np.mean([t for r, t in zip(reqs, fifo_times) if r[0] == k] or [0.0])), 3)
                      for k in kinds}
         points.append(dict(qps="burst" if burst else qps, requests=n, measured=len(meas), mix=kinds, workers=workers,
+                           resident=dict(slots=resident_slots, completed=sst["resident_completed"],
+                                         launches=sst["resident_launches"],
+                                         gib=round(sst["resident_bytes"] / 2 ** 30, 2)),
                            service_ms_by_kind=service, fifo_ms_by_kind=fifo_kind,
                            p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
                            completed_per_s=round(len(meas) / span, 2), served_edges_per_s=ep / span,

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define RPQ_ABI_VERSION 1
+#define RPQ_ABI_VERSION 2
 
 /* Automata are epsilon-free NFAs with at most this many states, over at most
  * this many edge labels (labels are uint8 ids below n_labels). */
@@ -350,7 +350,10 @@ typedef struct {
     uint32_t slots;         /* units advanced together (0 = sized for ~64K sources in flight, <= 64 GB) */
     uint32_t chunk_edges;   /* items (edge x successor state) per work slice (0 = 16, raised while the
                                slice buffers would exceed a quarter of a slot's bitmaps) */
-    uint32_t reserved;
+    uint32_t list_share;    /* frontier lists, slice buffers and first-visit logs hold 1/list_share of
+                               the worst case (every row of every slot in one level); rows beyond wait
+                               for the next iteration, which changes no result (0 = 4, or 1 when a
+                               query is length-bounded: such queries need exact depths and require 1) */
 } rpq_batch_opts;
 
 typedef struct {
@@ -542,13 +545,32 @@ int crpq_eval(rpq_graph_t graph, const crpq_atom* atoms, uint32_t n_atoms, const
  * of the queue with the larger size.  This is the counterpart, across requests, of the paper's
  * pooled segment memory (Section 5) and of its temporary reduction of the start-vertex batch when
  * that pool runs short (ablation study, Section 8.4).
+ * With the resident engine on, dense RPQs skip the worker streams: a persistent batched kernel
+ * (rpq_batch_* form, open-ended) keeps its slots on the device and a driver thread appends each
+ * arriving request's units to the kernel's device unit queue between launches of a few
+ * iterations; idle slots take them at the next refill, so requests that arrive while others run
+ * are admitted as slots free up and their levels advance in the same launches (the counterpart of
+ * the paper's traversal queue feeding the exploration kernel, Section 4.2 and Algorithm 1).
  * Results are identical to running each request alone.
  */
 typedef struct rpq_server* rpq_server_t;
 
 typedef struct {
-    uint32_t workers;     /* requests in flight at once (0 = 4), each on its own stream */
-    uint32_t reserved;
+    uint32_t workers;          /* requests in flight at once on the worker streams (0 = 4) */
+    uint32_t reserved;         /* must be 0 */
+    /* Resident engine (0 slots = off): a persistent batched kernel whose slots stay on the
+     * device.  Dense RPQ requests it can run (automaton of at most resident_states states and
+     * resident_succ successors per (state, label); pairs only when the sources fit one unit) join
+     * its device unit queue as they arrive, between bounded launches of resident_iters
+     * iterations, and take slots as earlier units retire.  Its slot memory comes from the front
+     * of the pool; every other request runs on the worker streams in the rest of it. */
+    uint32_t resident_slots;   /* slots (units in flight) */
+    uint32_t resident_width;   /* sources per unit: 64 .. 4096, a power of two (0 = 64) */
+    uint32_t resident_states;  /* largest automaton (0 = 12) */
+    uint32_t resident_succ;    /* largest successor set per (state, label) (0 = 4) */
+    uint32_t resident_iters;   /* iterations per launch (0 = 8) */
+    uint32_t resident_max_units; /* requests of more units (sources / width, rounded up) go to the
+                                  workers, whose units can be wider (0 = no limit) */
 } rpq_server_opts;
 
 #define RPQ_REQ_RPQ  1u
@@ -581,14 +603,21 @@ typedef struct {
     int32_t status;               /* rpq_status once done (RPQ_EOVERFLOW: outputs truncated) */
     uint32_t done;                /* 0 while queued or running */
     uint64_t count, hash, product_edges, written;
-    uint64_t workspace_bytes;     /* pool bytes the request ran with */
-    double arrival_ms, start_ms, end_ms;   /* server clock */
+    uint64_t workspace_bytes;     /* pool bytes the request ran with (one slot's share on the
+                                     resident engine) */
+    double arrival_ms, start_ms, end_ms;   /* server clock; start = admitted to a worker or to the
+                                     resident engine's queue */
+    uint32_t resident;            /* 1 when the resident engine ran the request */
+    uint32_t reserved;
 } rpq_ticket;
 
 typedef struct {
     uint64_t submitted, completed, failed, queued, running;
     uint64_t pool_bytes, pool_in_use, pool_peak;
     uint64_t product_edges;       /* over completed requests */
+    uint64_t resident_completed;  /* requests the resident engine completed */
+    uint64_t resident_launches;   /* launches of the resident kernel */
+    uint64_t resident_bytes;      /* pool bytes held by the resident engine */
 } rpq_server_stats;
 
 /* Start a server on graph g with the device pool [pool, pool + pool_bytes) (256-byte aligned). */

@@ -87,7 +87,7 @@ class Profile(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("batch_width", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("list_share", ctypes.c_uint32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -145,7 +145,10 @@ RPQ_REQ_RPQ, RPQ_REQ_CRPQ = 1, 2
 
 
 class ServerOpts(ctypes.Structure):
-    _fields_ = [("workers", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+    _fields_ = [("workers", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("resident_slots", ctypes.c_uint32),
+                ("resident_width", ctypes.c_uint32), ("resident_states", ctypes.c_uint32),
+                ("resident_succ", ctypes.c_uint32), ("resident_iters", ctypes.c_uint32),
+                ("resident_max_units", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -160,12 +163,13 @@ class Ticket(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("done", ctypes.c_uint32), ("count", ctypes.c_uint64),
                 ("hash", ctypes.c_uint64), ("product_edges", ctypes.c_uint64), ("written", ctypes.c_uint64),
                 ("workspace_bytes", ctypes.c_uint64), ("arrival_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
-                ("end_ms", ctypes.c_double)]
+                ("end_ms", ctypes.c_double), ("resident", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "queued", "running",
-                                                "pool_bytes", "pool_in_use", "pool_peak", "product_edges")]
+                                                "pool_bytes", "pool_in_use", "pool_peak", "product_edges",
+                                                "resident_completed", "resident_launches", "resident_bytes")]
 
 
 # Every symbol include/rpq.h declares (checked by the CPU test suite).
@@ -881,22 +885,32 @@ def crpq_eval(g: Graph, atoms, n_vars: int, binding=None, vertex_label=None, dom
 def _ticket_dict(t: Ticket) -> dict:
     return dict(status=int(t.status), done=bool(t.done), count=int(t.count), hash=int(t.hash),
                 product_edges=int(t.product_edges), written=int(t.written), workspace_bytes=int(t.workspace_bytes),
-                arrival_ms=float(t.arrival_ms), start_ms=float(t.start_ms), end_ms=float(t.end_ms))
+                arrival_ms=float(t.arrival_ms), start_ms=float(t.start_ms), end_ms=float(t.end_ms),
+                resident=bool(t.resident))
 
 
 class Server:
     """A request loop over one resident graph (rpq_serve_* in include/rpq.h).
 
     The device pool is one torch allocation of pool_bytes held by the server; requests run on
-    `workers` streams as the pool admits them.  Tensors a request names (sources, outputs,
-    domains) are kept alive until its ticket is collected with wait() or a done poll()."""
+    `workers` streams as the pool admits them, or on the resident engine (resident_slots > 0)
+    for the dense RPQs it takes.  Tensors a request names (sources, outputs, domains) are kept
+    alive until its ticket is collected with wait() or a done poll()."""
 
-    def __init__(self, g: Graph, pool_bytes: int, workers: int = 4):
+    def __init__(self, g: Graph, pool_bytes: int, workers: int = 4, resident_slots: int = 0,
+                 resident_width: int = 0, resident_states: int = 0, resident_succ: int = 0,
+                 resident_iters: int = 0, resident_max_units: int = 0):
         torch = _torch()
         self.g = g
         self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
         o = ServerOpts()
         o.workers = int(workers)
+        o.resident_slots = int(resident_slots)
+        o.resident_width = int(resident_width)
+        o.resident_states = int(resident_states)
+        o.resident_succ = int(resident_succ)
+        o.resident_iters = int(resident_iters)
+        o.resident_max_units = int(resident_max_units)
         h = ctypes.c_void_p()
         _check(load_library().rpq_serve_start(g.handle, ctypes.byref(o), self.pool.data_ptr(), self.pool.numel(),
                                               ctypes.byref(h)))

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -60,14 +61,15 @@ struct BQuery {
     uint64_t* per_source;      // device [n][2] or null
     uint64_t* pairs;           // device output or null
     uint64_t capacity;
-    uint64_t stage_off;        // first staging key of this query
+    uint64_t* stage;           // device: where this query's units put their keys (staging, or the
+                               // output itself for a single-unit query of the open form)
     uint32_t first_unit, n_units;
     uint32_t flags;
     uint32_t max_len;          // length bound: the deepest depth recorded (0xFFFFFFFF = none)
 };
 
 struct BQueryOut {
-    unsigned long long count, hash, eprod, stage_top, max_depth, overflow, levels, pad;
+    unsigned long long count, hash, eprod, stage_top, max_depth, overflow, levels, units_done;
 };
 
 struct BUnit {
@@ -84,7 +86,8 @@ struct BSlot {
 struct BCtl {
     rpqd::GridSync gs;
     unsigned long long list_cnt[2], desc_cnt[2];
-    unsigned long long queue_head;
+    unsigned long long queue_head;      // units handed to slots
+    unsigned long long units_tail;      // open form: units published by the host
     unsigned long long n_running, n_retiring, n_pairs_retiring;
     unsigned long long err, iterations;
     unsigned long long items, descs, wreads, wupds;
@@ -124,6 +127,12 @@ struct BArgs {
     uint64_t* unit_start;    // [n_units] staging index (query-relative) of each unit's keys
     uint32_t V, L, Qmax, H, G, W, nchunks, n_units, n_queries, n_blocks;
     uint64_t slot_stride, summ_words, list_cap, desc_cap, timeout, deadline;
+    uint64_t log_cap;        // first-visit log entries per slot
+    // open form (a resident engine fed between launches): the unit queue is a ring of unit_mask + 1
+    // entries whose tail the host publishes in ctl->units_tail, and a launch ends after max_iters
+    // iterations with its state kept for the next one.  Closed form: unit_mask = ~0, max_iters = 0.
+    uint32_t open_form, max_iters;
+    uint64_t unit_mask;
 };
 
 __device__ __forceinline__ unsigned long long ld(const unsigned long long* p) {
@@ -308,10 +317,10 @@ __device__ void phase_compact(const BArgs& a, int p, uint32_t iter) {
     for (uint64_t w0 = gwave(a) * 64; w0 < n_words; w0 += gwaves(a) * 64) {
         const uint64_t wi = w0 + lane;
         uint64_t tw = wi < n_words ? xld(a.touch + wi) : 0;
+        const uint64_t tw0 = tw;
         const uint32_t slot = (uint32_t)(wi / words_per_slot);
         uint64_t first = 0;   // rows touched for the first time in their unit
         if (tw) {
-            a.touch[wi] = 0;
             if (ld32(&a.slots[slot].alive) != iter) st32(&a.slots[slot].alive, iter);
             const uint64_t ev = xld(a.ever + wi);
             first = tw & ~ev;
@@ -335,11 +344,11 @@ __device__ void phase_compact(const BArgs& a, int p, uint32_t iter) {
                 li = atomicAdd(&a.slots[slot].log_n, (unsigned long long)fc);
             }
             const uint64_t lbase = (wi - (uint64_t)slot * words_per_slot) * 64;
-            uint32_t* log = a.logs + (uint64_t)slot * a.slot_stride;
+            uint32_t* log = a.logs + (uint64_t)slot * a.log_cap;
             while (first) {
                 const int bt = __ffsll((long long)first) - 1;
                 first &= first - 1;
-                if (li < a.slot_stride) log[li] = (uint32_t)(lbase + bt);
+                if (li < a.log_cap) log[li] = (uint32_t)(lbase + bt);   // beyond: the slot is cleared whole
                 ++li;
             }
         }
@@ -351,12 +360,19 @@ __device__ void phase_compact(const BArgs& a, int p, uint32_t iter) {
         if (lane == 0) base = atomicAdd(&a.ctl->list_cnt[np], (unsigned long long)tot);
         base = __shfl(base, 0, 64);
         uint64_t pos = base + incl - c;
+        uint64_t left = 0;   // rows with no room in the list: they keep their touch bit (and Next)
         while (tw) {
             const int bt = __ffsll((long long)tw) - 1;
             tw &= tw - 1;
             if (pos < a.list_cap) ids[pos] = (uint32_t)(wi * 64 + bt);
-            else atomicOr(&a.ctl->err, 1ull);
+            else left |= 1ull << bt;
             ++pos;
+        }
+        if (tw0) {
+            a.touch[wi] = left;
+            // a row left for the next iteration reaches its level late: exact depths are lost, so a
+            // length-bounded query cannot wait
+            if (left && a.queries[ld32(&a.slots[slot].query)].max_len != 0xFFFFFFFFu) atomicOr(&a.ctl->err, 1ull);
         }
     }
 }
@@ -399,7 +415,7 @@ __device__ void phase_retire_extract(const BArgs& a, uint32_t n_ret) {
         const uint32_t k = (uint32_t)((wv / a.nchunks) % K);
         const uint32_t slot = ld32(&a.retiring[wv / ((uint64_t)a.nchunks * K)]);
         const uint32_t u = ld32(&a.slots[slot].unit);
-        const BUnit unit = a.units[u];
+        const BUnit unit = a.units[u & a.unit_mask];
         const BQuery& Qy = a.queries[unit.query];
         if (WRITE && !Qy.pairs) continue;
         const uint32_t j = k * 64 + lane;
@@ -431,7 +447,7 @@ __device__ void phase_retire_extract(const BArgs& a, uint32_t n_ret) {
                 if (valid && ((word >> lane) & 1)) {
                     const uint64_t key = (s << 32) | v;
                     if (WRITE) {
-                        if (cursor < Qy.capacity) a.stage[Qy.stage_off + cursor] = key;
+                        if (cursor < Qy.capacity) Qy.stage[cursor] = key;
                         ++cursor;
                     } else {
                         ++cnt;
@@ -463,7 +479,7 @@ __device__ void phase_retire_prefix(const BArgs& a, uint32_t n_ret) {
     for (uint32_t r = blockIdx.x; r < n_ret; r += a.n_blocks) {
         const uint32_t slot = ld32(&a.retiring[r]);
         const uint32_t u = ld32(&a.slots[slot].unit);
-        const BUnit unit = a.units[u];
+        const BUnit unit = a.units[u & a.unit_mask];
         const BQuery& Qy = a.queries[unit.query];
         if (!Qy.pairs) continue;   // uniform per block
         if (t == 0) s_carry = 0;
@@ -499,8 +515,8 @@ __device__ void phase_retire_prefix(const BArgs& a, uint32_t n_ret) {
         if (t == 0) {
             const uint64_t tot = s_carry;
             const unsigned long long st = atomicAdd(&a.qout[unit.query].stage_top, (unsigned long long)tot);
-            a.unit_total[u] = tot;
-            a.unit_start[u] = st;
+            a.unit_total[u & a.unit_mask] = tot;
+            a.unit_start[u & a.unit_mask] = st;
             if (st + tot > Qy.capacity) atomicOr(&a.qout[unit.query].overflow, 1ull);
             s_base = st;
         }
@@ -520,8 +536,16 @@ __device__ void phase_retire_clear(const BArgs& a, uint32_t n_ret) {
         const uint64_t wps = a.slot_stride / 64;
         for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < wps; i += (uint64_t)a.n_blocks * kBlock)
             a.ever[(uint64_t)slot * wps + i] = 0;
-        const uint64_t n = min((uint64_t)ld(&a.slots[slot].log_n), a.slot_stride);
-        const uint32_t* log = a.logs + (uint64_t)slot * a.slot_stride;
+        const uint64_t n = ld(&a.slots[slot].log_n);
+        if (n > a.log_cap) {
+            // the log overflowed: clear every row of the slot
+            uint64_t* vs = a.vis + (uint64_t)slot * a.slot_stride * K;
+            const uint64_t words = a.slot_stride * K;
+            for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += (uint64_t)a.n_blocks * kBlock)
+                vs[i] = 0;
+            continue;
+        }
+        const uint32_t* log = a.logs + (uint64_t)slot * a.log_cap;
         for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)a.n_blocks * kBlock) {
             uint64_t* vs = a.vis + ((uint64_t)slot * a.slot_stride + xld(log + i)) * K;
 #pragma unroll
@@ -552,26 +576,39 @@ __device__ void phase_retire_clear(const BArgs& a, uint32_t n_ret) {
 // refill (block 0 assigns units to idle slots), then every block seeds the new units
 // ------------------------------------------------------------------------------------------------
 __device__ void phase_assign(const BArgs& a, uint32_t iter) {
-    __shared__ uint32_t s_running;
-    if (threadIdx.x == 0) s_running = 0;
+    __shared__ uint32_t s_running, s_idle;
+    __shared__ unsigned long long s_head, s_avail;
+    if (threadIdx.x == 0) {
+        s_running = 0;
+        s_idle = 0;
+        const unsigned long long head = ld(&a.ctl->queue_head);
+        const unsigned long long tail = a.open_form ? ld(&a.ctl->units_tail) : (unsigned long long)a.n_units;
+        s_head = head;
+        s_avail = tail > head ? tail - head : 0;
+    }
     __syncthreads();
+    const unsigned long long head = s_head, avail = s_avail;
     for (uint32_t s = threadIdx.x; s < a.G; s += kBlock) {
         uint32_t st = ld32(&a.slots[s].state);
         if (st == S_RETIRE) {
             // retired in this iteration's earlier phases: account its depth, free the slot
-            const uint32_t qid = a.units[ld32(&a.slots[s].unit)].query;
+            const uint32_t qid = a.units[ld32(&a.slots[s].unit) & a.unit_mask].query;
             const uint32_t depth = iter - ld32(&a.slots[s].start_iter);
             atomicMax(&a.qout[qid].max_depth, (unsigned long long)depth);
             atomicAdd(&a.qout[qid].levels, (unsigned long long)depth);
+            atomicAdd(&a.qout[qid].units_done, 1ull);
             st64(&a.slots[s].log_n, 0);
             st32(&a.slots[s].state, S_IDLE);
             st = S_IDLE;
         }
         if (st == S_IDLE) {
-            const unsigned long long u = atomicAdd(&a.ctl->queue_head, 1ull);
-            if (u < a.n_units) {
+            // idle slots take the next units in queue order; the head moves by exactly the units
+            // taken, so a unit published later is never skipped
+            const uint32_t rank = atomicAdd(&s_idle, 1u);
+            if (rank < avail) {
+                const unsigned long long u = head + rank;
                 st32(&a.slots[s].unit, (uint32_t)u);
-                st32(&a.slots[s].query, a.units[u].query);
+                st32(&a.slots[s].query, a.units[u & a.unit_mask].query);
                 st32(&a.slots[s].alive, iter);
                 st32(&a.slots[s].start_iter, iter);
                 st32(&a.slots[s].state, S_RUN);
@@ -582,7 +619,10 @@ __device__ void phase_assign(const BArgs& a, uint32_t iter) {
         if (st == S_RUN) atomicAdd(&s_running, 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) st64(&a.ctl->n_running, s_running);
+    if (threadIdx.x == 0) {
+        st64(&a.ctl->n_running, s_running);
+        st64(&a.ctl->queue_head, head + min((unsigned long long)s_idle, avail));
+    }
 }
 
 template <int K>
@@ -601,7 +641,7 @@ __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
             slot = (uint32_t)(i / a.W);
             j = (uint32_t)(i % a.W);
             if (ld32(&a.slots[slot].state) == S_RUN && ld32(&a.slots[slot].start_iter) == iter) {
-                const BUnit unit = a.units[ld32(&a.slots[slot].unit)];
+                const BUnit unit = a.units[ld32(&a.slots[slot].unit) & a.unit_mask];
                 if (j < unit.n) {
                     const BQuery& Qy = a.queries[unit.query];
                     const uint64_t sidx = unit.src_off + j;
@@ -634,9 +674,14 @@ __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
             const unsigned long long pos = base + __popcll(m & rpqd::lanemask_lt());
             const unsigned long long li = lbase + __popcll(m & rpqd::lanemask_lt());
             if (take) {
-                if (pos < a.list_cap) ids[pos] = (uint32_t)row;
-                else atomicOr(&a.ctl->err, 1ull);
-                if (li < a.slot_stride) a.logs[(uint64_t)slot * a.slot_stride + li] = (uint32_t)(row - (uint64_t)slot * a.slot_stride);
+                if (pos < a.list_cap) {
+                    ids[pos] = (uint32_t)row;
+                } else {
+                    // no room: the seed waits on its touch bit for the next compaction
+                    or_relaxed(&a.touch[row >> 6], 1ull << (row & 63));
+                    if (a.queries[ld32(&a.slots[slot].query)].max_len != 0xFFFFFFFFu) atomicOr(&a.ctl->err, 1ull);
+                }
+                if (li < a.log_cap) a.logs[(uint64_t)slot * a.log_cap + li] = (uint32_t)(row - (uint64_t)slot * a.slot_stride);
             }
         }
     }
@@ -683,6 +728,39 @@ __device__ void phase_finalize(const BArgs& a, int p, uint32_t iter, uint64_t& t
             stop = iter - ld32(&a.slots[slot].start_iter) >= a.queries[qid].max_len;
         }
         const uint32_t n_here = (uint32_t)min<uint64_t>(64, n - e0);
+        // the entry's work (its item count) and slices come first: a wave that finds no room for
+        // its slices changes nothing and leaves its rows for the next iteration
+        if (active) {
+            const uint64_t m = stop ? 0 : (a.lmask[v] & nfa->qlab[q]);
+            work = m ? rpqd::entry_work(a.row_ptr, L, nfa->delta, v, q, m) : 0;
+        }
+        const uint64_t ndesc = work > H ? (work + H - 1) / H : 0;
+        const uint64_t dincl = rpqd::wave_incl_scan_u64(ndesc);
+        const uint64_t dexcl = dincl - ndesc;
+        const uint64_t dtot = __shfl(dincl, 63, 64);
+        unsigned long long dbase = 0;
+        if (dtot) {
+            if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)dtot);
+            dbase = __shfl(dbase, 0, 64);
+        }
+        if (dtot && dbase + dtot > a.desc_cap) {
+            // no room: empty slices where the wave reserved space inside the buffer (the expansion
+            // reads every slice below the count), empty frontier rows, and the rows' touch bits back
+            // on so that the next compaction lists them again with their Next bits
+            for (uint64_t i = lane; i < dtot && dbase + i < a.desc_cap; i += 64) {
+                Desc dd;
+                dd.entry = (uint32_t)e0;
+                dd.beg = 0;
+                dd.len = 0;
+                dout[dbase + i] = dd;
+            }
+            for (uint32_t idx = grp; idx < n_here; idx += GS) rows[(e0 + idx) * K + k] = 0;
+            if (active) {
+                or_relaxed(&a.touch[row32 >> 6], 1ull << (row32 & 63));
+                if (a.queries[qid].max_len != 0xFFFFFFFFu) atomicOr(&a.ctl->err, 2ull);
+            }
+            continue;
+        }
         uint32_t my_pc = 0;   // new source bits of this lane's row
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
             uint32_t r[kUnroll], an[kUnroll], sp[kUnroll];
@@ -721,8 +799,6 @@ __device__ void phase_finalize(const BArgs& a, int p, uint32_t iter, uint64_t& t
             ++t_frows;
             if (my_ans != 0xFFFFFFFFu && pc)
                 or_relaxed(&a.summ[(uint64_t)slot * a.summ_words + v / 64], 1ull << (v & 63));
-            const uint64_t m = stop ? 0 : (a.lmask[v] & nfa->qlab[q]);
-            work = m ? rpqd::entry_work(a.row_ptr, L, nfa->delta, v, q, m) : 0;
             eprod = (uint64_t)pc * work;
         }
         // product edges per query (one atomic per wave when the wave holds one query)
@@ -733,15 +809,9 @@ __device__ void phase_finalize(const BArgs& a, int p, uint32_t iter, uint64_t& t
         } else if (active && eprod) {
             atomicAdd(&a.qout[qid].eprod, (unsigned long long)eprod);
         }
-        // entries of more than H items are cut into slices of at most H items, written by the whole wave
-        const uint64_t ndesc = work > H ? (work + H - 1) / H : 0;
-        const uint64_t dincl = rpqd::wave_incl_scan_u64(ndesc);
-        const uint64_t dexcl = dincl - ndesc;
-        const uint64_t dtot = __shfl(dincl, 63, 64);
+        // entries of more than H items are cut into slices of at most H items, written by the whole
+        // wave into the room reserved above
         if (dtot) {
-            unsigned long long dbase = 0;
-            if (lane == 0) dbase = atomicAdd(dcnt, (unsigned long long)dtot);
-            dbase = __shfl(dbase, 0, 64);
             for (uint64_t i0 = 0; i0 < dtot; i0 += 64) {
                 const uint64_t i = i0 + lane;
                 int c = 0;
@@ -788,11 +858,15 @@ __device__ void phase_finalize(const BArgs& a, int p, uint32_t iter, uint64_t& t
 template <int K>
 __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
     uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0, t_frows = 0, t_fwords = 0;
-    int p = 0;
+    // iterations continue the numbering of earlier launches on the same state (open form); every
+    // block reads the count before the first barrier, and it is only written after the last one of
+    // an iteration.  Iteration i expands list (i - 1) & 1.
+    const uint32_t iter0 = (uint32_t)ld(&a.ctl->iterations) + 1;
+    int p = (int)((iter0 - 1) & 1);
     const uint64_t t_start = wall_clock64();
     uint64_t t_last = t_start;
     if (blockIdx.x == 0 && threadIdx.x == 0) st64(&a.ctl->t_begin, t_start);
-    for (uint32_t iter = 1;; ++iter) {
+    for (uint32_t iter = iter0;; ++iter) {
         // whole-kernel deadline: a run that exceeds it is abandoned (every block leaves at its
         // next barrier) and reported as an error
         if (blockIdx.x == 0 && threadIdx.x == 0 && wall_clock64() - t_start > a.deadline)
@@ -825,6 +899,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
         BAR(7);
         p ^= 1;
         if (blockIdx.x == 0 && threadIdx.x == 0) st64(&a.ctl->iterations, iter);
+        // open form: the launch ends here with its state intact; the next one resumes at iter + 1
+        if (a.max_iters && iter - iter0 + 1 >= a.max_iters) break;
     }
     t_items = rpqd::wave_sum_u64(t_items);
     t_descs = rpqd::wave_sum_u64(t_descs);
@@ -869,7 +945,7 @@ __global__ void k_gather_pairs(BArgs a, const uint64_t* __restrict__ unit_prefix
         const uint64_t n = a.unit_total[u];
         for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
             if (src0 + i < Qy.capacity && dst0 + i < Qy.capacity)
-                Qy.pairs[dst0 + i] = a.stage[Qy.stage_off + src0 + i];
+                Qy.pairs[dst0 + i] = Qy.stage[src0 + i];
         }
     }
 }
@@ -890,7 +966,7 @@ struct HostQuery {
 
 struct Layout {
     uint32_t K, W, G, Qmax, H, nchunks, n_units;
-    uint64_t slot_stride, summ_words, list_cap, desc_cap, stage_keys;
+    uint64_t slot_stride, summ_words, list_cap, desc_cap, log_cap, stage_keys;
     uint64_t off_ctl, off_nfas, off_queries, off_qout, off_units, off_slots, off_vis, off_next, off_touch, off_ever,
         off_ans,
         off_summ, off_ids[2], off_rows[2], off_desc[2], off_logs, off_retiring, off_partial, off_srcbase, off_stage,
@@ -937,12 +1013,81 @@ void to_bnfa(const rpq_nfa& n, uint32_t L, BNfa* d) {
         }
 }
 
+// Slot geometry shared by both forms: slice size (auto unless fixed), slices per slot and the device
+// bytes of one slot.  x.W, x.K, x.Qmax and (when fixed) x.H are set by the caller.
+// share > 1 sizes the frontier lists, slice buffers and first-visit logs for 1/share of the worst
+// case (every row of every slot in one level): rows beyond them wait for a later iteration, and a
+// slot whose log overflows is cleared whole.
+void size_slots(const rpq_graph* g, uint32_t max_succ, bool auto_chunk, uint32_t share, Layout* x,
+                uint64_t* desc_per_slot, uint64_t* per_slot) {
+    x->slot_stride = ((uint64_t)x->Qmax * g->V + 63) / 64 * 64;
+    x->summ_words = (g->V + 63) / 64;
+    x->nchunks = (uint32_t)((g->V + kChunkV - 1) / kChunkV);
+    // slices of one level and slot: entries with more than H items take ceil(work / H) <= 2 work / H
+    // each, and all entries of one state hold at most E * max |delta(q, l)| items
+    const uint64_t bitmap_bytes = x->slot_stride * x->K * 8 * 2;   // Vis + Next of one slot
+    // default slice size: the smallest that keeps a slot's slice buffers within a quarter of its bitmaps
+    while (auto_chunk && x->H < 256 &&
+           2 * (2 * (uint64_t)x->Qmax * max_succ * g->E / x->H + 2) * sizeof(Desc) > bitmap_bytes / 4)
+        x->H *= 2;
+    *desc_per_slot = (2 * (uint64_t)x->Qmax * max_succ * g->E / x->H + 2) / share + 64;
+    x->log_cap = std::max<uint64_t>(64, x->slot_stride / share);
+    const uint64_t list_per_slot = x->slot_stride / share + 64;
+    // per slot: Vis + Next, touch and first-visit bits, Ans, summary, first-visit log, and its share
+    // of the two frontier lists (row id + K-word row per entry) and of the two slice buffers
+    *per_slot = x->slot_stride * x->K * 8 * 2 + x->slot_stride / 4 + (uint64_t)g->V * x->K * 8 + x->summ_words * 8 +
+                x->log_cap * 4 + 2 * list_per_slot * (4 + x->K * 8) + 2 * *desc_per_slot * sizeof(Desc);
+}
+
+// Offsets of every array for G slots, nq query-table entries and n_unit_entries unit entries.
+void place(const rpq_graph* g, uint32_t nq, uint64_t n_unit_entries, Layout* x) {
+    const uint64_t G = x->G;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const uint64_t nu = std::max<uint64_t>(1, n_unit_entries);
+    x->off_ctl = take(sizeof(BCtl));
+    x->off_nfas = take(sizeof(BNfa) * nq);
+    x->off_queries = take(sizeof(BQuery) * nq);
+    x->off_qout = take(sizeof(BQueryOut) * nq);
+    x->off_units = take(sizeof(BUnit) * nu);
+    x->off_slots = take(sizeof(BSlot) * G);
+    x->off_vis = take(G * x->slot_stride * x->K * 8);
+    x->off_next = take(G * x->slot_stride * x->K * 8);
+    x->off_touch = take(G * x->slot_stride / 8);
+    x->off_ever = take(G * x->slot_stride / 8);
+    x->off_ans = take(G * (uint64_t)g->V * x->K * 8);
+    x->off_summ = take(G * x->summ_words * 8);
+    for (int p = 0; p < 2; ++p) {
+        x->off_ids[p] = take(x->list_cap * 4);
+        x->off_rows[p] = take(x->list_cap * x->K * 8);
+        x->off_desc[p] = take(x->desc_cap * sizeof(Desc));
+    }
+    x->off_logs = take(G * x->log_cap * 4);
+    x->off_retiring = take(G * 4);
+    x->off_partial = take(G * x->W * (uint64_t)x->nchunks * 4);
+    x->off_srcbase = take(G * x->W * 8);
+    x->off_stage = take(std::max<uint64_t>(1, x->stage_keys) * 8);
+    x->off_utotal = take(nu * 8);
+    x->off_ustart = take(nu * 8);
+    x->off_uprefix = take((nu + 1) * 8);
+    x->off_scan_tmp = take((rpq::scan_temp_elems(nu) + 1) * 8);
+    x->total = off;
+}
+
+bool valid_width(uint32_t W) {
+    return W == 64 || W == 128 || W == 256 || W == 512 || W == 1024 || W == 2048 || W == 4096;
+}
+
 int plan(rpq_batch* b) {
     const rpq_graph* g = b->g;
     Layout x;
     std::memset(&x, 0, sizeof x);
     x.W = b->opts.batch_width ? b->opts.batch_width : 512;
-    if (x.W != 64 && x.W != 128 && x.W != 256 && x.W != 512 && x.W != 1024 && x.W != 2048 && x.W != 4096) {
+    if (!valid_width(x.W)) {
         rpq::set_error("batch_width must be 64 .. 4096, a power of two");
         return RPQ_EINVAL;
     }
@@ -957,9 +1102,7 @@ int plan(rpq_batch* b) {
     // units
     b->units.clear();
     uint32_t qi = 0;
-    std::vector<std::pair<uint32_t, uint32_t>> qunits;
     for (auto& q : b->queries) {
-        const uint32_t first = (uint32_t)b->units.size();
         for (uint64_t off = 0; off < q.n_sources; off += x.W) {
             BUnit u;
             u.query = qi;
@@ -967,29 +1110,24 @@ int plan(rpq_batch* b) {
             u.src_off = off;
             b->units.push_back(u);
         }
-        qunits.emplace_back(first, (uint32_t)b->units.size() - first);
         ++qi;
     }
     x.n_units = (uint32_t)b->units.size();
-    x.slot_stride = ((uint64_t)x.Qmax * g->V + 63) / 64 * 64;
-    x.summ_words = (g->V + 63) / 64;
-    // slices of one level and slot: entries with more than H items take ceil(work / H) <= 2 work / H
-    // each, and all entries of one state hold at most E * max |delta(q, l)| items
     uint32_t max_succ = 1;
     for (auto& q : b->queries)
         for (uint32_t i = 0; i < RPQ_MAX_STATES * RPQ_MAX_LABELS; ++i)
             max_succ = std::max(max_succ, (uint32_t)__builtin_popcount(q.nfa.delta[i]));
-    const uint64_t bitmap_bytes = x.slot_stride * x.K * 8 * 2;   // Vis + Next of one slot
-    // default slice size: the smallest that keeps a slot's slice buffers within a quarter of its bitmaps
-    while (!b->opts.chunk_edges && x.H < 256 &&
-           2 * (2 * (uint64_t)x.Qmax * max_succ * g->E / x.H + 2) * sizeof(Desc) > bitmap_bytes / 4)
-        x.H *= 2;
-    const uint64_t desc_per_slot = 2 * (uint64_t)x.Qmax * max_succ * g->E / x.H + 2;
-    // per slot: Vis + Next, touch and first-visit bits, Ans, summary, first-visit log, and its share
-    // of the two frontier lists (row id + K-word row per entry) and of the two slice buffers
-    const uint64_t per_slot = x.slot_stride * x.K * 8 * 2 + x.slot_stride / 4 + (uint64_t)g->V * x.K * 8 +
-                              x.summ_words * 8 + x.slot_stride * 4 + 2 * x.slot_stride * (4 + x.K * 8) +
-                              2 * desc_per_slot * sizeof(Desc);
+    // lists and slices sized for a quarter of the worst case (rows beyond wait a level), except when a
+    // query is length-bounded: its rows must be expanded at their exact depth
+    bool bounded = false;
+    for (auto& q : b->queries) bounded |= q.max_len != 0xFFFFFFFFu;
+    const uint32_t share = b->opts.list_share ? b->opts.list_share : (bounded ? 1 : 4);
+    if (bounded && share != 1) {
+        rpq::set_error("a batch with length-bounded queries needs list_share 1");
+        return RPQ_EINVAL;
+    }
+    uint64_t desc_per_slot = 0, per_slot = 0;
+    size_slots(g, max_succ, !b->opts.chunk_edges, share, &x, &desc_per_slot, &per_slot);
     uint64_t G = b->opts.slots;
     if (!G) {
         const uint64_t budget = 64ull << 30;
@@ -1002,55 +1140,18 @@ int plan(rpq_batch* b) {
         return RPQ_EUNSUPPORTED;
     }
     x.G = (uint32_t)G;
-    x.nchunks = (uint32_t)((g->V + kChunkV - 1) / kChunkV);
-    // frontier list: worst case every row of every slot in one level
-    x.list_cap = (uint64_t)x.G * x.slot_stride;
+    x.list_cap = (uint64_t)x.G * (x.slot_stride / share + 64);
     x.desc_cap = (uint64_t)x.G * desc_per_slot;
     x.stage_keys = 0;
     for (auto& q : b->queries)
         if (q.pairs) x.stage_keys += q.capacity;
-    uint64_t off = 0;
-    auto take = [&](uint64_t bytes) {
-        const uint64_t o = off;
-        off = align256(off + bytes);
-        return o;
-    };
-    const uint32_t nq = (uint32_t)b->queries.size();
-    x.off_ctl = take(sizeof(BCtl));
-    x.off_nfas = take(sizeof(BNfa) * nq);
-    x.off_queries = take(sizeof(BQuery) * nq);
-    x.off_qout = take(sizeof(BQueryOut) * nq);
-    x.off_units = take(sizeof(BUnit) * std::max<uint32_t>(1, x.n_units));
-    x.off_slots = take(sizeof(BSlot) * x.G);
-    x.off_vis = take(G * x.slot_stride * x.K * 8);
-    x.off_next = take(G * x.slot_stride * x.K * 8);
-    x.off_touch = take(G * x.slot_stride / 8);
-    x.off_ever = take(G * x.slot_stride / 8);
-    x.off_ans = take(G * (uint64_t)g->V * x.K * 8);
-    x.off_summ = take(G * x.summ_words * 8);
-    for (int p = 0; p < 2; ++p) {
-        x.off_ids[p] = take(x.list_cap * 4);
-        x.off_rows[p] = take(x.list_cap * x.K * 8);
-        x.off_desc[p] = take(x.desc_cap * sizeof(Desc));
-    }
-    x.off_logs = take(G * x.slot_stride * 4);
-    x.off_retiring = take(G * 4);
-    x.off_partial = take(G * x.W * (uint64_t)x.nchunks * 4);
-    x.off_srcbase = take(G * x.W * 8);
-    x.off_stage = take(std::max<uint64_t>(1, x.stage_keys) * 8);
-    x.off_utotal = take(std::max<uint32_t>(1, x.n_units) * 8);
-    x.off_ustart = take(std::max<uint32_t>(1, x.n_units) * 8);
-    x.off_uprefix = take((std::max<uint32_t>(1, x.n_units) + 1) * 8);
-    x.off_scan_tmp = take((rpq::scan_temp_elems(std::max<uint32_t>(1, x.n_units)) + 1) * 8);
-    x.total = off;
+    place(g, (uint32_t)b->queries.size(), x.n_units, &x);
     b->lay = x;
-    (void)qunits;
     return RPQ_OK;
 }
 
-BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
-    const Layout& x = b->lay;
-    const rpq_graph* g = b->g;
+BArgs args_for(const rpq_graph* g, const Layout& x, char* ws, unsigned n_blocks, uint32_t n_units,
+               uint32_t n_queries) {
     BArgs a;
     std::memset(&a, 0, sizeof a);
     a.row_ptr = g->out.row_ptr;
@@ -1088,16 +1189,26 @@ BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
     a.G = x.G;
     a.W = x.W;
     a.nchunks = x.nchunks;
-    a.n_units = b->unit_limit ? std::min(x.n_units, b->unit_limit) : x.n_units;
-    a.n_queries = (uint32_t)b->queries.size();
+    a.n_units = n_units;
+    a.n_queries = n_queries;
     a.n_blocks = n_blocks;
     a.slot_stride = x.slot_stride;
     a.summ_words = x.summ_words;
     a.list_cap = x.list_cap;
     a.desc_cap = x.desc_cap;
+    a.log_cap = x.log_cap;
     a.timeout = 100ull * 1000 * 1000 * 30;    // one barrier wait: 30 s of the 100 MHz clock
     a.deadline = 100ull * 1000 * 1000 * 300;  // whole run: 300 s
+    a.open_form = 0;
+    a.max_iters = 0;
+    a.unit_mask = ~0ull;
     return a;
+}
+
+BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
+    const Layout& x = b->lay;
+    return args_for(b->g, x, ws, n_blocks, b->unit_limit ? std::min(x.n_units, b->unit_limit) : x.n_units,
+                    (uint32_t)b->queries.size());
 }
 
 #define RPQ_BDISPATCH(K, CALL)                                   \
@@ -1113,7 +1224,7 @@ BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
     }
 
 template <int K>
-int co_resident_blocks(unsigned* out) {
+int co_resident_blocks(unsigned* out, int max_per_cu = 4) {
     int per_cu = 0, dev = 0, n_cu = 0;
     RPQ_HIP(hipGetDevice(&dev));
     RPQ_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1124,7 +1235,7 @@ int co_resident_blocks(unsigned* out) {
     }
     // up to four 256-thread blocks per CU: enough waves in flight for the level phases
     // while the grid barrier stays cheap
-    *out = (unsigned)std::min<uint64_t>((uint64_t)std::min(per_cu, 4) * n_cu,
+    *out = (unsigned)std::min<uint64_t>((uint64_t)std::min(per_cu, max_per_cu) * n_cu,
                                         (uint64_t)rpqd::kBarMaxGroups * rpqd::kBarGroup);
     return RPQ_OK;
 }
@@ -1352,7 +1463,7 @@ int rpq_batch_run(rpq_batch_t b, void* workspace, uint64_t workspace_bytes, hipS
             d.per_source = h.per_source;
             d.pairs = h.pairs;
             d.capacity = h.capacity;
-            d.stage_off = stage_off;
+            d.stage = reinterpret_cast<uint64_t*>(ws + x.off_stage) + stage_off;
             if (h.pairs) stage_off += h.capacity;
             d.first_unit = ufirst;
             d.n_units = (uint32_t)((h.n_sources + x.W - 1) / x.W);
@@ -1558,3 +1669,382 @@ int rpq_batch_autotune(rpq_batch_t b, const rpq_batch_opts* candidates, uint32_t
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Resident engine: the open form of the persistent kernel.  Between launches the host uploads the
+// queries that arrived (automaton, query record, zeroed outputs, and their units appended to the
+// device ring) and publishes the new tail; the kernel's refill phase hands the new units to slots
+// as they free up.  A launch ends after max_iters iterations, or earlier when no slot runs and the
+// queue is empty, and leaves slots, lists and counters for the next one.
+// ------------------------------------------------------------------------------------------------
+namespace {
+
+constexpr uint32_t kResQueries = 4096;       // query-table entries
+constexpr uint64_t kResRing = 1ull << 16;    // unit-ring entries (a power of two)
+constexpr uint32_t kResMaxStaged = 256;      // queries uploaded per launch
+constexpr uint64_t kResMaxStagedUnits = 1ull << 14;
+constexpr uint32_t kResShare = 8;            // lists, slices and logs for 1/8 of the worst case
+
+struct ResRecord {
+    uint32_t q, pad;
+    BNfa nfa;
+    BQuery bq;
+};
+
+// Install the staged records into their table entries, zero their outputs, publish the unit tail
+// and reset the grid barrier for the launch that follows on the same stream.
+__global__ void k_res_install(BArgs a, const ResRecord* __restrict__ recs, uint32_t n_recs,
+                              unsigned long long units_tail) {
+    for (uint32_t i = blockIdx.x; i < n_recs; i += gridDim.x) {
+        const ResRecord& r = recs[i];
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&r.nfa);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(const_cast<BNfa*>(a.nfas) + r.q);
+        for (uint32_t j = threadIdx.x; j < sizeof(BNfa) / 4; j += blockDim.x) dst[j] = src[j];
+        const uint32_t* qs = reinterpret_cast<const uint32_t*>(&r.bq);
+        uint32_t* qd = reinterpret_cast<uint32_t*>(const_cast<BQuery*>(a.queries) + r.q);
+        for (uint32_t j = threadIdx.x; j < sizeof(BQuery) / 4; j += blockDim.x) qd[j] = qs[j];
+        unsigned long long* o = reinterpret_cast<unsigned long long*>(a.qout + r.q);
+        for (uint32_t j = threadIdx.x; j < sizeof(BQueryOut) / 8; j += blockDim.x) o[j] = 0;
+        if (r.bq.per_source)
+            for (uint64_t j = threadIdx.x; j < 2 * r.bq.n_sources; j += blockDim.x) r.bq.per_source[j] = 0;
+    }
+    if (blockIdx.x == 0) {
+        unsigned int* g = reinterpret_cast<unsigned int*>(&a.ctl->gs);
+        for (uint32_t j = threadIdx.x; j < sizeof(rpqd::GridSync) / 4; j += blockDim.x) g[j] = 0;
+        if (threadIdx.x == 0) a.ctl->units_tail = units_tail;
+    }
+}
+
+}  // namespace
+
+namespace rpq {
+
+struct Resident {
+    rpq_graph* g = nullptr;
+    Layout x{};
+    char* ws = nullptr;
+    ResRecord* d_recs = nullptr;        // device upload area
+    unsigned long long* d_bad = nullptr;
+    unsigned n_blocks = 0;
+    uint32_t max_succ = 0;
+    bool broken = false;
+    struct Entry {
+        bool used = false;
+        uint64_t token = 0, u0 = 0, n_units = 0, capacity = 0;
+        bool pairs = false;
+    };
+    std::vector<Entry> table;
+    std::vector<uint32_t> free_q;
+    uint32_t q_hi = 0;                  // table entries [0, q_hi) may be in use
+    struct Staged {
+        uint64_t token;
+        ResidentQuery q;
+    };
+    std::vector<Staged> staged;
+    uint64_t units_tail = 0;            // units published to the device ring
+    uint64_t n_active = 0;
+    ResRecord* h_recs = nullptr;        // pinned
+    BUnit* h_units = nullptr;           // pinned
+    BQueryOut* h_out = nullptr;         // pinned
+    BCtl* h_ctl = nullptr;              // pinned
+    unsigned long long* h_bad = nullptr;   // pinned
+};
+
+namespace {
+
+int res_layout(const rpq_graph* g, uint32_t W, uint32_t G, uint32_t Qmax, uint32_t max_succ, Layout* out,
+               uint64_t* total) {
+    if (!valid_width(W) || G == 0 || G > 1024 || Qmax == 0 || Qmax > RPQ_MAX_STATES || max_succ == 0 ||
+        max_succ > RPQ_MAX_STATES) {
+        rpq::set_error("resident engine: width 64..4096 (power of two), 1..1024 slots, 1..32 states");
+        return RPQ_EINVAL;
+    }
+    Layout x;
+    std::memset(&x, 0, sizeof x);
+    x.W = W;
+    x.K = W / 64;
+    x.H = 16;
+    x.Qmax = Qmax;
+    x.G = G;
+    uint64_t desc_per_slot = 0, per_slot = 0;
+    size_slots(g, max_succ, true, kResShare, &x, &desc_per_slot, &per_slot);
+    if ((uint64_t)G * x.slot_stride >= 0xFFFFFFFFull) {
+        rpq::set_error("slots * states * vertices must stay below 2^32; use fewer slots");
+        return RPQ_EUNSUPPORTED;
+    }
+    x.list_cap = (uint64_t)G * (x.slot_stride / kResShare + 64);
+    x.desc_cap = (uint64_t)G * desc_per_slot;
+    x.stage_keys = 0;
+    x.n_units = 0;
+    place(g, kResQueries, kResRing, &x);
+    *out = x;
+    *total = align256(x.total) + align256(sizeof(ResRecord) * kResMaxStaged) + kResMaxStaged * 8;
+    return RPQ_OK;
+}
+
+BArgs res_args(const Resident* r, uint32_t max_iters) {
+    BArgs a = args_for(r->g, r->x, r->ws, r->n_blocks, 0, kResQueries);
+    a.open_form = 1;
+    a.max_iters = max_iters;
+    a.unit_mask = kResRing - 1;
+    return a;
+}
+
+// every query staged, queued or running completes with `status`
+void res_fail_all(Resident* r, int status, std::vector<ResidentDone>* done) {
+    for (uint32_t q = 0; q < r->q_hi; ++q) {
+        Resident::Entry& e = r->table[q];
+        if (!e.used) continue;
+        ResidentDone d{};
+        d.token = e.token;
+        d.status = status;
+        done->push_back(d);
+        e.used = false;
+        r->free_q.push_back(q);
+    }
+    for (auto& st : r->staged) {
+        ResidentDone d{};
+        d.token = st.token;
+        d.status = status;
+        done->push_back(d);
+    }
+    r->staged.clear();
+    r->n_active = 0;
+}
+
+}  // namespace
+
+int resident_bytes(const rpq_graph* g, uint32_t W, uint32_t G, uint32_t Qmax, uint32_t max_succ, uint64_t* bytes) {
+    Layout x;
+    return res_layout(g, W, G, Qmax, max_succ, &x, bytes);
+}
+
+int resident_create(rpq_graph* g, uint32_t W, uint32_t G, uint32_t Qmax, uint32_t max_succ, void* mem,
+                    uint64_t bytes, hipStream_t stream, Resident** out) {
+    Layout x;
+    uint64_t need = 0;
+    RPQ_TRY(res_layout(g, W, G, Qmax, max_succ, &x, &need));
+    if (!mem || bytes < need || (reinterpret_cast<uintptr_t>(mem) & 255)) {
+        rpq::set_error("resident engine needs %llu bytes of 256-byte aligned device memory",
+                       (unsigned long long)need);
+        return RPQ_ENOMEM;
+    }
+    std::unique_ptr<Resident> r(new (std::nothrow) Resident());
+    if (!r) {
+        rpq::set_error("out of host memory");
+        return RPQ_ENOMEM;
+    }
+    r->g = g;
+    r->x = x;
+    r->ws = reinterpret_cast<char*>(mem);
+    r->d_recs = reinterpret_cast<ResRecord*>(r->ws + align256(x.total));
+    r->d_bad = reinterpret_cast<unsigned long long*>(r->ws + align256(x.total) +
+                                                     align256(sizeof(ResRecord) * kResMaxStaged));
+    r->max_succ = max_succ;
+    r->table.resize(kResQueries);
+    for (uint32_t q = kResQueries; q-- > 0;) r->free_q.push_back(q);
+    // half the co-resident occupancy: requests outside the engine keep room on every compute unit
+    RPQ_BDISPATCH(x.K, RPQ_TRY(co_resident_blocks<KK>(&r->n_blocks, 2)));
+    RPQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&r->h_recs), sizeof(ResRecord) * kResMaxStaged));
+    RPQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&r->h_units), sizeof(BUnit) * kResMaxStagedUnits));
+    RPQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&r->h_out), sizeof(BQueryOut) * kResQueries));
+    RPQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&r->h_ctl), sizeof(BCtl)));
+    RPQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&r->h_bad), 8 * kResMaxStaged));
+    // a clean state: no units, idle slots, empty bitmaps
+    const BArgs a = res_args(r.get(), 1);
+    RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(r->ws + x.off_ctl), sizeof(BCtl) / 8, 0, stream));
+    RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(r->ws + x.off_qout), sizeof(BQueryOut) / 8 * kResQueries, 0,
+                          stream));
+    RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(r->ws + x.off_slots), sizeof(BSlot) / 8 * x.G, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.vis, (uint64_t)x.G * x.slot_stride * x.K, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.next, (uint64_t)x.G * x.slot_stride * x.K, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.touch, (uint64_t)x.G * x.slot_stride / 64, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.ever, (uint64_t)x.G * x.slot_stride / 64, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.ans, (uint64_t)x.G * g->V * x.K, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.summ, (uint64_t)x.G * x.summ_words, 0, stream));
+    RPQ_TRY(rpq::fill_u64(a.unit_total, kResRing, 0, stream));
+    RPQ_HIP(hipStreamSynchronize(stream));
+    *out = r.release();
+    return RPQ_OK;
+}
+
+void resident_destroy(Resident* r) {
+    if (!r) return;
+    for (void* p : {static_cast<void*>(r->h_recs), static_cast<void*>(r->h_units), static_cast<void*>(r->h_out),
+                    static_cast<void*>(r->h_ctl), static_cast<void*>(r->h_bad)})
+        if (p) (void)hipHostFree(p);
+    delete r;
+}
+
+bool resident_fits(const Resident* r, const ResidentQuery& q) {
+    if (q.nfa.n_states == 0 || q.nfa.n_states > r->x.Qmax) return false;
+    for (uint32_t i = 0; i < RPQ_MAX_STATES * RPQ_MAX_LABELS; ++i)
+        if ((uint32_t)__builtin_popcount(q.nfa.delta[i]) > r->max_succ) return false;
+    const uint64_t n_units = (q.n_sources + r->x.W - 1) / r->x.W;
+    if (q.pairs && n_units > 1) return false;
+    return n_units <= kResMaxStagedUnits;
+}
+
+bool resident_broken(const Resident* r) { return r->broken; }
+
+int resident_admit(Resident* r, const ResidentQuery& q, uint64_t token) {
+    if (r->broken || !resident_fits(r, q)) {
+        rpq::set_error("query does not fit the resident engine");
+        return RPQ_EUNSUPPORTED;
+    }
+    uint64_t staged_units = 0;
+    for (auto& s : r->staged) staged_units += (s.q.n_sources + r->x.W - 1) / r->x.W;
+    const uint64_t n_units = (q.n_sources + r->x.W - 1) / r->x.W;
+    // ring room: units still referenced by active queries start at the oldest active unit
+    uint64_t oldest = r->units_tail;
+    for (uint32_t i = 0; i < r->q_hi; ++i)
+        if (r->table[i].used) oldest = std::min(oldest, r->table[i].u0);
+    if (r->staged.size() >= kResMaxStaged || r->free_q.size() <= r->staged.size() ||
+        staged_units + n_units > kResMaxStagedUnits ||
+        r->units_tail + staged_units + n_units - oldest > kResRing) {
+        rpq::set_error("resident engine is full");
+        return RPQ_ENOMEM;
+    }
+    r->staged.push_back({token, q});
+    return RPQ_OK;
+}
+
+bool resident_idle(const Resident* r) { return r->staged.empty() && r->n_active == 0; }
+
+int resident_step(Resident* r, uint32_t max_iters, hipStream_t stream, std::vector<ResidentDone>* done) {
+    if (r->broken) {
+        res_fail_all(r, RPQ_EDEVICE, done);
+        rpq::set_error("resident engine is out of service after a device error");
+        return RPQ_EDEVICE;
+    }
+    const Layout& x = r->x;
+    // 1. sources of the staged queries: strictly ascending ids below V, checked before any unit of
+    //    them is published
+    const uint32_t n_st = (uint32_t)r->staged.size();
+    if (n_st) {
+        RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(r->d_bad), n_st, 0, stream));
+        for (uint32_t i = 0; i < n_st; ++i) {
+            const ResidentQuery& q = r->staged[i].q;
+            if (q.sources && q.n_sources) {
+                hipLaunchKernelGGL(k_check_sources, dim3((unsigned)std::min<uint64_t>((q.n_sources + 255) / 256, 4096)),
+                                   dim3(256), 0, stream, q.sources, q.n_sources, r->g->V, r->d_bad + i);
+                RPQ_LAUNCH_CHECK();
+            }
+        }
+        RPQ_HIP(hipMemcpyAsync(r->h_bad, r->d_bad, 8ull * n_st, hipMemcpyDeviceToHost, stream));
+        RPQ_HIP(hipStreamSynchronize(stream));
+    }
+    // 2. table entries, records and units of the valid ones
+    uint32_t n_rec = 0;
+    uint64_t n_u = 0;
+    const uint64_t tail0 = r->units_tail;
+    for (uint32_t i = 0; i < n_st; ++i) {
+        const ResidentQuery& q = r->staged[i].q;
+        const uint64_t token = r->staged[i].token;
+        if (r->h_bad[i]) {
+            ResidentDone d{};
+            d.token = token;
+            d.status = RPQ_EINVAL;
+            done->push_back(d);
+            continue;
+        }
+        const uint64_t nu = (q.n_sources + x.W - 1) / x.W;
+        if (nu == 0) {   // no sources: nothing to run
+            ResidentDone d{};
+            d.token = token;
+            d.status = RPQ_OK;
+            done->push_back(d);
+            continue;
+        }
+        const uint32_t qi = r->free_q.back();
+        r->free_q.pop_back();
+        r->q_hi = std::max(r->q_hi, qi + 1);
+        Resident::Entry& e = r->table[qi];
+        e.used = true;
+        e.token = token;
+        e.u0 = tail0 + n_u;
+        e.n_units = nu;
+        e.pairs = q.pairs != nullptr;
+        e.capacity = q.pairs ? q.capacity : 0;
+        ResRecord& rec = r->h_recs[n_rec++];
+        std::memset(&rec, 0, sizeof rec);
+        rec.q = qi;
+        to_bnfa(q.nfa, r->g->L, &rec.nfa);
+        rec.bq.sources = q.sources;
+        rec.bq.n_sources = q.n_sources;
+        rec.bq.per_source = q.per_source;
+        rec.bq.pairs = q.pairs;
+        rec.bq.capacity = q.pairs ? q.capacity : 0;
+        rec.bq.stage = q.pairs;   // one unit: its keys are the query's output, in order
+        rec.bq.first_unit = (uint32_t)(e.u0 & 0xFFFFFFFFu);
+        rec.bq.n_units = (uint32_t)nu;
+        rec.bq.flags = (q.pairs ? RPQ_PAIRS : 0) | (q.per_source ? RPQ_PER_SOURCE : 0);
+        rec.bq.max_len = q.max_len;
+        for (uint64_t k = 0; k < nu; ++k) {
+            BUnit& u = r->h_units[n_u++];
+            u.query = qi;
+            u.n = (uint32_t)std::min<uint64_t>(x.W, q.n_sources - k * x.W);
+            u.src_off = k * x.W;
+        }
+        ++r->n_active;
+    }
+    r->staged.clear();
+    if (r->n_active == 0) return RPQ_OK;
+    // 3. upload: records, then the units into the ring (two pieces where it wraps)
+    BArgs a = res_args(r, max_iters);
+    if (n_rec) RPQ_HIP(hipMemcpyAsync(r->d_recs, r->h_recs, sizeof(ResRecord) * n_rec, hipMemcpyHostToDevice, stream));
+    if (n_u) {
+        BUnit* ring = reinterpret_cast<BUnit*>(r->ws + x.off_units);
+        const uint64_t at = tail0 & (kResRing - 1);
+        const uint64_t first = std::min<uint64_t>(n_u, kResRing - at);
+        RPQ_HIP(hipMemcpyAsync(ring + at, r->h_units, sizeof(BUnit) * first, hipMemcpyHostToDevice, stream));
+        if (first < n_u)
+            RPQ_HIP(hipMemcpyAsync(ring, r->h_units + first, sizeof(BUnit) * (n_u - first), hipMemcpyHostToDevice,
+                                   stream));
+    }
+    r->units_tail = tail0 + n_u;
+    hipLaunchKernelGGL(k_res_install, dim3(std::max<uint32_t>(1, std::min<uint32_t>(n_rec, 256))), dim3(256), 0,
+                       stream, a, r->d_recs, n_rec, (unsigned long long)r->units_tail);
+    RPQ_LAUNCH_CHECK();
+    // 4. one bounded launch, then the control block and the query outputs
+    RPQ_BDISPATCH(x.K, hipLaunchKernelGGL(k_batch<KK>, dim3(r->n_blocks), dim3(kBlock), 0, stream, a));
+    RPQ_LAUNCH_CHECK();
+    RPQ_HIP(hipMemcpyAsync(r->h_ctl, r->ws + x.off_ctl, sizeof(BCtl), hipMemcpyDeviceToHost, stream));
+    RPQ_HIP(hipMemcpyAsync(r->h_out, r->ws + x.off_qout, sizeof(BQueryOut) * r->q_hi, hipMemcpyDeviceToHost, stream));
+    RPQ_HIP(hipStreamSynchronize(stream));
+    if (r->h_ctl->gs.abort || r->h_ctl->err) {
+        r->broken = true;
+        rpq::set_error(r->h_ctl->gs.abort ? "resident kernel aborted at a grid barrier"
+                                          : "internal capacity exceeded in the resident kernel (flags 0x%llx)",
+                       (unsigned long long)r->h_ctl->err);
+        res_fail_all(r, RPQ_EDEVICE, done);
+        return RPQ_EDEVICE;
+    }
+    // 5. queries whose every unit has retired
+    for (uint32_t qi = 0; qi < r->q_hi; ++qi) {
+        Resident::Entry& e = r->table[qi];
+        if (!e.used) continue;
+        const BQueryOut& o = r->h_out[qi];
+        if (o.units_done < e.n_units) continue;
+        ResidentDone d{};
+        d.token = e.token;
+        d.count = o.count;
+        d.hash = o.hash;
+        d.product_edges = o.eprod;
+        d.levels = o.levels;
+        d.max_depth = o.max_depth;
+        d.status = RPQ_OK;
+        if (e.pairs) {
+            d.written = std::min<uint64_t>(o.count, e.capacity);
+            if (o.count > e.capacity) d.status = RPQ_EOVERFLOW;
+        }
+        done->push_back(d);
+        e.used = false;
+        r->free_q.push_back(qi);
+        --r->n_active;
+    }
+    while (r->q_hi > 0 && !r->table[r->q_hi - 1].used) --r->q_hi;
+    return RPQ_OK;
+}
+
+}  // namespace rpq

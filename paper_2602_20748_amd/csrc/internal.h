@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <vector>
 
 #include <cstdint>
 #include <cstdio>
@@ -94,6 +95,46 @@ uint64_t* host_stage();
 int sparse_eval(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
                 uint64_t max_len, void* workspace, uint64_t workspace_bytes, rpq_result* res, hipStream_t stream);
 int sparse_workspace_size(rpq_graph_t g, const rpq_nfa* nfa, uint64_t n_sources, uint32_t flags, uint64_t* bytes);
+
+// ---- resident engine: the persistent batched kernel fed between bounded launches (batch.hip) ----
+// The open form of the batched launch.  Its slots (fixed unit width W and automaton size Qmax) live
+// in a caller-provided device region for the engine's lifetime; queries are staged on the host,
+// uploaded before the next launch and join the device unit queue, whose idle slots take units at
+// every iteration's refill.  Each launch runs at most max_iters iterations and keeps the state for
+// the next one.
+struct ResidentQuery {
+    rpq_nfa nfa;
+    const uint32_t* sources;     // device, ascending; null = ids [0, n_sources)
+    uint64_t n_sources;
+    uint64_t* pairs;             // device or null (single-unit queries only)
+    uint64_t capacity;
+    uint64_t* per_source;        // device [n][2] or null
+    uint32_t max_len;            // deepest level recorded (0xFFFFFFFF = no bound)
+};
+struct ResidentDone {
+    uint64_t token;
+    int status;
+    uint64_t count, hash, product_edges, levels, max_depth, written;
+};
+struct Resident;
+// Device bytes of an engine with G slots of W sources for automata of at most Qmax states and at
+// most max_succ successors per (state, label).
+int resident_bytes(const rpq_graph* g, uint32_t W, uint32_t G, uint32_t Qmax, uint32_t max_succ, uint64_t* bytes);
+int resident_create(rpq_graph* g, uint32_t W, uint32_t G, uint32_t Qmax, uint32_t max_succ, void* mem,
+                    uint64_t bytes, hipStream_t stream, Resident** out);
+void resident_destroy(Resident* r);
+// Whether the engine can run this query (automaton within Qmax / max_succ; pairs only when the
+// sources fit one unit).  Reads only what is fixed at creation.
+bool resident_fits(const Resident* r, const ResidentQuery& q);
+// Stage a query for the next launch; RPQ_ENOMEM while the query table or the unit ring is full.
+int resident_admit(Resident* r, const ResidentQuery& q, uint64_t token);
+// True when no query is staged, queued or running.
+bool resident_idle(const Resident* r);
+// True once a device error took the engine out of service (it then accepts nothing).
+bool resident_broken(const Resident* r);
+// Upload what is staged, run one launch of at most max_iters iterations on `stream`, wait, and
+// append the queries that completed.  On a device error every query in flight completes with it.
+int resident_step(Resident* r, uint32_t max_iters, hipStream_t stream, std::vector<ResidentDone>* done);
 
 inline int bits_for(uint64_t max_value) {   // bits needed to represent values <= max_value
     int b = 0;

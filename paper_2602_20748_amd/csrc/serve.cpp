@@ -9,6 +9,11 @@
 // call asks for.  A dense RPQ that does not fit the whole pool is split (fewer units in flight,
 // then narrower units).  A request that runs short of workspace re-enters the queue at the
 // front with the size the library asked for.
+//
+// With the resident engine on, dense RPQs it can run go to a driver thread instead: it stages
+// every such request that arrived into the engine (its units join the device unit queue of the
+// persistent batched kernel), runs one bounded launch, completes the requests whose units have
+// all retired, and repeats while anything is queued or running.
 #include "internal.h"
 
 #include <algorithm>
@@ -87,6 +92,7 @@ struct Job {
     std::vector<uint32_t> neq;
     uint64_t need = 0;               // workspace bytes to admit with
     rpq_ticket t{};
+    bool resident = false;           // routed to the resident engine
 };
 
 }  // namespace
@@ -102,6 +108,14 @@ struct rpq_server {
     std::vector<std::thread> workers;
     bool stopping = false;
     uint64_t running = 0, completed = 0, failed = 0, eprod = 0;
+    // resident engine (null when off): its queue, driver thread and pool segment
+    rpq::Resident* res = nullptr;
+    std::deque<Job*> res_queue;
+    std::condition_variable cv_res;
+    std::thread driver;
+    uint64_t res_off = 0, res_bytes = 0, res_slot_bytes = 0, res_running = 0, res_completed = 0, res_launches = 0;
+    uint32_t res_iters = 8;
+    uint32_t res_width = 64, res_max_units = 0;
     std::chrono::steady_clock::time_point t0;
 
     double now_ms() const {
@@ -138,6 +152,18 @@ int dense_plan(rpq_graph_t g, Job* j, uint64_t limit) {
     }
     rpq::set_error("request needs more than the %llu-byte pool even at one 64-source unit", (unsigned long long)limit);
     return RPQ_ENOMEM;
+}
+
+void finish_job(rpq_server* s, Job* j, int rc, double end) {
+    j->t.status = rc;
+    j->t.end_ms = end;
+    j->t.done = 1;
+    if (rc == RPQ_OK || rc == RPQ_EOVERFLOW) {
+        ++s->completed;
+        s->eprod += j->t.product_edges;
+    } else {
+        ++s->failed;
+    }
 }
 
 int run_job(rpq_server* s, Job* j, char* ws, hipStream_t stream, uint64_t* needed) {
@@ -230,19 +256,87 @@ void worker_main(rpq_server* s) {
             j->need = needed;              // run again with the workspace the library asked for
             s->queue.push_front(j);
         } else {
-            j->t.status = rc;
-            j->t.end_ms = end;
-            j->t.done = 1;
-            if (rc == RPQ_OK || rc == RPQ_EOVERFLOW) {
-                ++s->completed;
-                s->eprod += j->t.product_edges;
-            } else {
-                ++s->failed;
-            }
+            finish_job(s, j, rc, end);
             s->cv_done.notify_all();
         }
         s->cv_work.notify_all();
     }
+}
+
+void driver_main(rpq_server* s) {
+    (void)hipSetDevice(s->g->device);
+    hipStream_t stream = nullptr;
+    const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+    std::vector<rpq::ResidentDone> done;
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // stage every arrival that fits now (arrival order); the rest waits for the next launch
+        while (!s->res_queue.empty()) {
+            Job* j = s->res_queue.front();
+            rpq::ResidentQuery q{};
+            q.nfa = j->req.nfa;
+            q.sources = j->req.sources;
+            q.n_sources = (j->req.flags & RPQ_ALL_SOURCES) && j->req.n_sources == 0 ? s->g->V : j->req.n_sources;
+            q.pairs = (j->req.flags & RPQ_PAIRS) ? j->req.pairs : nullptr;
+            q.capacity = j->req.capacity;
+            q.per_source = (j->req.flags & RPQ_PER_SOURCE) ? j->req.per_source : nullptr;
+            q.max_len = 0xFFFFFFFFu;
+            if (rpq::resident_admit(s->res, q, j->id) != RPQ_OK) break;
+            s->res_queue.pop_front();
+            j->t.start_ms = s->now_ms();
+            j->t.workspace_bytes = s->res_slot_bytes;
+            ++s->res_running;
+        }
+        if (rpq::resident_broken(s->res) && !s->res_queue.empty()) {
+            // after a device error the engine takes nothing more: its queue goes to the workers
+            while (!s->res_queue.empty()) {
+                Job* j = s->res_queue.front();
+                s->res_queue.pop_front();
+                j->resident = false;
+                j->t.resident = 0;
+                s->queue.push_back(j);
+            }
+            s->cv_work.notify_all();
+        }
+        if (rpq::resident_idle(s->res)) {
+            if (s->stopping && s->res_queue.empty()) break;
+            s->cv_res.wait_for(lk, std::chrono::milliseconds(5));
+            continue;
+        }
+        lk.unlock();
+        done.clear();
+        const int rc = have_stream ? rpq::resident_step(s->res, s->res_iters, stream, &done) : RPQ_EDEVICE;
+        (void)rc;   // a device error completes every request in flight with it (in `done`)
+        const double end = s->now_ms();
+        lk.lock();
+        ++s->res_launches;
+        for (const rpq::ResidentDone& d : done) {
+            Job* j = s->jobs[d.token].get();
+            j->t.count = d.count;
+            j->t.hash = d.hash;
+            j->t.product_edges = d.product_edges;
+            j->t.written = d.written;
+            --s->res_running;
+            if (d.status == RPQ_OK || d.status == RPQ_EOVERFLOW) ++s->res_completed;
+            finish_job(s, j, d.status, end);
+        }
+        if (!done.empty()) s->cv_done.notify_all();
+    }
+    lk.unlock();
+    if (have_stream) (void)hipStreamDestroy(stream);
+}
+
+// Whether a request goes to the resident engine: dense RPQs without reversal or length bound,
+// whose automaton and source count the engine takes.
+bool route_resident(const rpq_server* s, const rpq_request* r) {
+    if (!s->res || r->kind != RPQ_REQ_RPQ) return false;
+    if (r->flags & ~(RPQ_PAIRS | RPQ_PER_SOURCE | RPQ_ALL_SOURCES)) return false;
+    rpq::ResidentQuery q{};
+    q.nfa = r->nfa;
+    q.n_sources = (r->flags & RPQ_ALL_SOURCES) && r->n_sources == 0 ? s->g->V : r->n_sources;
+    q.pairs = (r->flags & RPQ_PAIRS) ? r->pairs : nullptr;
+    if (s->res_max_units && (q.n_sources + s->res_width - 1) / s->res_width > s->res_max_units) return false;
+    return rpq::resident_fits(s->res, q);
 }
 
 int check_request(rpq_server* s, const rpq_request* r) {
@@ -285,6 +379,10 @@ int rpq_serve_start(rpq_graph_t g, const rpq_server_opts* opts, void* pool, uint
         rpq::set_error("at most 64 workers");
         return RPQ_EINVAL;
     }
+    if (opts && opts->reserved) {
+        rpq::set_error("reserved server options must be 0");
+        return RPQ_EINVAL;
+    }
     auto* s = new (std::nothrow) rpq_server();
     if (!s) {
         rpq::set_error("out of host memory");
@@ -294,6 +392,34 @@ int rpq_serve_start(rpq_graph_t g, const rpq_server_opts* opts, void* pool, uint
     s->pool = reinterpret_cast<char*>(pool);
     s->alloc.reset(new PoolAlloc(pool_bytes & ~(kAlign - 1)));
     s->t0 = std::chrono::steady_clock::now();
+    if (opts && opts->resident_slots) {
+        const uint32_t W = opts->resident_width ? opts->resident_width : 64;
+        const uint32_t Q = opts->resident_states ? opts->resident_states : 12;
+        const uint32_t succ = opts->resident_succ ? opts->resident_succ : 4;
+        s->res_iters = opts->resident_iters ? opts->resident_iters : 8;
+        s->res_width = W;
+        s->res_max_units = opts->resident_max_units;
+        int rc = rpq::resident_bytes(g, W, opts->resident_slots, Q, succ, &s->res_bytes);
+        if (rc == RPQ_OK && !s->alloc->alloc(s->res_bytes, &s->res_off)) {
+            rpq::set_error("the resident engine needs %llu bytes; the pool has %llu",
+                           (unsigned long long)s->res_bytes, (unsigned long long)s->alloc->size());
+            rc = RPQ_ENOMEM;
+        }
+        hipStream_t st = nullptr;
+        if (rc == RPQ_OK && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            rpq::set_error("stream creation failed");
+            rc = RPQ_EDEVICE;
+        }
+        if (rc == RPQ_OK) rc = rpq::resident_create(g, W, opts->resident_slots, Q, succ, s->pool + s->res_off,
+                                                    s->res_bytes, st, &s->res);
+        if (st) (void)hipStreamDestroy(st);
+        if (rc != RPQ_OK) {
+            delete s;
+            return rc;
+        }
+        s->res_slot_bytes = s->res_bytes / opts->resident_slots;
+        s->driver = std::thread(driver_main, s);
+    }
     for (uint32_t i = 0; i < nw; ++i) s->workers.emplace_back(worker_main, s);
     *out = s;
     return RPQ_OK;
@@ -313,6 +439,8 @@ int rpq_serve_submit(rpq_server_t s, const rpq_request* r, uint64_t* ticket) {
     }
     j->req = *r;
     const uint64_t pool = s->alloc->size();
+    j->resident = route_resident(s, r);
+    j->t.resident = j->resident ? 1 : 0;
     if (r->kind == RPQ_REQ_RPQ) {
         const uint64_t n = (r->flags & RPQ_ALL_SOURCES) && r->n_sources == 0 ? s->g->V : r->n_sources;
         if (r->flags & RPQ_SPARSE) {
@@ -351,9 +479,14 @@ int rpq_serve_submit(rpq_server_t s, const rpq_request* r, uint64_t* ticket) {
     j->id = s->jobs.size();
     j->t.arrival_ms = r->arrival_ms >= 0 ? r->arrival_ms : s->now_ms();
     *ticket = j->id;
-    s->queue.push_back(j.get());
+    if (j->resident) {
+        s->res_queue.push_back(j.get());
+        s->cv_res.notify_one();
+    } else {
+        s->queue.push_back(j.get());
+        s->cv_work.notify_one();
+    }
     s->jobs.push_back(std::move(j));
-    s->cv_work.notify_one();
     return RPQ_OK;
 }
 
@@ -408,12 +541,15 @@ int rpq_serve_stats(rpq_server_t s, rpq_server_stats* out) {
     out->submitted = s->jobs.size();
     out->completed = s->completed;
     out->failed = s->failed;
-    out->queued = s->queue.size();
-    out->running = s->running;
+    out->queued = s->queue.size() + s->res_queue.size();
+    out->running = s->running + s->res_running;
     out->pool_bytes = s->alloc->size();
     out->pool_in_use = s->alloc->used();
     out->pool_peak = s->alloc->peak();
     out->product_edges = s->eprod;
+    out->resident_completed = s->res_completed;
+    out->resident_launches = s->res_launches;
+    out->resident_bytes = s->res ? s->res_bytes : 0;
     return RPQ_OK;
 }
 
@@ -424,8 +560,11 @@ int rpq_serve_stop(rpq_server_t s) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stopping = true;
         s->cv_work.notify_all();
+        s->cv_res.notify_all();
     }
+    if (s->driver.joinable()) s->driver.join();
     for (auto& t : s->workers) t.join();
+    rpq::resident_destroy(s->res);
     delete s;
     return RPQ_OK;
 }

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
     assert sorted(rpq.EXPORTED_SYMBOLS) == declared
     for name in declared:
         assert hasattr(lib, name), name
-    assert rpq.rpq_abi_version() == 1
+    assert rpq.rpq_abi_version() == 2
 
 
 def test_struct_sizes_match_header():

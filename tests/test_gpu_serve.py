@@ -206,3 +206,138 @@ def test_submit_rejects(rpq, rmat18):
     assert ok["status"] == 0 and ok["count"] > 0   # the server keeps serving after a failed request
     assert srv.stats()["failed"] == 1
     srv.stop()
+
+
+def engine_takes(rpq, rx, names, states=12, succ=4):
+    """The server's routing rule for the resident engine's automaton limits."""
+    nfa = rpq.rpq_nfa_compile(rx, names)
+    most = max(bin(int(nfa.delta[i])).count("1") for i in range(len(nfa.delta)))
+    return nfa.n_states <= states and most <= succ
+
+
+def test_resident_engine_admits_while_running_and_matches_oracle(rpq, rmat18, og18):
+    """Dense RPQs go to the resident engine (a persistent batched kernel fed between bounded
+    launches); a second wave is submitted while the first runs and joins the same device unit
+    queue.  Every result equals the oracle's and the request's result alone; CRPQs and sparse
+    requests run on the worker streams at the same time."""
+    import time
+
+    import torch
+    el, g = rmat18
+    rng = np.random.default_rng(611)
+    T = oracle_threads()
+    items = []
+    for i in range(36):
+        rx = synth.random_regex(rng, el.names[:6], max_leaves=6)
+        if i % 6 == 5:
+            # light CRPQs (no closures): they only have to run on the workers beside the engine
+            s = int(rng.integers(0, el.n_vertices))
+            if i % 12 == 5:
+                items.append(("crpq", [(0, "e", 1), (1, "f|g", 2)], 3, [s, None, None]))
+            else:
+                items.append(("crpq", [(0, "a.b", 1), (0, "c|d", 1)], 2, [s, None]))
+        elif i % 6 == 4:
+            items.append(("rpq_sparse", rx, np.array([int(rng.integers(0, el.n_vertices))], np.uint32)))
+        elif i % 2 == 0:
+            items.append(("single", rx, np.array([int(rng.integers(0, el.n_vertices))], np.uint32)))
+        else:
+            lo = int(rng.integers(0, el.n_vertices - 300))
+            items.append(("slice", rx, np.arange(lo, lo + 300, dtype=np.uint32)))
+    want, alone = [], []
+    for i, it in enumerate(items):
+        say("case: resident oracle/alone %d %s" % (i, it[:2]))
+        if it[0] == "crpq":
+            want.append(oracle_result(og18, it))
+            alone.append(run_alone(rpq, g, el, it))
+            continue
+        kind, rx, src = it
+        w = oracle.rpq(og18, rx, sources=src, threads=T)
+        want.append(w)
+        nfa = rpq.rpq_nfa_compile(rx, el.names)
+        a = rpq.rpq_eval(g, nfa, src, flags=rpq.RPQ_SPARSE if kind == "rpq_sparse" else 0,
+                         pairs=True if kind != "slice" else None, per_source=True if kind == "slice" else None)
+        alone.append(a)
+    say("case: resident engine, 16 slots of 64 sources, 2 workers")
+    srv = rpq.Server(g, 16 << 30, workers=2, resident_slots=16, resident_width=64, resident_iters=4)
+    subs = []
+
+    def submit_item(it):
+        if it[0] == "crpq":
+            _, atoms, nv, binding = it
+            return srv.submit_crpq(atoms, nv, binding=binding), None, None
+        kind, rx, src = it
+        nfa = rpq.rpq_nfa_compile(rx, el.names)
+        if kind == "slice":
+            ps = torch.full((src.size, 2), -1, dtype=torch.int64, device="cuda")
+            return srv.submit_rpq(nfa, src, per_source=ps), None, ps
+        buf = torch.empty(1 << 20, dtype=torch.int64, device="cuda")
+        flags = rpq.RPQ_SPARSE if kind == "rpq_sparse" else 0
+        return srv.submit_rpq(nfa, src, flags=flags, pairs=buf), buf, None
+
+    half = len(items) // 2
+    for it in items[:half]:
+        subs.append(submit_item(it))
+    # the second wave arrives while the first is on the device
+    t0 = time.perf_counter()
+    while srv.stats()["resident_launches"] < 1 and time.perf_counter() - t0 < 30:
+        time.sleep(0.0005)
+    for it in items[half:]:
+        subs.append(submit_item(it))
+    done = [srv.wait(t) for t, _, _ in subs]
+    st = srv.stats()
+    srv.stop()
+    say("resident stats", st)
+    assert st["failed"] == 0 and st["completed"] == len(items) and st["pool_in_use"] == st["resident_bytes"]
+    n_res = 0
+    for it, (t, buf, ps), d, w, a in zip(items, subs, done, want, alone):
+        assert d["status"] == 0, (it[:2], d)
+        if it[0] == "crpq":
+            assert not d["resident"]
+            assert (d["count"], d["hash"]) == w[:2] == a[:2], it
+            continue
+        kind = it[0]
+        assert d["resident"] == (kind in ("single", "slice") and engine_takes(rpq, it[1], el.names)), (kind, d)
+        n_res += d["resident"]
+        assert (d["count"], d["hash"], d["product_edges"]) == (w.count, w.hash, w.product_edges), it[:2]
+        assert (d["count"], d["hash"], d["product_edges"]) == (a.count, a.hash, a.product_edges), it[:2]
+        if kind == "slice":
+            assert np.array_equal(ps.cpu().numpy().view(np.uint64), w.per_source), it[:2]
+        else:
+            got = buf[: d["written"]].cpu().numpy().view(np.uint64)
+            assert d["written"] == d["count"]
+            assert np.array_equal(got, w.pairs), it[:2]
+    assert n_res == st["resident_completed"] == sum(1 for it in items if it[0] in ("single", "slice")
+                                                    and engine_takes(rpq, it[1], el.names))
+    assert n_res >= 20
+    assert st["resident_launches"] >= 2
+    # continuous admission: some second-wave request joined while a first-wave one was still running
+    first_end = max(d["end_ms"] for d, it in zip(done[:half], items[:half]) if it[0] in ("single", "slice"))
+    assert any(d["resident"] and d["start_ms"] < first_end for d in done[half:])
+
+
+def test_resident_engine_worker_fallback_and_small_pairs(rpq):
+    """On the uniform graph: automata larger than the engine's go to the workers; many single-source
+    requests with pairs on the engine equal the oracle's keys."""
+    import torch
+    el = synth.workload_graph("uniform_v1000_e5000_l4")
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
+    og = oracle.OracleGraph.from_edgelist(el)
+    srv = rpq.Server(g, 1 << 30, workers=2, resident_slots=8, resident_width=64, resident_states=4)
+    rng = np.random.default_rng(12)
+    reqs = []
+    for i in range(60):
+        rx = ["a.b.c*", "(a|b)*.d", "a*", "a.b.c.d.a.b"][i % 4]    # the last has 7 states: workers
+        src = np.array([int(rng.integers(0, el.n_vertices))], np.uint32)
+        buf = torch.empty(4096, dtype=torch.int64, device="cuda")
+        reqs.append((rx, src, buf, srv.submit_rpq(rpq.rpq_nfa_compile(rx, el.names), src, pairs=buf)))
+    say("case: resident engine on the uniform graph, 60 single-source requests")
+    for rx, src, buf, t in reqs:
+        d = srv.wait(t)
+        w = oracle.rpq(og, rx, sources=src)
+        assert d["status"] == 0 and d["resident"] == (rx != "a.b.c.d.a.b"), (rx, d)
+        assert (d["count"], d["hash"], d["product_edges"]) == (w.count, w.hash, w.product_edges), rx
+        assert np.array_equal(buf[: d["written"]].cpu().numpy().view(np.uint64), w.pairs), rx
+    st = srv.stats()
+    srv.stop()
+    assert st["failed"] == 0 and st["resident_completed"] == 45
+    g.close()
