@@ -166,3 +166,63 @@ def test_batch_invalid_sources_and_overflow(rpq):
     assert got.status == rpq.RPQ_EOVERFLOW and got.count == ref.count
     b.close()
     g.close()
+
+
+def test_batch_autotune_then_run_matches_plain_and_oracle(rpq):
+    """rpq_batch_autotune times candidate plans on a prefix of the queue; the plan it keeps must give
+    every query exactly its plain result, and the oracle's for the single-source ones."""
+    el = synth.workload_graph("rmat18_l8")
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
+    og = oracle.OracleGraph.from_edgelist(el)
+    rng = np.random.default_rng(2718)
+    mix = build_mix(rng, el.names, el.n_vertices, 24)
+    b = rpq.rpq_batch_create(g)
+    qids, refs = [], []
+    for rx, src, want_pairs, per_source in mix:
+        nfa = rpq.rpq_nfa_compile(rx, el.names)
+        ref = plain(rpq, g, nfa, src, want_pairs, per_source)
+        refs.append(ref)
+        qids.append(b.add(nfa, src, pairs_capacity=ref.count + 1 if want_pairs else None, per_source=per_source))
+    say("case: autotune 24 queries on rmat18")
+    tuned = b.autotune()
+    say("tuned plan", tuned)
+    assert tuned["batch_width"] in (64, 256, 512, 1024, 2048)
+    b.run()
+    for qi, (rx, src, want_pairs, per_source), ref in zip(qids, mix, refs):
+        got = b.result(qi)
+        assert (got.count, got.hash, got.product_edges) == (ref.count, ref.hash, ref.product_edges), rx
+        if want_pairs:
+            assert np.array_equal(keys(got.pairs), keys(ref.pairs)), rx
+        if per_source:
+            assert np.array_equal(got.per_source.cpu().numpy(), ref.per_source.cpu().numpy()), rx
+        if src.size == 1:
+            want = oracle.rpq(og, rx, sources=src)
+            assert (got.count, got.hash, got.product_edges) == (want.count, want.hash, want.product_edges), rx
+            assert np.array_equal(keys(got.pairs), want.pairs), rx
+    b.close()
+    g.close()
+
+
+def test_batch_tiny_lists_defer_rows_without_changing_results(rpq):
+    """With frontier lists, slice buffers and first-visit logs sized for 1/64 of the worst case, rows
+    that do not fit wait for a later iteration (and overflowing logs clear their slot whole): every
+    result must stay the plain one.  A length-bounded query needs exact depths and refuses the setting."""
+    el = synth.workload_graph("rmat18_l8")
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
+    rng = np.random.default_rng(64)
+    mix = []
+    for i in range(12):
+        rx = ["a*", "a.b*", "(a|b).c*", "(a.b)*"][i % 4] if i < 4 else synth.random_regex(rng, el.names)
+        if i % 3 == 0:
+            mix.append((rx, np.array([int(rng.integers(0, el.n_vertices))], np.uint32), True, False))
+        else:
+            lo = int(rng.integers(0, el.n_vertices - 1024))
+            mix.append((rx, np.arange(lo, lo + 1024, dtype=np.uint32), False, True))
+    check_batch(rpq, g, el, mix, dict(batch_width=256, slots=6, list_share=64), runs=2)
+    b = rpq.rpq_batch_create(g, dict(batch_width=64, slots=2, list_share=64))
+    b.add(rpq.rpq_nfa_compile("a*", el.names), np.array([1, 2], np.uint32), max_length=3)
+    with pytest.raises(rpq.RpqError) as e:
+        b.run()
+    assert e.value.code == rpq.RPQ_EINVAL
+    b.close()
+    g.close()
