@@ -96,6 +96,11 @@ def parse_args():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving: measured seconds per rate")
     ap.add_argument("--serve-warmup-seconds", type=float, default=2.0, help="serving: warm-up seconds per rate")
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-resident-slots", type=int, default=8,
+                    help="serving: slots of the resident engine that runs the single-source RPQs (0 = off: "
+                         "they run on the workers with the hash-set search)")
+    ap.add_argument("--serve-resident-iters", type=int, default=8,
+                    help="serving: iterations per launch of the resident engine")
     ap.add_argument("--serve-pool-gib", type=float, default=96.0)
     ap.add_argument("--serve-max-requests", type=int, default=4000,
                     help="serving: cap on requests per rate (keeps the FIFO comparison bounded)")
@@ -290,12 +295,13 @@ def serve_main(args):
                              names=el.names)
     points, identical = serve_points(g, el, spec["seed"], args.qps, args.serve_seconds, args.serve_warmup_seconds,
                                      args.serve_workers, args.serve_pool_gib, args.serve_max_requests,
-                                     args.serve_max_requests)
+                                     args.serve_max_requests, resident_slots=args.serve_resident_slots,
+                                     resident_iters=args.serve_resident_iters)
     line = {
         "metric": "p99 latency (serving)", "value": points[-1]["p99_ms"] if points else None, "unit": "ms",
         "n_gpus": 1, "higher_is_better": False, "dtype": "u64", "data": "synthetic (seeded R-MAT; Poisson arrivals)",
-        "config": {"workload": "%s serving: %d workers, %.0f GiB pool" % (args.workload, args.serve_workers,
-                                                                          args.serve_pool_gib)},
+        "config": {"workload": "%s serving: %d workers, %d resident slots, %.0f GiB pool" % (
+            args.workload, args.serve_workers, args.serve_resident_slots, args.serve_pool_gib)},
         "results_identical_to_alone": identical, "points": points,
     }
     print(json.dumps(line), flush=True)
@@ -688,7 +694,8 @@ def main():
         torch.cuda.empty_cache()
         points, identical = serve_points(g, el, spec["seed"], args.serve_leg, args.serve_leg_seconds, 2.0,
                                          args.serve_workers, args.serve_pool_gib, args.serve_max_requests,
-                                         args.serve_leg_burst)
+                                         args.serve_leg_burst, resident_slots=args.serve_resident_slots,
+                                         resident_iters=args.serve_resident_iters)
         serving = dict(points=points, results_identical_to_alone=identical,
                        p50_ms={str(p["qps"]): p["p50_ms"] for p in points},
                        p99_ms={str(p["qps"]): p["p99_ms"] for p in points},

@@ -118,6 +118,8 @@ struct rpq_server {
     uint32_t res_width = 64, res_max_units = 0;
     std::chrono::steady_clock::time_point t0;
 
+    uint64_t worker_pool() const { return alloc->size() - (res ? ((res_bytes + 255) & ~255ull) : 0); }
+
     double now_ms() const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -252,7 +254,7 @@ void worker_main(rpq_server* s) {
         lk.lock();
         s->alloc->release(off, std::max<uint64_t>(j->need, kAlign));
         --s->running;
-        if (rc == RPQ_ENOMEM && needed > j->need && needed <= s->alloc->size()) {
+        if (rc == RPQ_ENOMEM && needed > j->need && needed <= s->worker_pool()) {
             j->need = needed;              // run again with the workspace the library asked for
             s->queue.push_front(j);
         } else {
@@ -438,7 +440,8 @@ int rpq_serve_submit(rpq_server_t s, const rpq_request* r, uint64_t* ticket) {
         return RPQ_ENOMEM;
     }
     j->req = *r;
-    const uint64_t pool = s->alloc->size();
+    // the part of the pool the workers can ever get (the resident engine holds the rest)
+    const uint64_t pool = s->worker_pool();
     j->resident = route_resident(s, r);
     j->t.resident = j->resident ? 1 : 0;
     if (r->kind == RPQ_REQ_RPQ) {

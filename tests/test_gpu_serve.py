@@ -341,3 +341,31 @@ def test_resident_engine_worker_fallback_and_small_pairs(rpq):
     srv.stop()
     assert st["failed"] == 0 and st["resident_completed"] == 45
     g.close()
+
+
+def test_resident_engine_leaves_workers_a_pool_they_can_use(rpq, rmat18):
+    """Worker requests are planned against the part of the pool the engine does not hold: with a pool
+    only a little larger than the engine, dense requests for the workers are split to fit and finish
+    (regression: they were planned against the whole pool and waited forever)."""
+    import torch
+    el, g = rmat18
+    probe = rpq.Server(g, 4 << 30, workers=1, resident_slots=4)
+    res_bytes = probe.stats()["resident_bytes"]
+    probe.stop()
+    rx = "a.b*"
+    nfa = rpq.rpq_nfa_compile(rx, el.names)
+    src = np.arange(1000, 1512, dtype=np.uint32)   # 8 units of 64: pairs go to the workers
+    small = rpq.rpq_eval_workspace_size(g, nfa, src.size, rpq.RPQ_PAIRS, dict(batch_width=64, concurrency=1))
+    full = rpq.rpq_eval_workspace_size(g, nfa, src.size, rpq.RPQ_PAIRS)
+    pool = res_bytes + int(small * 1.5) + (1 << 20)
+    assert full > pool - res_bytes     # the default plan does not fit what the workers get
+    ref = rpq.rpq_eval(g, nfa, src, pairs=True)
+    say("case: resident engine + a worker pool of %d bytes (default plan %d)" % (pool - res_bytes, full))
+    srv = rpq.Server(g, pool, workers=1, resident_slots=4)
+    buf = torch.empty(ref.count + 16, dtype=torch.int64, device="cuda")
+    t = srv.submit_rpq(nfa, src, pairs=buf)
+    d = srv.wait(t)
+    srv.stop()
+    assert d["status"] == 0 and not d["resident"]
+    assert (d["count"], d["hash"], d["product_edges"]) == (ref.count, ref.hash, ref.product_edges)
+    assert np.array_equal(buf[: d["written"]].cpu().numpy(), ref.pairs.cpu().numpy())
