@@ -199,9 +199,10 @@ int rpq_nfa_reverse(const rpq_nfa* in, rpq_nfa* out);
 /* Tuning knobs; zero fields take defaults (the autotuner's choice when one is cached). */
 typedef struct {
     uint32_t batch_width;    /* sources per unit: 64, 128, 256, 512, 1024, 2048 or 4096
-                                (0 = the widest up to 2048 that n_sources / 8 fills) */
-    uint32_t concurrency;    /* units advanced together (0 = ~64K sources in flight,
-                                workspace <= 64 GB) */
+                                (0 = the widest up to 2048, or 4096 on graphs of 2^22 vertices
+                                or more, that n_sources / 8 fills) */
+    uint32_t concurrency;    /* units advanced together (0 = ~64K sources in flight within
+                                64 GB of workspace, at least one unit) */
     uint32_t sync_every;     /* levels launched between host checks for the fixpoint (0 = 4) */
     uint32_t chunk_edges;    /* items (edge x successor state) per expansion work slice: entries
                                 with more items are cut into slices of this size (0 = 16, raised

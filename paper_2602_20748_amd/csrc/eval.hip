@@ -130,7 +130,7 @@ __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint6
 //               contiguous K-word access instead of K scattered ones.
 // kUnroll items per group are loaded before any of them is updated (memory-level parallelism).
 // ------------------------------------------------------------------------------------------------
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;
 
 template <int K>
 __device__ __forceinline__ void expand_segments(const Args& a, const uint32_t* s_delta, const uint64_t* rows,
@@ -708,26 +708,30 @@ void to_dev_nfa(const rpq_nfa* nfa, uint32_t L, DevNfa* d) {
         }
 }
 
-// Default shape: about 64K sources in flight, in units of up to 2048 sources (measured on
-// R-MAT scale 18, all-pairs: throughput rises with the sources advanced per level up to ~64K;
-// 2048-wide units beat 1024 and 4096 at equal sources in flight), entries of more than 16
-// items cut into slices (16 beat 32, 64, 128 and 256 there; raised on graphs where the slice
-// buffers would outgrow a quarter of the bitmaps), and per-call workspace within 64 GB of the
-// 288 GB device.
+// Default shape: about 64K sources in flight, in units of up to 2048 sources below 2^22
+// vertices and 4096 from there (measured: R-MAT scale 18 all-pairs, where throughput rises with
+// the sources advanced per level up to ~64K and 2048-wide units beat 1024 and 4096; R-MAT
+// scale 23 from 65,536 sources, where 4096-wide units beat 2048 by 5% and 1024 lost 6%), entries
+// of more than 16 items cut into slices (16 beat 32, 64, 128 and 256; raised on graphs where the
+// slice buffers would outgrow a quarter of the bitmaps).  Units in flight are sized for 64 GB of
+// the 288 GB device, and a unit of the default width may take up to 96 GB alone (at scale 23 one
+// 4096-wide unit per group, 3.45 s per step, beat two per group within 96 GB, 3.57 s).
 constexpr uint64_t kTargetInFlight = 65536;
 constexpr uint64_t kWorkspaceBudget = 64ull << 30;
-constexpr uint32_t kMaxDefaultWidth = 2048;
+constexpr uint64_t kUnitBudget = 96ull << 30;
 constexpr uint32_t kDefaultChunk = 16;
+
+uint32_t max_default_width(uint32_t V) { return V >= (1u << 22) ? 4096 : 2048; }
 
 uint64_t unit_bytes(uint64_t QV, uint32_t W) {
     // Vis + Next + two frontier lists of rows + row ids
     return QV * (W / 8) * 4 + QV * 8;
 }
 
-uint32_t default_width(uint64_t n_sources, uint64_t QV) {
+uint32_t default_width(uint64_t n_sources, uint64_t QV, uint32_t V) {
     uint32_t W = 64;
-    while (W < kMaxDefaultWidth && (uint64_t)W * 2 <= std::max<uint64_t>(64, n_sources / 8)) W *= 2;
-    while (W > 64 && unit_bytes(QV, W) > kWorkspaceBudget) W /= 2;
+    while (W < max_default_width(V) && (uint64_t)W * 2 <= std::max<uint64_t>(64, n_sources / 8)) W *= 2;
+    while (W > 64 && unit_bytes(QV, W) > kUnitBudget) W /= 2;
     return W;
 }
 
@@ -738,7 +742,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     x.Q = dn.Q;
     x.L = g->L;
     x.V = g->V;
-    x.W = (o && o->batch_width) ? o->batch_width : default_width(n_sources, (uint64_t)dn.Q * g->V);
+    x.W = (o && o->batch_width) ? o->batch_width : default_width(n_sources, (uint64_t)dn.Q * g->V, g->V);
     if (x.W != 64 && x.W != 128 && x.W != 256 && x.W != 512 && x.W != 1024 && x.W != 2048 && x.W != 4096) {
         rpq::set_error("batch_width must be 64, 128, 256, 512, 1024, 2048 or 4096");
         return RPQ_EINVAL;
