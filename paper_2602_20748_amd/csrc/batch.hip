@@ -781,7 +781,8 @@ __device__ void phase_finalize(const BArgs& a, int p, uint32_t iter, uint64_t& t
                     rows[(e0 + idx) * K + k] = sp[u] ? 0 : nk[u];
                     if (nk[u]) {
                         a.next[(uint64_t)r[u] * K + k] = 0;
-                        or_relaxed(a.vis + (uint64_t)r[u] * K + k, nk[u]);
+                        // the row is on the list once and nothing else writes its Vis word in this phase
+                        a.vis[(uint64_t)r[u] * K + k] |= nk[u];
                         pc = (uint32_t)__popcll(nk[u]);
                         ++t_fwords;
                         if (an[u] != 0xFFFFFFFFu) or_relaxed(a.ans + (uint64_t)an[u] * K + k, nk[u]);

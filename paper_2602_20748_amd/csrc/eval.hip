@@ -382,7 +382,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_wo
                     rows[(e0 + idx) * K + k] = nk[u];
                     if (nk[u]) {
                         a.next[(uint64_t)r[u] * K + k] = 0;
-                        or_relaxed(&a.vis[(uint64_t)r[u] * K + k], nk[u]);
+                        // a row is on the list once, and nothing else writes its Vis word in this
+                        // kernel: a plain read-modify-write (an atomic OR cost 0.82 vs 0.69 ms a launch)
+                        a.vis[(uint64_t)r[u] * K + k] |= nk[u];
                         if (an[u] != 0xFFFFFFFFu) or_relaxed(&a.ans[(uint64_t)an[u] * K + k], nk[u]);
                         pc = (uint32_t)__popcll(nk[u]);
                     }
