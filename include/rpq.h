@@ -29,15 +29,22 @@
  *     before returning.
  *   - Inputs are validated before any traversal kernel runs; invalid input
  *     yields RPQ_EINVAL and leaves outputs untouched.
- *   - A graph handle may be used from one host thread at a time.
+ *   - A graph is read-only after rpq_graph_create: calls from several host
+ *     threads may use one graph at once (each with its own workspace and
+ *     stream; the server does so), but rpq_graph_destroy must follow them all.
+ *     A batch handle is used from one host thread at a time; a server's calls
+ *     may come from any thread.
  *   - Device memory: only rpq_graph_create allocates it (the graph); every other
- *     call works in caller-owned device buffers (workspaces, outputs).  Host-side
+ *     call works in caller-owned device buffers (workspaces, outputs), and
+ *     rpq_eval_noalloc in the library's static scratch array.  Host-side
  *     runtime objects created after rpq_graph_create: rpq_eval keeps, per host
  *     thread, a 4 KB pinned staging buffer for counter reads and a second stream
- *     for extraction (both created on the thread's first use, kept until the
- *     process ends); rpq_batch_create pins a small control block; rpq_batch_run
- *     creates a capture stream, two timing events and the executable graph of
- *     its batch; rpq_serve_start creates one stream per worker thread.
+ *     for extraction, and rpq_eval_stream a copy stream (all created on the
+ *     thread's first use, kept until the process ends); rpq_batch_create pins a
+ *     small control block; rpq_batch_run creates a capture stream, two timing
+ *     events and the executable graph of its batch; rpq_serve_start creates one
+ *     stream per worker thread and, with the resident engine, a driver thread
+ *     with its stream and five pinned buffers (freed by rpq_serve_stop).
  */
 #ifndef RPQ_H
 #define RPQ_H

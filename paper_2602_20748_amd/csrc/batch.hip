@@ -88,7 +88,7 @@ struct BCtl {
     unsigned long long list_cnt[2], desc_cnt[2];
     unsigned long long queue_head;      // units handed to slots
     unsigned long long units_tail;      // open form: units published by the host
-    unsigned long long n_running, n_retiring, n_pairs_retiring;
+    unsigned long long n_running, n_retiring, n_pairs_retiring, n_started;
     unsigned long long err, iterations;
     unsigned long long items, descs, wreads, wupds;
     unsigned long long frows, fwords;   // finalize tallies: rows, non-zero next words
@@ -380,7 +380,8 @@ __device__ void phase_compact(const BArgs& a, int p, uint32_t iter) {
 // ------------------------------------------------------------------------------------------------
 // decide (block 0): running slots that produced no touched rows this iteration retire
 // ------------------------------------------------------------------------------------------------
-__device__ void phase_decide(const BArgs& a, uint32_t iter) {
+// Returns (to every thread of block 0) the number of slots that retire.
+__device__ uint32_t phase_decide(const BArgs& a, uint32_t iter) {
     __shared__ uint32_t s_n, s_pairs;
     if (threadIdx.x == 0) {
         s_n = 0;
@@ -397,10 +398,12 @@ __device__ void phase_decide(const BArgs& a, uint32_t iter) {
         }
     }
     __syncthreads();
+    const uint32_t n = s_n;
     if (threadIdx.x == 0) {
-        st64(&a.ctl->n_retiring, s_n);
+        st64(&a.ctl->n_retiring, n);
         st64(&a.ctl->n_pairs_retiring, s_pairs);
     }
+    return n;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -576,11 +579,12 @@ __device__ void phase_retire_clear(const BArgs& a, uint32_t n_ret) {
 // refill (block 0 assigns units to idle slots), then every block seeds the new units
 // ------------------------------------------------------------------------------------------------
 __device__ void phase_assign(const BArgs& a, uint32_t iter) {
-    __shared__ uint32_t s_running, s_idle;
+    __shared__ uint32_t s_running, s_idle, s_started;
     __shared__ unsigned long long s_head, s_avail;
     if (threadIdx.x == 0) {
         s_running = 0;
         s_idle = 0;
+        s_started = 0;
         const unsigned long long head = ld(&a.ctl->queue_head);
         const unsigned long long tail = a.open_form ? ld(&a.ctl->units_tail) : (unsigned long long)a.n_units;
         s_head = head;
@@ -614,6 +618,7 @@ __device__ void phase_assign(const BArgs& a, uint32_t iter) {
                 st32(&a.slots[s].state, S_RUN);
                 // seeding happens in phase_seed for slots whose start_iter == iter
                 st = S_RUN;
+                atomicAdd(&s_started, 1u);
             }
         }
         if (st == S_RUN) atomicAdd(&s_running, 1u);
@@ -621,6 +626,7 @@ __device__ void phase_assign(const BArgs& a, uint32_t iter) {
     __syncthreads();
     if (threadIdx.x == 0) {
         st64(&a.ctl->n_running, s_running);
+        st64(&a.ctl->n_started, s_started);
         st64(&a.ctl->queue_head, head + min((unsigned long long)s_idle, avail));
     }
 }
@@ -876,7 +882,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
         BAR(0);
         phase_compact(a, p, iter);
         BAR(1);
-        if (blockIdx.x == 0) phase_decide(a, iter);
+        // block 0 decides which slots retire; when none does, it refills at once (nothing to retire
+        // first), which saves the refill's barrier
+        if (blockIdx.x == 0 && phase_decide(a, iter) == 0) phase_assign(a, iter);
         BAR(2);
         const uint32_t n_ret = (uint32_t)ld(&a.ctl->n_retiring);
         if (n_ret) {
@@ -890,12 +898,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
             }
             phase_retire_clear<K>(a, n_ret);
             BAR(5);
+            if (blockIdx.x == 0) phase_assign(a, iter);
+            BAR(6);
         }
-        if (blockIdx.x == 0) phase_assign(a, iter);
-        BAR(6);
         if (ld(&a.ctl->n_running) == 0) break;
-        phase_seed<K>(a, p, iter);
-        BAR(6);
+        // seeding only when a slot took a unit in this iteration
+        if (ld(&a.ctl->n_started)) {
+            phase_seed<K>(a, p, iter);
+            BAR(6);
+        }
         phase_finalize<K>(a, p, iter, t_frows, t_fwords);
         BAR(7);
         p ^= 1;
