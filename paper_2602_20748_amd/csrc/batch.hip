@@ -39,7 +39,9 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kUnroll = 4;                 // rows per lane group loaded before any is updated
 constexpr uint32_t kChunkV = 4096;          // vertices per extraction chunk (64 summary words)
 
-constexpr uint32_t S_IDLE = 0, S_RUN = 1, S_RETIRE = 2;
+// S_RETIRE: retiring in this iteration's retire phases (queries with pairs); S_DRAIN: retiring in the
+// next iteration, its extraction beside that iteration's expansion and its clear beside its compaction
+constexpr uint32_t S_IDLE = 0, S_RUN = 1, S_RETIRE = 2, S_DRAIN = 3;
 
 // A slice [beg, beg + len) of the item space of frontier entry `entry` (entries with more than
 // H items are cut into such slices of at most H items; lighter ones are expanded straight from
@@ -79,7 +81,7 @@ struct BUnit {
 
 struct BSlot {
     uint32_t state, unit, query, alive;
-    uint32_t start_iter, pad0;
+    uint32_t start_iter, end_iter;   // end_iter: the iteration that found the fixpoint (S_DRAIN)
     unsigned long long log_n;
 };
 
@@ -89,6 +91,7 @@ struct BCtl {
     unsigned long long queue_head;      // units handed to slots
     unsigned long long units_tail;      // open form: units published by the host
     unsigned long long n_running, n_retiring, n_pairs_retiring, n_started;
+    unsigned long long n_drain[2];      // slots to drain, decided by iterations of each parity
     unsigned long long err, iterations;
     unsigned long long items, descs, wreads, wupds;
     unsigned long long frows, fwords;   // finalize tallies: rows, non-zero next words
@@ -120,6 +123,7 @@ struct BArgs {
     Desc* desc1;
     uint32_t* logs;          // [G][slot_stride] first-visited rows (slot-local row ids)
     uint32_t* retiring;      // [G] slot ids retiring this iteration
+    uint32_t* drain;         // [2][G] slot ids to drain, by the parity of the iteration that decided
     uint32_t* partial;       // [G][W][nchunks] pair counts per (source, chunk)
     uint64_t* srcbase;       // [G][W] first staging index of each source of a retiring unit
     uint64_t* stage;         // staging keys of all queries
@@ -388,13 +392,25 @@ __device__ uint32_t phase_decide(const BArgs& a, uint32_t iter) {
         s_pairs = 0;
     }
     __syncthreads();
+    __shared__ uint32_t s_drain;
+    if (threadIdx.x == 0) s_drain = 0;
+    __syncthreads();
+    uint32_t* drain = a.drain + (uint64_t)(iter & 1) * a.G;
     for (uint32_t s = threadIdx.x; s < a.G; s += kBlock) {
         if (ld32(&a.slots[s].state) == S_RUN && ld32(&a.slots[s].alive) != iter) {
-            st32(&a.slots[s].state, S_RETIRE);
-            const uint32_t i = atomicAdd(&s_n, 1u);
-            st32(&a.retiring[i], s);
             const uint32_t qid = ld32(&a.slots[s].query);
-            if (a.queries[qid].pairs) atomicAdd(&s_pairs, 1u);
+            if (a.queries[qid].pairs) {
+                // keys need a prefix over the unit before they are written: retire now
+                st32(&a.slots[s].state, S_RETIRE);
+                const uint32_t i = atomicAdd(&s_n, 1u);
+                st32(&a.retiring[i], s);
+                atomicAdd(&s_pairs, 1u);
+            } else {
+                st32(&a.slots[s].state, S_DRAIN);
+                st32(&a.slots[s].end_iter, iter);
+                const uint32_t i = atomicAdd(&s_drain, 1u);
+                st32(&drain[i], s);
+            }
         }
     }
     __syncthreads();
@@ -402,6 +418,7 @@ __device__ uint32_t phase_decide(const BArgs& a, uint32_t iter) {
     if (threadIdx.x == 0) {
         st64(&a.ctl->n_retiring, n);
         st64(&a.ctl->n_pairs_retiring, s_pairs);
+        st64(&a.ctl->n_drain[iter & 1], s_drain);
     }
     return n;
 }
@@ -410,13 +427,13 @@ __device__ uint32_t phase_decide(const BArgs& a, uint32_t iter) {
 // retire: extraction over the non-empty Ans rows of each retiring slot
 // ------------------------------------------------------------------------------------------------
 template <int K, bool WRITE>
-__device__ void phase_retire_extract(const BArgs& a, uint32_t n_ret) {
+__device__ void phase_retire_extract(const BArgs& a, const uint32_t* list, uint32_t n_ret) {
     const int lane = threadIdx.x & 63;
     const uint64_t total = (uint64_t)n_ret * K * a.nchunks;
     for (uint64_t wv = gwave(a); wv < total; wv += gwaves(a)) {
         const uint32_t chunk = (uint32_t)(wv % a.nchunks);
         const uint32_t k = (uint32_t)((wv / a.nchunks) % K);
-        const uint32_t slot = ld32(&a.retiring[wv / ((uint64_t)a.nchunks * K)]);
+        const uint32_t slot = ld32(&list[wv / ((uint64_t)a.nchunks * K)]);
         const uint32_t u = ld32(&a.slots[slot].unit);
         const BUnit unit = a.units[u & a.unit_mask];
         const BQuery& Qy = a.queries[unit.query];
@@ -531,11 +548,11 @@ __device__ void phase_retire_prefix(const BArgs& a, uint32_t n_ret) {
 
 // clear the rows a retiring unit visited, its Ans rows and summary; the slot becomes idle
 template <int K>
-__device__ void phase_retire_clear(const BArgs& a, uint32_t n_ret) {
+__device__ void phase_retire_clear(const BArgs& a, const uint32_t* list, uint32_t n_ret) {
     const int lane = threadIdx.x & 63;
     // Vis rows from the per-slot log, and the slot's first-visit bits
     for (uint32_t r = 0; r < n_ret; ++r) {
-        const uint32_t slot = ld32(&a.retiring[r]);
+        const uint32_t slot = ld32(&list[r]);
         const uint64_t wps = a.slot_stride / 64;
         for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < wps; i += (uint64_t)a.n_blocks * kBlock)
             a.ever[(uint64_t)slot * wps + i] = 0;
@@ -557,7 +574,7 @@ __device__ void phase_retire_clear(const BArgs& a, uint32_t n_ret) {
     }
     // Ans rows flagged in the summary, then the summary itself
     for (uint32_t r = 0; r < n_ret; ++r) {
-        const uint32_t slot = ld32(&a.retiring[r]);
+        const uint32_t slot = ld32(&list[r]);
         for (uint64_t w0 = gwave(a) * 64; w0 < a.summ_words; w0 += gwaves(a) * 64) {
             const uint64_t wi = w0 + lane;
             uint64_t sw = wi < a.summ_words ? xld(a.summ + (uint64_t)slot * a.summ_words + wi) : 0;
@@ -594,10 +611,12 @@ __device__ void phase_assign(const BArgs& a, uint32_t iter) {
     const unsigned long long head = s_head, avail = s_avail;
     for (uint32_t s = threadIdx.x; s < a.G; s += kBlock) {
         uint32_t st = ld32(&a.slots[s].state);
-        if (st == S_RETIRE) {
-            // retired in this iteration's earlier phases: account its depth, free the slot
+        const bool drained = st == S_DRAIN && ld32(&a.slots[s].end_iter) != iter;
+        if (st == S_RETIRE || drained) {
+            // retired in this iteration's earlier phases (or drained beside its expansion and
+            // compaction): account its depth, free the slot
             const uint32_t qid = a.units[ld32(&a.slots[s].unit) & a.unit_mask].query;
-            const uint32_t depth = iter - ld32(&a.slots[s].start_iter);
+            const uint32_t depth = (drained ? ld32(&a.slots[s].end_iter) : iter) - ld32(&a.slots[s].start_iter);
             atomicMax(&a.qout[qid].max_depth, (unsigned long long)depth);
             atomicAdd(&a.qout[qid].levels, (unsigned long long)depth);
             atomicAdd(&a.qout[qid].units_done, 1ull);
@@ -878,9 +897,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
         // next barrier) and reported as an error
         if (blockIdx.x == 0 && threadIdx.x == 0 && wall_clock64() - t_start > a.deadline)
             __hip_atomic_store(&a.ctl->gs.abort, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // slots that reached their fixpoint in the previous iteration (no pairs to write): their counts
+        // and checksums beside this expansion, their clear beside this compaction (a retiring slot
+        // has no frontier, so its rows are not the ones these phases touch)
+        const uint32_t* drain = a.drain + (uint64_t)((iter - 1) & 1) * a.G;
+        const uint32_t n_dr = (uint32_t)ld(&a.ctl->n_drain[(iter - 1) & 1]);
         phase_expand<K>(a, p, t_items, t_descs, t_wread, t_wupd);
+        if (n_dr) phase_retire_extract<K, false>(a, drain, n_dr);
         BAR(0);
         phase_compact(a, p, iter);
+        if (n_dr) phase_retire_clear<K>(a, drain, n_dr);
         BAR(1);
         // block 0 decides which slots retire; when none does, it refills at once (nothing to retire
         // first), which saves the refill's barrier
@@ -888,20 +914,21 @@ __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
         BAR(2);
         const uint32_t n_ret = (uint32_t)ld(&a.ctl->n_retiring);
         if (n_ret) {
-            phase_retire_extract<K, false>(a, n_ret);
+            phase_retire_extract<K, false>(a, a.retiring, n_ret);
             BAR(3);
             if (ld(&a.ctl->n_pairs_retiring)) {
                 phase_retire_prefix(a, n_ret);
                 BAR(4);
-                phase_retire_extract<K, true>(a, n_ret);
+                phase_retire_extract<K, true>(a, a.retiring, n_ret);
                 BAR(4);
             }
-            phase_retire_clear<K>(a, n_ret);
+            phase_retire_clear<K>(a, a.retiring, n_ret);
             BAR(5);
             if (blockIdx.x == 0) phase_assign(a, iter);
             BAR(6);
         }
-        if (ld(&a.ctl->n_running) == 0) break;
+        // done when no slot runs and none waits to be drained in the next iteration
+        if (ld(&a.ctl->n_running) == 0 && ld(&a.ctl->n_drain[iter & 1]) == 0) break;
         // seeding only when a slot took a unit in this iteration
         if (ld(&a.ctl->n_started)) {
             phase_seed<K>(a, p, iter);
@@ -981,7 +1008,8 @@ struct Layout {
     uint64_t slot_stride, summ_words, list_cap, desc_cap, log_cap, stage_keys;
     uint64_t off_ctl, off_nfas, off_queries, off_qout, off_units, off_slots, off_vis, off_next, off_touch, off_ever,
         off_ans,
-        off_summ, off_ids[2], off_rows[2], off_desc[2], off_logs, off_retiring, off_partial, off_srcbase, off_stage,
+        off_summ, off_ids[2], off_rows[2], off_desc[2], off_logs, off_retiring, off_drain, off_partial, off_srcbase,
+        off_stage,
         off_utotal, off_ustart, off_uprefix, off_scan_tmp, total;
 };
 
@@ -1080,6 +1108,7 @@ void place(const rpq_graph* g, uint32_t nq, uint64_t n_unit_entries, Layout* x) 
     }
     x->off_logs = take(G * x->log_cap * 4);
     x->off_retiring = take(G * 4);
+    x->off_drain = take(2 * G * 4);
     x->off_partial = take(G * x->W * (uint64_t)x->nchunks * 4);
     x->off_srcbase = take(G * x->W * 8);
     x->off_stage = take(std::max<uint64_t>(1, x->stage_keys) * 8);
@@ -1189,6 +1218,7 @@ BArgs args_for(const rpq_graph* g, const Layout& x, char* ws, unsigned n_blocks,
     a.desc1 = reinterpret_cast<Desc*>(ws + x.off_desc[1]);
     a.logs = reinterpret_cast<uint32_t*>(ws + x.off_logs);
     a.retiring = reinterpret_cast<uint32_t*>(ws + x.off_retiring);
+    a.drain = reinterpret_cast<uint32_t*>(ws + x.off_drain);
     a.partial = reinterpret_cast<uint32_t*>(ws + x.off_partial);
     a.srcbase = reinterpret_cast<uint64_t*>(ws + x.off_srcbase);
     a.stage = reinterpret_cast<uint64_t*>(ws + x.off_stage);
