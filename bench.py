@@ -380,6 +380,38 @@ def expand_roofline(prof):
     return method, impl, avg_ms
 
 
+def other_rooflines(prof):
+    """Method bytes and HBM fraction of the two other level-step kernels, from their exact tallies.
+
+    finalize (timed with the compaction that feeds it, one pair per level): 8 B per row id (written by
+      compaction, read by finalize); per row word 16 B (Next read, frontier write); per non-zero word
+      8 B more to clear it and 16 B to read and write the visited word; per such word of a final-state
+      row 16 B for the answer word.  The touch bitmap compaction scans (one bit per row) is left out;
+      the tallies include the seeding finalize of each group (one row per source), which is not timed.
+    extract (count passes, timed on the extraction stream): 8 B per answer word read."""
+    out = {}
+    fl = prof["finalize_launches"]
+    if fl and prof["finalize_ms"] > 0:
+        b = (8 * prof["finalize_rows"] + 16 * prof["finalize_row_words"] + 24 * prof["finalize_words"]
+             + 16 * prof["finalize_ans_words"]) / fl
+        ms = prof["finalize_ms"] / fl
+        a = b / (ms / 1e3) / 1e9
+        out["finalize"] = dict(bound="hbm", achieved=round(a, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
+                               frac=round(a / HBM_PEAK_GBPS, 5), avg_launch_ms=round(ms, 5), launches=fl,
+                               alg_bytes_per_launch=round(b, 1), kernel="k_compact + k_finalize",
+                               counters={k: prof[k] for k in ("finalize_rows", "finalize_row_words",
+                                                              "finalize_words", "finalize_ans_words")})
+    xl = prof["extract_launches"]
+    if xl and prof["extract_ms"] > 0:
+        b = 8 * prof["extract_words"] / xl
+        ms = prof["extract_ms"] / xl
+        a = b / (ms / 1e3) / 1e9
+        out["extract"] = dict(bound="hbm", achieved=round(a, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
+                              frac=round(a / HBM_PEAK_GBPS, 5), avg_launch_ms=round(ms, 5), launches=xl,
+                              alg_bytes_per_launch=round(b, 1), kernel="k_extract (count pass)")
+    return out
+
+
 def host_cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -589,7 +621,9 @@ def main():
         method, impl, avg_ms = expand_roofline(prof)
         achieved = method / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
         achieved_impl = impl / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+        step_rooflines = other_rooflines(prof)
         forms["plain"] = dict(
+            step_rooflines=step_rooflines,
             value=eprod / secs, ms_per_step=secs * 1e3 / args.steps, distinct_pairs_per_s=pairs / secs,
             per_query=per_query,
             roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
@@ -737,9 +771,11 @@ def main():
         "batched_over_plain": batched_over_plain,
         "batched_vs_plain_mixes": mix_results,
         "serving": serving,
-        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "roofline"} for k, v in forms.items()},
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk not in ("roofline", "step_rooflines")}
+                  for k, v in forms.items()},
         "roofline": main_form["roofline"],
-        "roofline_other": {k: v["roofline"] for k, v in forms.items() if k != form},
+        "roofline_other": dict({k: v["roofline"] for k, v in forms.items() if k != form},
+                               **(forms["plain"].get("step_rooflines") or {}) if "plain" in forms else {}),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

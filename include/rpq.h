@@ -661,6 +661,7 @@ int rpq_serve_stop(rpq_server_t s);
  *   word_reads    8-byte visited words read, each with the 8-byte next-frontier word beside it
  *                 (frontier word != 0)
  *   word_updates  8-byte atomic ORs into the next-frontier bitmap (bits not yet there)
+ * and of finalize (finalize_*) and of the extraction's count passes (extract_*).
  */
 typedef struct {
     uint64_t expand_launches;
@@ -672,6 +673,13 @@ typedef struct {
     uint64_t row_words;
     uint64_t word_reads;
     uint64_t word_updates;
+    uint64_t finalize_rows;      /* rows moved from Next to the frontier by finalize */
+    uint64_t finalize_row_words; /* their 8-byte words (each read from Next, written to the frontier) */
+    uint64_t finalize_words;     /* their non-zero 8-byte Next words (each ORed into Vis, then cleared) */
+    uint64_t finalize_ans_words; /* those of final-state rows (each also ORed into Ans) */
+    uint64_t extract_launches;   /* extraction count passes, timed on the extraction stream */
+    double extract_ms;
+    uint64_t extract_words;      /* 8-byte answer words those passes read */
 } rpq_profile;
 
 /* Turn event timing of the level kernels on (1) or off (0).  Process-wide. */

@@ -82,7 +82,11 @@ class Profile(ctypes.Structure):
     _fields_ = [("expand_launches", ctypes.c_uint64), ("expand_ms", ctypes.c_double),
                 ("finalize_launches", ctypes.c_uint64), ("finalize_ms", ctypes.c_double),
                 ("edge_items", ctypes.c_uint64), ("descriptors", ctypes.c_uint64), ("row_words", ctypes.c_uint64),
-                ("word_reads", ctypes.c_uint64), ("word_updates", ctypes.c_uint64)]
+                ("word_reads", ctypes.c_uint64), ("word_updates", ctypes.c_uint64),
+                ("finalize_rows", ctypes.c_uint64), ("finalize_row_words", ctypes.c_uint64),
+                ("finalize_words", ctypes.c_uint64),
+                ("finalize_ans_words", ctypes.c_uint64), ("extract_launches", ctypes.c_uint64),
+                ("extract_ms", ctypes.c_double), ("extract_words", ctypes.c_uint64)]
 
 
 class BatchOpts(ctypes.Structure):

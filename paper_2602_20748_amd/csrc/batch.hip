@@ -1953,12 +1953,9 @@ int resident_admit(Resident* r, const ResidentQuery& q, uint64_t token) {
 
 bool resident_idle(const Resident* r) { return r->staged.empty() && r->n_active == 0; }
 
-int resident_step(Resident* r, uint32_t max_iters, hipStream_t stream, std::vector<ResidentDone>* done) {
-    if (r->broken) {
-        res_fail_all(r, RPQ_EDEVICE, done);
-        rpq::set_error("resident engine is out of service after a device error");
-        return RPQ_EDEVICE;
-    }
+namespace {
+
+int step_body(Resident* r, uint32_t max_iters, hipStream_t stream, std::vector<ResidentDone>* done) {
     const Layout& x = r->x;
     // 1. sources of the staged queries: strictly ascending ids below V, checked before any unit of
     //    them is published
@@ -2087,6 +2084,24 @@ int resident_step(Resident* r, uint32_t max_iters, hipStream_t stream, std::vect
     }
     while (r->q_hi > 0 && !r->table[r->q_hi - 1].used) --r->q_hi;
     return RPQ_OK;
+}
+
+}  // namespace
+
+int resident_step(Resident* r, uint32_t max_iters, hipStream_t stream, std::vector<ResidentDone>* done) {
+    if (r->broken) {
+        res_fail_all(r, RPQ_EDEVICE, done);
+        rpq::set_error("resident engine is out of service after a device error");
+        return RPQ_EDEVICE;
+    }
+    const int rc = step_body(r, max_iters, stream, done);
+    if (rc != RPQ_OK && !r->broken) {
+        // a failed HIP call leaves the device state unknown: nothing staged or in flight can finish
+        (void)hipStreamSynchronize(stream);
+        r->broken = true;
+        res_fail_all(r, rc, done);
+    }
+    return rc;
 }
 
 }  // namespace rpq

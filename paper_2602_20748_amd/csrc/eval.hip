@@ -61,7 +61,10 @@ constexpr int C_ROWW = 12;
 constexpr int C_WREAD = 13;
 constexpr int C_WUPD = 14;
 constexpr int C_LASTLEVEL = 15; // 1 + highest level index whose finalize appended rows (this group)
-constexpr int C_NCOUNTERS = 16;
+constexpr int C_FROWS = 16;     // finalize tallies (profiling): rows finalized,
+constexpr int C_FWORDS = 17;    //   their non-zero Next words,
+constexpr int C_FANS = 18;      //   and those of rows of final states
+constexpr int C_NCOUNTERS = 19;
 
 constexpr uint64_t ERR_LIST = 1, ERR_DESC = 2, ERR_SOURCES = 4;
 
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_wo
     const uint32_t H = a.H, V = a.V;
     const uint32_t QV = a.Q * a.V;
     const uint32_t fin = s_final;
-    uint64_t eprod = 0;
+    uint64_t eprod = 0, t_rows = 0, t_words = 0, t_ans = 0;
     const uint64_t n_waves = (uint64_t)gridDim.x * kWaves;
     const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     for (uint64_t e0 = wave * 64; e0 < n; e0 += n_waves * 64) {
@@ -362,6 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_wo
         // Ans row of a final-state entry, else none
         const uint32_t my_ans = ((fin >> q) & 1) ? slot * V + v : 0xFFFFFFFFu;
         const uint32_t n_here = (uint32_t)min<uint64_t>(64, n - e0);
+        t_rows += n_here * (lane == 0);
         uint32_t my_pc = 0;
         // word phase
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
@@ -385,7 +389,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_wo
                         // a row is on the list once, and nothing else writes its Vis word in this
                         // kernel: a plain read-modify-write (an atomic OR cost 0.82 vs 0.69 ms a launch)
                         a.vis[(uint64_t)r[u] * K + k] |= nk[u];
-                        if (an[u] != 0xFFFFFFFFu) or_relaxed(&a.ans[(uint64_t)an[u] * K + k], nk[u]);
+                        ++t_words;
+                        if (an[u] != 0xFFFFFFFFu) {
+                            or_relaxed(&a.ans[(uint64_t)an[u] * K + k], nk[u]);
+                            ++t_ans;
+                        }
                         pc = (uint32_t)__popcll(nk[u]);
                     }
                 }
@@ -443,7 +451,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_wo
         }
     }
     eprod = rpqd::wave_sum_u64(eprod);
+    t_words = rpqd::wave_sum_u64(t_words);
+    t_ans = rpqd::wave_sum_u64(t_ans);
     if (lane == 0 && eprod) atomicAdd(&a.counters[C_EPROD], (unsigned long long)eprod);
+    if (lane == 0 && t_rows) {
+        atomicAdd(&a.counters[C_FROWS], (unsigned long long)t_rows);
+        atomicAdd(&a.counters[C_FWORDS], (unsigned long long)t_words);
+        atomicAdd(&a.counters[C_FANS], (unsigned long long)t_ans);
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -876,7 +891,7 @@ struct Profiler {
     bool on = false;
     rpq_profile acc{};
     std::vector<hipEvent_t> pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pend_expand, pend_finalize;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pend_expand, pend_finalize, pend_extract;
 
     hipEvent_t get() {
         if (!pool.empty()) {
@@ -888,8 +903,21 @@ struct Profiler {
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         return e;
     }
-    // caller holds mu and has synchronised the stream the events were recorded on
-    void resolve() {
+    // caller holds mu and has synchronised the stream(s) the events were recorded on; extraction
+    // events (second stream) only when with_extract
+    void resolve(bool with_extract = false) {
+        if (with_extract) {
+            for (auto& pr : pend_extract) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+                    acc.extract_ms += ms;
+                    acc.extract_launches++;
+                }
+                pool.push_back(pr.first);
+                pool.push_back(pr.second);
+            }
+            pend_extract.clear();
+        }
         for (int which = 0; which < 2; ++which) {
             auto& v = which ? pend_finalize : pend_expand;
             for (auto& pr : v) {
@@ -1463,8 +1491,24 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
         // this group's count pass overwrites those arrays
         if (ps) RPQ_TRY(st.pump(true));
         RPQ_TRY(rpq::fill_u64(reinterpret_cast<uint64_t*>(acc), (uint64_t)G_eff * x.W * 2, 0, xs));
+        // profiling: the count pass timed on its own stream; it reads every answer word of the group
+        hipEvent_t xe0 = nullptr, xe1 = nullptr;
+        if (!noalloc && profiler().on) {
+            Profiler& pr = profiler();
+            std::lock_guard<std::mutex> lk(pr.mu);
+            xe0 = pr.get();
+            xe1 = pr.get();
+            pr.acc.extract_words += (uint64_t)G_eff * x.V * x.K;
+        }
+        if (xe0) RPQ_HIP(hipEventRecord(xe0, xs));
         RPQ_DISPATCH_K(x.K, RPQ_TRY(launch_extract<KK>(a, false, sources, n_sources, gbase, G_eff, x.W, x.nchunks,
                                                        x.chunk_v, acc, partial, nullptr, nullptr, 0, 0, xs)));
+        if (xe0 && xe1) {
+            RPQ_HIP(hipEventRecord(xe1, xs));
+            Profiler& pr = profiler();
+            std::lock_guard<std::mutex> lk(pr.mu);
+            pr.pend_extract.emplace_back(xe0, xe1);
+        }
         hipLaunchKernelGGL(k_group_finish, dim3(1), dim3(1024), 0, xs, a.counters, acc, partial, srcbase,
                            (flags & RPQ_PER_SOURCE) ? res->per_source : nullptr, n_sources, gbase,
                            (uint64_t)G_eff * x.W, x.nchunks);
@@ -1494,7 +1538,11 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
         Profiler& pr = profiler();
         std::lock_guard<std::mutex> lk(pr.mu);
         if (pr.on) {
-            pr.resolve();
+            pr.resolve(true);   // both streams are drained here
+            pr.acc.finalize_rows += stage[C_FROWS];
+            pr.acc.finalize_row_words += stage[C_FROWS] * x.K;
+            pr.acc.finalize_words += stage[C_FWORDS];
+            pr.acc.finalize_ans_words += stage[C_FANS];
             pr.acc.edge_items += stage[C_ITEMS];
             pr.acc.descriptors += stage[C_DESCS];
             pr.acc.row_words += stage[C_ROWW];

@@ -53,3 +53,19 @@ def test_expand_roofline_counts_one_visited_word_read_per_item_word():
     assert impl - method == 8 * 275_400_000
     assert abs(avg_ms - 1.4714) < 1e-12
     assert abs(method / (avg_ms / 1e3) / 8e12 - 0.2626) < 5e-4
+
+
+def test_finalize_and_extract_rooflines_from_their_tallies():
+    # two finalize launches over 1,000 rows of 64 words, 30,000 of them non-zero and 5,000 of those in
+    # final-state rows; one extraction count pass over 1,000,000 answer words
+    prof = dict(finalize_launches=2, finalize_ms=2 * 0.5, finalize_rows=2000, finalize_row_words=128_000,
+                finalize_words=60_000, finalize_ans_words=10_000, extract_launches=1, extract_ms=0.25,
+                extract_words=1_000_000)
+    out = bench.other_rooflines(prof)
+    fin_bytes = (8 * 2000 + 16 * 128_000 + 24 * 60_000 + 16 * 10_000) / 2
+    assert out["finalize"]["alg_bytes_per_launch"] == round(fin_bytes, 1)
+    assert abs(out["finalize"]["achieved"] - round(fin_bytes / 0.5e-3 / 1e9, 2)) < 1e-9
+    assert abs(out["extract"]["achieved"] - 8e6 / 0.25e-3 / 1e9) < 1e-6
+    assert abs(out["extract"]["frac"] - round(8e6 / 0.25e-3 / 1e9 / 8000, 5)) < 1e-9
+    # no launches, no entry
+    assert bench.other_rooflines(dict(prof, finalize_launches=0, extract_launches=0)) == {}
