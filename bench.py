@@ -60,6 +60,8 @@ def parse_args():
     ap.add_argument("--concurrency", type=int, default=0)
     ap.add_argument("--sync-every", type=int, default=0)
     ap.add_argument("--chunk-edges", type=int, default=0)
+    ap.add_argument("--visit", choices=["auto", "two-reads", "seen-or"], default="auto",
+                    help="plain form: how the expansion finds new bits (auto: by graph size)")
     ap.add_argument("--no-autotune", action="store_true", help="batched form: keep the default plan")
     ap.add_argument("--batched-plan", default="",
                     help="batched form: WIDTH:CHUNK, a fixed plan instead of the autotuner's (profiling runs)")
@@ -369,13 +371,13 @@ def expand_roofline(prof):
       unit's sources): 4 B neighbour id per item, 16 B per work segment (the row offsets), 8 B per
       frontier word read, one 8 B read of the target's visited word per item-word, and 8 B per OR
       into the next frontier.
-    impl: what this kernel loads on purpose -- the same, with the next-frontier word read beside
-      the visited word (16 B per item-word instead of 8), a choice that skips ORs already done and
-      brings the OR's line into L2."""
+    impl: what this kernel moves on purpose -- the same plus 8 B per access beyond the method's: the
+      next-frontier word read beside each visited word (two-read scheme), or the second OR of each
+      new word, into the visited bitmap (seen-OR scheme)."""
     launches = max(1, prof["expand_launches"])
-    base = 4 * prof["edge_items"] + 16 * prof["descriptors"] + 8 * prof["row_words"] + 8 * prof["word_updates"]
-    method = (base + 8 * prof["word_reads"]) / launches
-    impl = (base + 16 * prof["word_reads"]) / launches
+    method = (4 * prof["edge_items"] + 16 * prof["descriptors"] + 8 * prof["row_words"] + 8 * prof["word_reads"]
+              + 8 * prof["word_updates"]) / launches
+    impl = method + 8 * prof["expand_extra_words"] / launches
     avg_ms = prof["expand_ms"] / launches
     return method, impl, avg_ms
 
@@ -385,24 +387,25 @@ def other_rooflines(prof):
 
     finalize (timed with the compaction that feeds it, one pair per level): 8 B per row id (written by
       compaction, read by finalize); per row word 16 B (Next read, frontier write); per non-zero word
-      8 B more to clear it and 16 B to read and write the visited word; per such word of a final-state
-      row 16 B for the answer word.  The touch bitmap compaction scans (one bit per row) is left out;
+      8 B more to clear it, and 16 B to read and write the visited word where finalize does that
+      (two-read scheme; with seen OR the expansion has set the bits); per non-zero word of a
+      final-state row 16 B for the answer word.  The touch bitmap compaction scans (one bit per row) is left out;
       the tallies include the seeding finalize of each group (one row per source), which is not timed.
     extract (count passes, timed on the extraction stream): 8 B per answer word read."""
     out = {}
     fl = prof["finalize_launches"]
-    if fl and prof["finalize_ms"] > 0:
-        b = (8 * prof["finalize_rows"] + 16 * prof["finalize_row_words"] + 24 * prof["finalize_words"]
-             + 16 * prof["finalize_ans_words"]) / fl
+    if fl and prof["finalize_ms"] / fl > 1e-6:
+        b = (8 * prof["finalize_rows"] + 16 * prof["finalize_row_words"] + 8 * prof["finalize_words"]
+             + 16 * prof["finalize_vis_words"] + 16 * prof["finalize_ans_words"]) / fl
         ms = prof["finalize_ms"] / fl
         a = b / (ms / 1e3) / 1e9
         out["finalize"] = dict(bound="hbm", achieved=round(a, 2), peak=HBM_PEAK_GBPS, unit="GB/s",
                                frac=round(a / HBM_PEAK_GBPS, 5), avg_launch_ms=round(ms, 5), launches=fl,
                                alg_bytes_per_launch=round(b, 1), kernel="k_compact + k_finalize",
-                               counters={k: prof[k] for k in ("finalize_rows", "finalize_row_words",
-                                                              "finalize_words", "finalize_ans_words")})
+                               counters={k: prof[k] for k in ("finalize_rows", "finalize_row_words", "finalize_words",
+                                                              "finalize_vis_words", "finalize_ans_words")})
     xl = prof["extract_launches"]
-    if xl and prof["extract_ms"] > 0:
+    if xl and prof["extract_ms"] / xl > 1e-6:
         b = 8 * prof["extract_words"] / xl
         ms = prof["extract_ms"] / xl
         a = b / (ms / 1e3) / 1e9
@@ -576,7 +579,8 @@ def main():
     # ------------------------------------------------------------------ plain form
     if args.only in ("", "plain"):
         opts = dict(batch_width=args.batch_width, concurrency=args.concurrency, sync_every=args.sync_every,
-                    chunk_edges=args.chunk_edges)
+                    chunk_edges=args.chunk_edges,
+                    visit={"auto": 0, "two-reads": rpq.RPQ_VISIT_TWO_READS, "seen-or": rpq.RPQ_VISIT_SEEN_OR}[args.visit])
         per_source = torch.zeros((n_src, 2), dtype=torch.int64, device="cuda")
         qtimes = {q: 0.0 for q in queries}
 
@@ -639,7 +643,10 @@ def main():
                           frac_impl=round(achieved_impl / HBM_PEAK_GBPS, 5),
                           finalize_avg_ms=round(prof["finalize_ms"] / max(1, prof["finalize_launches"]), 5),
                           counters={k: prof[k] for k in ("expand_launches", "edge_items", "descriptors", "row_words",
-                                                         "word_reads", "word_updates", "expand_ms", "finalize_ms")}))
+                                                         "word_reads", "word_updates", "expand_extra_words",
+                                                         "expand_ms", "finalize_ms")},
+                          visit=(args.visit if args.visit != "auto"
+                                 else "seen-or" if el.n_vertices >= (1 << 22) else "two-reads")))
 
     # ------------------------------------------------------------------ batched form
     g.release_workspace()

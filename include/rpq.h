@@ -216,8 +216,17 @@ typedef struct {
                                 while the slice buffers would exceed a quarter of a unit's bitmaps) */
     uint32_t max_length;     /* with RPQ_LENGTH_BOUND: the longest walk (in edges) that counts;
                                 0 keeps only zero-length walks */
-    uint32_t reserved;       /* must be 0 */
+    uint32_t visit;          /* how the expansion finds a target word's new bits (Section 4, the
+                                visited check before the update); same results either way.
+                                RPQ_VISIT_TWO_READS: read the visited and the Next word, OR the
+                                rest into Next; finalize adds each level's Next to the visited
+                                bitmap.  RPQ_VISIT_SEEN_OR: read only the visited word, OR the rest
+                                into it and into Next.  0 = seen OR on graphs of 2^22 vertices or
+                                more (where the reads come from HBM), two reads below. */
 } rpq_eval_opts;
+
+#define RPQ_VISIT_TWO_READS 1u
+#define RPQ_VISIT_SEEN_OR   2u
 
 /*
  * Result of rpq_eval (host struct).
@@ -675,11 +684,16 @@ typedef struct {
     uint64_t word_updates;
     uint64_t finalize_rows;      /* rows moved from Next to the frontier by finalize */
     uint64_t finalize_row_words; /* their 8-byte words (each read from Next, written to the frontier) */
-    uint64_t finalize_words;     /* their non-zero 8-byte Next words (each ORed into Vis, then cleared) */
+    uint64_t finalize_words;     /* their non-zero 8-byte Next words (each cleared) */
+    uint64_t finalize_vis_words; /* of those, the ones finalize ORed into Vis (all with two reads,
+                                    none with seen OR, where the expansion set them) */
     uint64_t finalize_ans_words; /* those of final-state rows (each also ORed into Ans) */
     uint64_t extract_launches;   /* extraction count passes, timed on the extraction stream */
     double extract_ms;
     uint64_t extract_words;      /* 8-byte answer words those passes read */
+    uint64_t expand_extra_words; /* 8-byte accesses of the expansion beyond the method's: the Next
+                                    word read beside each visited word (two reads), or the second
+                                    OR of each new word (seen OR) */
 } rpq_profile;
 
 /* Turn event timing of the level kernels on (1) or off (0).  Process-wide. */

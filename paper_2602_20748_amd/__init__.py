@@ -26,7 +26,7 @@ __all__ = [
     "Nfa", "EvalOpts", "RPQ_NOALLOC_SCRATCH_BYTES",
     "RPQ_OK", "RPQ_EINVAL", "RPQ_ENOMEM", "RPQ_EOVERFLOW", "RPQ_EDEVICE", "RPQ_EUNSUPPORTED", "RPQ_ECANCELED",
     "RPQ_BUILD_IN_CSR", "RPQ_PAIRS", "RPQ_PER_SOURCE", "RPQ_ALL_SOURCES", "RPQ_REVERSE", "RPQ_SPARSE",
-    "RPQ_LENGTH_BOUND", "rpq_batch_bound_length",
+    "RPQ_LENGTH_BOUND", "rpq_batch_bound_length", "RPQ_VISIT_TWO_READS", "RPQ_VISIT_SEEN_OR",
     "RPQ_MAX_STATES", "RPQ_MAX_LABELS", "EXPORTED_SYMBOLS", "rpq_profile_enable", "rpq_profile_read",
     "Batch", "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size",
     "rpq_batch_run", "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune",
@@ -44,6 +44,7 @@ RPQ_BUILD_IN_CSR = 1
 RPQ_PAIRS, RPQ_PER_SOURCE, RPQ_ALL_SOURCES, RPQ_REVERSE, RPQ_SPARSE, RPQ_LENGTH_BOUND = 1, 2, 4, 8, 16, 32
 RPQ_MAX_STATES, RPQ_MAX_LABELS = 32, 64
 RPQ_NOALLOC_SCRATCH_BYTES = 256 << 20
+RPQ_VISIT_TWO_READS, RPQ_VISIT_SEEN_OR = 1, 2
 
 _STATUS = {0: "RPQ_OK", -1: "RPQ_EINVAL", -2: "RPQ_ENOMEM", -3: "RPQ_EOVERFLOW", -4: "RPQ_EDEVICE",
            -5: "RPQ_EUNSUPPORTED", -6: "RPQ_ECANCELED"}
@@ -75,7 +76,7 @@ class GraphInfo(ctypes.Structure):
 class EvalOpts(ctypes.Structure):
     _fields_ = [("batch_width", ctypes.c_uint32), ("concurrency", ctypes.c_uint32),
                 ("sync_every", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32),
-                ("max_length", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("max_length", ctypes.c_uint32), ("visit", ctypes.c_uint32)]
 
 
 class Profile(ctypes.Structure):
@@ -84,9 +85,10 @@ class Profile(ctypes.Structure):
                 ("edge_items", ctypes.c_uint64), ("descriptors", ctypes.c_uint64), ("row_words", ctypes.c_uint64),
                 ("word_reads", ctypes.c_uint64), ("word_updates", ctypes.c_uint64),
                 ("finalize_rows", ctypes.c_uint64), ("finalize_row_words", ctypes.c_uint64),
-                ("finalize_words", ctypes.c_uint64),
+                ("finalize_words", ctypes.c_uint64), ("finalize_vis_words", ctypes.c_uint64),
                 ("finalize_ans_words", ctypes.c_uint64), ("extract_launches", ctypes.c_uint64),
-                ("extract_ms", ctypes.c_double), ("extract_words", ctypes.c_uint64)]
+                ("extract_ms", ctypes.c_double), ("extract_words", ctypes.c_uint64),
+                ("expand_extra_words", ctypes.c_uint64)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -423,7 +425,10 @@ def _opts(opts) -> Optional[EvalOpts]:
     if isinstance(opts, EvalOpts):
         return opts
     o = EvalOpts()
+    names = {f[0] for f in EvalOpts._fields_}
     for k, v in dict(opts).items():
+        if k not in names:
+            raise ValueError("unknown rpq_eval_opts field %r" % k)
         setattr(o, k, int(v))
     return o
 

@@ -86,7 +86,7 @@ struct Args {
     const uint32_t* dst;
     const uint64_t* lmask;
     const DevNfa* nfa;
-    uint64_t* vis;
+    uint64_t* vis;          // visited bits (with seen_or: also those found at the current level)
     uint64_t* next;
     uint64_t* touch;        // one bit per (slot, q, v) row: row has bits in Next
     uint64_t* ans;
@@ -99,6 +99,7 @@ struct Args {
     unsigned long long* counters;
     const uint64_t* target;   // optional [V / 64] bitmap: only result vertices with their bit set count
     uint32_t V, L, Q, H;
+    uint32_t seen_or;         // visit scheme: 0 = two reads, 1 = seen OR (see the expansion)
     uint64_t list_cap, desc_cap;
 };
 
@@ -132,10 +133,30 @@ __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint6
 //               visited row and the Next row of an item are each read or updated as one
 //               contiguous K-word access instead of K scattered ones.
 // kUnroll items per group are loaded before any of them is updated (memory-level parallelism).
+//
+// New bits of a target word (Section 4, the visited check before the atomic update) are found in
+// one of two ways, both giving the same Next:
+//   two reads  the visited word and the Next word are read; bits in neither are ORed into Next,
+//              and finalize ORs each level's Next into the visited bitmap;
+//   seen OR    only the visited word is read; bits not in it are ORed into both it and Next.  The
+//              visited bitmap then also holds the bits found so far at this level (so it filters
+//              as well as the two reads together), and finalize leaves it alone.  One read and two
+//              ORs per new word instead of two reads and one OR: better where the reads come from
+//              HBM (R-MAT scale 23: 3.41 -> 3.17 s a step), worse where they hit in cache and the
+//              atomics bound the kernel (scale 18: 606 -> 634 ms).
 // ------------------------------------------------------------------------------------------------
 constexpr int kUnroll = 8;
 
-template <int K>
+// An empty asm that takes each value as an operand.  Without it the compiler moves the arithmetic
+// that consumes a conditionally loaded value into the load's own conditional block, where it must
+// wait for that load: the kUnroll loads would then complete one at a time instead of together.
+template <int N>
+__device__ __forceinline__ void keep_in_flight(uint64_t (&x)[N]) {
+#pragma unroll
+    for (int u = 0; u < N; ++u) asm volatile("" : "+v"(x[u]));
+}
+
+template <int K, bool SEEN>
 __device__ __forceinline__ void expand_segments(const Args& a, const uint32_t* s_delta, const uint64_t* rows,
                                                 bool have, uint32_t ent, uint32_t slot, uint32_t q, uint32_t v,
                                                 uint64_t m, uint64_t beg, uint32_t len, uint64_t& t_items,
@@ -177,7 +198,7 @@ __device__ __forceinline__ void expand_segments(const Args& a, const uint32_t* s
         // word phase
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
             uint32_t r[kUnroll];
-            uint64_t f[kUnroll], vw[kUnroll], nx[kUnroll];
+            uint64_t f[kUnroll], nb[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t idx = j + u * GS + grp;
@@ -185,28 +206,49 @@ __device__ __forceinline__ void expand_segments(const Args& a, const uint32_t* s
                 const uint32_t e = __shfl(c_ent, idx & 63, 64);
                 f[u] = idx < n_here ? rows[(uint64_t)e * K + k] : 0;
             }
+            if constexpr (SEEN) {
+                // the visited word holds every bit of earlier levels (their ORs completed before
+                // this launch): bits not in it as read are new at this level
+                uint64_t sw[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < kUnroll; ++u) sw[u] = f[u] ? a.vis[(uint64_t)r[u] * K + k] : ~0ull;
+                keep_in_flight<kUnroll>(sw);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    nb[u] = f[u] & ~sw[u];
+                    if (nb[u]) {
+                        or_relaxed(&a.vis[(uint64_t)r[u] * K + k], nb[u]);
+                        or_relaxed(&a.next[(uint64_t)r[u] * K + k], nb[u]);
+                    }
+                }
+            } else {
                 // the visited word and the Next word together: bits already in Next need no OR, and
                 // the OR then finds its line in L2 (Next only gains bits during an expansion, so a
                 // stale copy can only let through an OR that is not needed)
-                vw[u] = f[u] ? a.vis[(uint64_t)r[u] * K + k] : ~0ull;
-                nx[u] = f[u] ? a.next[(uint64_t)r[u] * K + k] : ~0ull;
+                uint64_t vw[kUnroll], nx[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    vw[u] = f[u] ? a.vis[(uint64_t)r[u] * K + k] : ~0ull;
+                    nx[u] = f[u] ? a.next[(uint64_t)r[u] * K + k] : ~0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    nb[u] = f[u] & ~vw[u] & ~nx[u];
+                    if (nb[u]) or_relaxed(&a.next[(uint64_t)r[u] * K + k], nb[u]);
+                }
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t nb = f[u] & ~vw[u] & ~nx[u];
                 t_wread += f[u] != 0;
-                t_wupd += nb != 0;
-                if (nb) or_relaxed(&a.next[(uint64_t)r[u] * K + k], nb);
-                const uint64_t hit = __ballot(nb != 0) & gmask;
+                t_wupd += nb[u] != 0;
+                const uint64_t hit = __ballot(nb[u] != 0) & gmask;
                 if (k == 0 && hit) or_relaxed(&a.touch[r[u] >> 6], 1ull << (r[u] & 63));
             }
         }
     }
 }
 
-template <int K>
+template <int K, bool SEEN>
 __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
     __shared__ uint32_t s_delta[RPQ_MAX_STATES * RPQ_MAX_LABELS];
     __shared__ uint64_t s_qlab[RPQ_MAX_STATES];
@@ -240,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
             len = have ? (uint32_t)work : 0;
         }
         t_segs += __popcll(__ballot(have)) * (lane == 0);
-        expand_segments<K>(a, s_delta, rows, have, (uint32_t)e, slot, q, v, m, 0, len, t_items, t_wread, t_wupd);
+        expand_segments<K, SEEN>(a, s_delta, rows, have, (uint32_t)e, slot, q, v, m, 0, len, t_items, t_wread, t_wupd);
     }
     // heavy entries, as slices
     const Desc* desc = desc_of(a, p);
@@ -264,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(Args a, int p) {
             have = true;
         }
         t_segs += __popcll(__ballot(have)) * (lane == 0);
-        expand_segments<K>(a, s_delta, rows, have, ent, slot, q, v, m, beg, len, t_items, t_wread, t_wupd);
+        expand_segments<K, SEEN>(a, s_delta, rows, have, ent, slot, q, v, m, beg, len, t_items, t_wread, t_wupd);
     }
     t_items = rpqd::wave_sum_u64(t_items);
     t_segs = rpqd::wave_sum_u64(t_segs);
@@ -387,8 +429,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_wo
                     if (nk[u]) {
                         a.next[(uint64_t)r[u] * K + k] = 0;
                         // a row is on the list once, and nothing else writes its Vis word in this
-                        // kernel: a plain read-modify-write (an atomic OR cost 0.82 vs 0.69 ms a launch)
-                        a.vis[(uint64_t)r[u] * K + k] |= nk[u];
+                        // kernel: a plain read-modify-write (an atomic OR cost 0.82 vs 0.69 ms a
+                        // launch).  With seen OR the expansion has already set these bits.
+                        if (!a.seen_or) a.vis[(uint64_t)r[u] * K + k] |= nk[u];
                         ++t_words;
                         if (an[u] != 0xFFFFFFFFu) {
                             or_relaxed(&a.ans[(uint64_t)an[u] * K + k], nk[u]);
@@ -481,6 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args a, const uint32_t* __restr
         init &= init - 1;
         const uint64_t row = ((uint64_t)slot * a.Q + q) * a.V + s;
         or_relaxed(&a.next[row * K + k], bit);
+        if (a.seen_or) or_relaxed(&a.vis[row * K + k], bit);
         or_relaxed(&a.touch[row >> 6], 1ull << (row & 63));
     }
 }
@@ -671,6 +715,7 @@ __global__ __launch_bounds__(1024) void k_group_finish(unsigned long long* __res
 // ------------------------------------------------------------------------------------------------
 struct Layout {
     uint32_t K, W, G, Q, L, V, H, nchunks, chunk_v, sync_every;
+    uint32_t seen_or;   // visit scheme of the expansion (1 = seen OR, 0 = two reads)
     uint64_t max_len;   // deepest level finalized: the length bound, or no bound (UINT64_MAX)
     uint64_t list_cap, desc_cap;
     uint64_t off_counters, off_nfa, off_vis, off_next, off_touch, off_ans, off_ans2, off_ids[2], off_rows[2],
@@ -737,6 +782,9 @@ constexpr uint64_t kTargetInFlight = 65536;
 constexpr uint64_t kWorkspaceBudget = 64ull << 30;
 constexpr uint64_t kUnitBudget = 96ull << 30;
 constexpr uint32_t kDefaultChunk = 16;
+// Graphs from this many vertices on take the seen-OR visit scheme by default (the expansion's
+// comment has the measurements at scales 18 and 23).
+constexpr uint32_t kSeenOrFrom = 1u << 22;
 
 uint32_t max_default_width(uint32_t V) { return V >= (1u << 22) ? 4096 : 2048; }
 
@@ -766,6 +814,7 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     }
     x.K = x.W / 64;
     x.H = (o && o->chunk_edges) ? o->chunk_edges : kDefaultChunk;
+    x.seen_or = (o && o->visit) ? o->visit == RPQ_VISIT_SEEN_OR : g->V >= kSeenOrFrom;
     if (x.H > 65535) {
         rpq::set_error("chunk_edges must be <= 65535");
         return RPQ_EINVAL;
@@ -856,6 +905,7 @@ Args make_args(const rpq_graph* g, uint32_t flags, const Layout& x, char* ws) {
     a.L = x.L;
     a.Q = x.Q;
     a.H = x.H;
+    a.seen_or = x.seen_or;
     a.list_cap = x.list_cap;
     a.desc_cap = x.desc_cap;
     return a;
@@ -875,9 +925,10 @@ unsigned resident_grid(const void* kernel) {
 
 template <int K>
 struct LevelGrids {
-    unsigned expand, compact, finalize;
+    unsigned expand, expand_seen, compact, finalize;
     static const LevelGrids& get() {
-        static const LevelGrids g{resident_grid(reinterpret_cast<const void*>(&k_expand<K>)),
+        static const LevelGrids g{resident_grid(reinterpret_cast<const void*>(&k_expand<K, false>)),
+                                  resident_grid(reinterpret_cast<const void*>(&k_expand<K, true>)),
                                   resident_grid(reinterpret_cast<const void*>(&k_compact)),
                                   resident_grid(reinterpret_cast<const void*>(&k_finalize<K>))};
         return g;
@@ -963,7 +1014,10 @@ int launch_level(const Args& a, int p, uint64_t n_rows, uint32_t level, int coun
         e2 = pr.get();
     }
     if (e0) RPQ_HIP(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(k_expand<K>, dim3(LevelGrids<K>::get().expand), dim3(kBlock), 0, s, a, p);
+    if (a.seen_or)
+        hipLaunchKernelGGL((k_expand<K, true>), dim3(LevelGrids<K>::get().expand_seen), dim3(kBlock), 0, s, a, p);
+    else
+        hipLaunchKernelGGL((k_expand<K, false>), dim3(LevelGrids<K>::get().expand), dim3(kBlock), 0, s, a, p);
     RPQ_LAUNCH_CHECK();
     if (e1) RPQ_HIP(hipEventRecord(e1, s));
     hipLaunchKernelGGL(k_compact, dim3(LevelGrids<K>::get().compact), dim3(kBlock), 0, s, a, p, n_rows, level);
@@ -1263,8 +1317,8 @@ int prepare(rpq_graph_t g, const rpq_nfa* nfa_in, uint64_t n_sources, uint32_t f
         rpq::set_error("RPQ_LENGTH_BOUND needs opts->max_length");
         return RPQ_EINVAL;
     }
-    if (opts && opts->reserved) {
-        rpq::set_error("rpq_eval_opts.reserved must be 0");
+    if (opts && opts->visit > RPQ_VISIT_SEEN_OR) {
+        rpq::set_error("rpq_eval_opts.visit must be 0, RPQ_VISIT_TWO_READS or RPQ_VISIT_SEEN_OR");
         return RPQ_EINVAL;
     }
     RPQ_TRY(validate_nfa(g, nfa_in));
@@ -1542,6 +1596,10 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
             pr.acc.finalize_rows += stage[C_FROWS];
             pr.acc.finalize_row_words += stage[C_FROWS] * x.K;
             pr.acc.finalize_words += stage[C_FWORDS];
+            pr.acc.finalize_vis_words += x.seen_or ? 0 : stage[C_FWORDS];
+            // beyond the method's bytes: the Next word read beside each visited word (two reads),
+            // or the second OR of each new word (seen OR)
+            pr.acc.expand_extra_words += x.seen_or ? stage[C_WUPD] : stage[C_WREAD];
             pr.acc.finalize_ans_words += stage[C_FANS];
             pr.acc.edge_items += stage[C_ITEMS];
             pr.acc.descriptors += stage[C_DESCS];

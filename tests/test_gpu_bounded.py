@@ -63,6 +63,7 @@ def test_bounded_random_graphs_every_form(rpq):
                 say("case: bounded trial=%d n=%d m=%d %s k=%d" % (trial, n, m, rx, k))
                 check(rpq, g, og, rx, sources, k)
                 check(rpq, g, og, rx, sources, k, opts=dict(batch_width=64, concurrency=1))
+                check(rpq, g, og, rx, sources, k, opts=dict(batch_width=128, visit=rpq.RPQ_VISIT_SEEN_OR))
                 check(rpq, g, og, rx, sources, k, flags=rpq.RPQ_SPARSE)
         g.close()
 
@@ -147,6 +148,7 @@ def test_bounded_rmat18_sampled_sources(rpq, regex):
     for k in (1, 3, 6):
         say("case: bounded rmat18 %s k=%d" % (regex, k))
         check(rpq, g, og, regex, src, k)
+        check(rpq, g, og, regex, src, k, opts=dict(visit=rpq.RPQ_VISIT_SEEN_OR))
     g.close()
 
 

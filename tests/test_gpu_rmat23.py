@@ -86,6 +86,12 @@ def test_rmat23_bench_sources_against_oracle(rpq, w23, regex):
     assert got.product_edges == want.product_edges, regex
     assert np.array_equal(got.pairs.cpu().numpy().view(np.uint64), want.pairs), regex
     assert np.array_equal(got.per_source.cpu().numpy().view(np.uint64), want.per_source), regex
+    # the default visit scheme at this size is seen OR; the two-read scheme, forced, agrees
+    say("case: rmat23 %s sampled sources, two-read visit scheme" % regex)
+    got2 = rpq.rpq_eval(g, nfa, src[pair_pos], pairs=True, opts=dict(visit=rpq.RPQ_VISIT_TWO_READS))
+    assert got2.count == want.count and got2.hash == want.hash, regex
+    assert got2.product_edges == want.product_edges, regex
+    assert np.array_equal(got2.pairs.cpu().numpy().view(np.uint64), want.pairs), regex
     assert samp.size == N_SAMPLES
 
 

@@ -112,9 +112,10 @@ def test_random_small_graphs_and_queries(rpq):
         og = oracle.OracleGraph(n, src, lab, dst, L, names[:L])
         sources = None if rng.random() < 0.5 else synth.sample_sources(n, int(rng.integers(1, n + 1)), seed=trial)
         width = int(rng.choice([64, 128, 256, 512, 1024, 2048, 4096]))
+        # both visit schemes, alternating by trial
         check_against_oracle(rpq, g, og, regex, sources=sources,
                              opts=dict(batch_width=width, concurrency=int(rng.integers(1, 4)),
-                                       chunk_edges=int(rng.integers(1, 100))))
+                                       chunk_edges=int(rng.integers(1, 100)), visit=1 + trial % 2))
         g.close()
 
 
@@ -151,6 +152,19 @@ def test_rmat18_sampled_sources(rpq, rmat18, regex):
     src = synth.sample_sources(el.n_vertices, 1024, seed=2018)
     say("case: rmat18 sampled 1024 sources q=%s" % regex)
     check_against_oracle(rpq, g, og, regex, sources=src)
+
+
+@pytest.mark.parametrize("regex", ["a*", "a.b*.c", "(a.b)*"])
+@pytest.mark.parametrize("visit", ["two-reads", "seen-or"])
+def test_rmat18_visit_schemes(rpq, rmat18, regex, visit):
+    # each way of finding a target word's new bits, forced (the default at this size is two reads),
+    # over eight 128-wide units advanced two at a time: pairs, per-source tallies and product
+    # edges against the oracle
+    el, g, og = rmat18
+    src = synth.sample_sources(el.n_vertices, 1000, seed=2026)
+    say("case: rmat18 visit=%s q=%s" % (visit, regex))
+    v = rpq.RPQ_VISIT_TWO_READS if visit == "two-reads" else rpq.RPQ_VISIT_SEEN_OR
+    check_against_oracle(rpq, g, og, regex, sources=src, opts=dict(visit=v, batch_width=128, concurrency=2))
 
 
 @pytest.mark.parametrize("regex", ["a*", "a.b*", "(a|b).c*", "a.b*.c", "(a.b)*"])
@@ -259,6 +273,11 @@ def test_invalid_inputs(rpq):
     with pytest.raises(rpq.RpqError) as ei:
         rpq.rpq_eval(g, nfa, np.array([1], np.uint32), opts=dict(batch_width=96))
     assert ei.value.code == rpq.RPQ_EINVAL
+    with pytest.raises(rpq.RpqError) as ei:
+        rpq.rpq_eval(g, nfa, np.array([1], np.uint32), opts=dict(visit=3))
+    assert ei.value.code == rpq.RPQ_EINVAL
+    with pytest.raises(ValueError):
+        rpq.rpq_eval(g, nfa, np.array([1], np.uint32), opts=dict(visits=2))
     big = rpq.rpq_nfa_compile("a", ["a", "b", "c", "d", "e"])
     big.delta[0 * 64 + 4] = 2
     with pytest.raises(rpq.RpqError) as ei:
