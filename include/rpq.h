@@ -371,10 +371,13 @@ typedef struct {
                                the worst case (every row of every slot in one level); rows beyond wait
                                for the next iteration, which changes no result (0 = 4, or 1 when a
                                query is length-bounded: such queries need exact depths and require 1) */
+    uint32_t visit;         /* the expansion's visit scheme, as rpq_eval_opts.visit (0 = seen OR on graphs of
+                               2^22 vertices or more, two reads below) */
 } rpq_batch_opts;
 
 typedef struct {
-    uint32_t n_queries, n_units, slots, batch_width, blocks, reserved;
+    uint32_t n_queries, n_units, slots, batch_width, blocks;
+    uint32_t visit;              /* visit scheme of the plan: RPQ_VISIT_TWO_READS or RPQ_VISIT_SEEN_OR */
     uint64_t workspace_bytes;
     uint64_t iterations;         /* level iterations of the last run */
     uint64_t edge_items, descriptors, word_reads, word_updates;   /* expansion tallies, last run */

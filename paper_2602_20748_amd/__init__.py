@@ -93,12 +93,12 @@ class Profile(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("batch_width", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32),
-                ("list_share", ctypes.c_uint32)]
+                ("list_share", ctypes.c_uint32), ("visit", ctypes.c_uint32)]
 
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_queries", ctypes.c_uint32), ("n_units", ctypes.c_uint32), ("slots", ctypes.c_uint32),
-                ("batch_width", ctypes.c_uint32), ("blocks", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("batch_width", ctypes.c_uint32), ("blocks", ctypes.c_uint32), ("visit", ctypes.c_uint32),
                 ("workspace_bytes", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
                 ("edge_items", ctypes.c_uint64), ("descriptors", ctypes.c_uint64), ("word_reads", ctypes.c_uint64),
                 ("word_updates", ctypes.c_uint64), ("finalized_rows", ctypes.c_uint64),
@@ -419,17 +419,22 @@ class EvalResult:
     status: int = RPQ_OK
 
 
+def _fill(st, fields) -> None:
+    """Set the named integer fields of a ctypes struct; an unknown name is an error."""
+    names = {f[0] for f in type(st)._fields_}
+    for k, v in dict(fields).items():
+        if k not in names:
+            raise ValueError("unknown %s field %r" % (type(st).__name__, k))
+        setattr(st, k, int(v))
+
+
 def _opts(opts) -> Optional[EvalOpts]:
     if opts is None:
         return None
     if isinstance(opts, EvalOpts):
         return opts
     o = EvalOpts()
-    names = {f[0] for f in EvalOpts._fields_}
-    for k, v in dict(opts).items():
-        if k not in names:
-            raise ValueError("unknown rpq_eval_opts field %r" % k)
-        setattr(o, k, int(v))
+    _fill(o, opts)
     return o
 
 
@@ -664,8 +669,7 @@ def rpq_batch_create(g: Graph, opts=None) -> Batch:
     o = None
     if opts:
         o = BatchOpts()
-        for k, v in dict(opts).items():
-            setattr(o, k, int(v))
+        _fill(o, opts)
     h = ctypes.c_void_p()
     _check(load_library().rpq_batch_create(g.handle, ctypes.byref(o) if o is not None else None, ctypes.byref(h)))
     return Batch(h.value, g)
@@ -768,8 +772,7 @@ def rpq_batch_autotune(b: Batch, candidates=None, workspace_bytes: int = 0, stre
         n = len(candidates)
         arr = (BatchOpts * n)()
         for i, c in enumerate(candidates):
-            for k, v in dict(c).items():
-                setattr(arr[i], k, int(v))
+            _fill(arr[i], c)
     best = BatchOpts()
     _check(load_library().rpq_batch_autotune(b.handle, arr, n, b.ws.data_ptr(), b.ws.numel(), _stream(stream),
                                              ctypes.byref(best)))

@@ -38,6 +38,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kUnroll = 4;                 // rows per lane group loaded before any is updated
 constexpr uint32_t kChunkV = 4096;          // vertices per extraction chunk (64 summary words)
+constexpr uint32_t kSeenOrFrom = 1u << 22;   // default visit scheme: seen OR from this many vertices
 
 // S_RETIRE: retiring in this iteration's retire phases (queries with pairs); S_DRAIN: retiring in the
 // next iteration, its extraction beside that iteration's expansion and its clear beside its compaction
@@ -137,6 +138,7 @@ struct BArgs {
     // iterations with its state kept for the next one.  Closed form: unit_mask = ~0, max_iters = 0.
     uint32_t open_form, max_iters;
     uint64_t unit_mask;
+    uint32_t seen_or;        // visit scheme of the expansion (as in the plain form): 1 = seen OR
 };
 
 __device__ __forceinline__ unsigned long long ld(const unsigned long long* p) {
@@ -162,6 +164,15 @@ __device__ __forceinline__ void or_relaxed(uint64_t* p, uint64_t v) {
 __device__ __forceinline__ uint64_t xld(const uint64_t* p) { return *p; }
 __device__ __forceinline__ uint32_t xld(const uint32_t* p) { return *p; }
 
+// An empty asm that takes each value as an operand, so that the arithmetic consuming conditionally
+// loaded values is not moved into the loads' own conditional blocks, where each would wait for its
+// load: the loads then stay in flight together.
+template <int N>
+__device__ __forceinline__ void keep_in_flight(uint64_t (&x)[N]) {
+#pragma unroll
+    for (int u = 0; u < N; ++u) asm volatile("" : "+v"(x[u]));
+}
+
 __device__ __forceinline__ uint64_t gwave(const BArgs& a) {
     return (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
 }
@@ -183,7 +194,7 @@ __device__ __forceinline__ void entry_of(const BArgs& a, uint32_t row, uint32_t*
     *nfa = a.nfas + ld32(&a.slots[*slot].query);
 }
 
-template <int K>
+template <int K, bool SEEN>
 __device__ __forceinline__ void expand_segments(const BArgs& a, const uint64_t* rows, bool have, uint32_t ent,
                                                 uint32_t slot, uint32_t q, uint32_t v, uint64_t m,
                                                 const uint32_t* delta, uint64_t beg, uint32_t len,
@@ -227,7 +238,7 @@ __device__ __forceinline__ void expand_segments(const BArgs& a, const uint64_t* 
         const uint32_t n_here = min(64u, total - base);
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
             uint32_t r[kUnroll];
-            uint64_t f[kUnroll], vw[kUnroll], nx[kUnroll];
+            uint64_t f[kUnroll], nb[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t idx = j + u * GS + grp;
@@ -235,26 +246,47 @@ __device__ __forceinline__ void expand_segments(const BArgs& a, const uint64_t* 
                 const uint32_t e = __shfl(c_ent, idx & 63, 64);
                 f[u] = idx < n_here ? xld(rows + (uint64_t)e * K + k) : 0;
             }
+            if constexpr (SEEN) {
+                // seen OR (as in the plain form): the visited word already holds every bit of the
+                // slot's earlier levels (ORed before the last barrier), so bits not in it are new
+                uint64_t sw[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < kUnroll; ++u) sw[u] = f[u] ? xld(a.vis + (uint64_t)r[u] * K + k) : ~0ull;
+                keep_in_flight<kUnroll>(sw);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    nb[u] = f[u] & ~sw[u];
+                    if (nb[u]) {
+                        or_relaxed(a.vis + (uint64_t)r[u] * K + k, nb[u]);
+                        or_relaxed(a.next + (uint64_t)r[u] * K + k, nb[u]);
+                    }
+                }
+            } else {
                 // visited and Next words together (as in the plain form)
-                vw[u] = f[u] ? xld(a.vis + (uint64_t)r[u] * K + k) : ~0ull;
-                nx[u] = f[u] ? xld(a.next + (uint64_t)r[u] * K + k) : ~0ull;
+                uint64_t vw[kUnroll], nx[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    vw[u] = f[u] ? xld(a.vis + (uint64_t)r[u] * K + k) : ~0ull;
+                    nx[u] = f[u] ? xld(a.next + (uint64_t)r[u] * K + k) : ~0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    nb[u] = f[u] & ~vw[u] & ~nx[u];
+                    if (nb[u]) or_relaxed(a.next + (uint64_t)r[u] * K + k, nb[u]);
+                }
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const uint64_t nb = f[u] & ~vw[u] & ~nx[u];
                 t_wread += f[u] != 0;
-                t_wupd += nb != 0;
-                if (nb) or_relaxed(a.next + (uint64_t)r[u] * K + k, nb);
-                const uint64_t hit = __ballot(nb != 0) & gmask;
+                t_wupd += nb[u] != 0;
+                const uint64_t hit = __ballot(nb[u] != 0) & gmask;
                 if (k == 0 && hit) or_relaxed(&a.touch[r[u] >> 6], 1ull << (r[u] & 63));
             }
         }
     }
 }
 
-template <int K>
+template <int K, bool SEEN>
 __device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t& t_descs, uint64_t& t_wread,
                              uint64_t& t_wupd) {
     const uint64_t n_list = min((uint64_t)ld(&a.ctl->list_cnt[p]), a.list_cap);
@@ -281,7 +313,7 @@ __device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t&
         }
         const uint64_t hb = __ballot(have);   // every lane takes part
         if (lane == 0) t_descs += __popcll(hb);
-        expand_segments<K>(a, rows, have, (uint32_t)e, slot, q, v, m, nfa->delta, 0, len, t_items, t_wread, t_wupd);
+        expand_segments<K, SEEN>(a, rows, have, (uint32_t)e, slot, q, v, m, nfa->delta, 0, len, t_items, t_wread, t_wupd);
     }
     const uint64_t n_db = (n_desc + 63) / 64;
     for (uint64_t b = gwave(a); b < n_db; b += gwaves(a)) {
@@ -301,7 +333,7 @@ __device__ void phase_expand(const BArgs& a, int p, uint64_t& t_items, uint64_t&
         }
         const uint64_t hb = __ballot(have);   // every lane takes part
         if (lane == 0) t_descs += __popcll(hb);
-        expand_segments<K>(a, rows, have, ent, slot, q, v, m, nfa->delta, beg, len, t_items, t_wread, t_wupd);
+        expand_segments<K, SEEN>(a, rows, have, ent, slot, q, v, m, nfa->delta, beg, len, t_items, t_wread, t_wupd);
     }
 }
 
@@ -686,6 +718,7 @@ __device__ void phase_seed(const BArgs& a, int p, uint32_t iter) {
                 init &= init - 1;
                 row = (uint64_t)slot * a.slot_stride + (uint64_t)q * a.V + s;
                 or_relaxed(&a.next[row * K + (j >> 6)], 1ull << (j & 63));
+                if (a.seen_or) or_relaxed(&a.vis[row * K + (j >> 6)], 1ull << (j & 63));
                 or_relaxed(&a.ever[row >> 6], 1ull << (row & 63));
             }
             const uint64_t m = __ballot(take);
@@ -806,8 +839,9 @@ __device__ void phase_finalize(const BArgs& a, int p, uint32_t iter, uint64_t& t
                     rows[(e0 + idx) * K + k] = sp[u] ? 0 : nk[u];
                     if (nk[u]) {
                         a.next[(uint64_t)r[u] * K + k] = 0;
-                        // the row is on the list once and nothing else writes its Vis word in this phase
-                        a.vis[(uint64_t)r[u] * K + k] |= nk[u];
+                        // the row is on the list once and nothing else writes its Vis word in this
+                        // phase (with seen OR the expansion has set these bits)
+                        if (!a.seen_or) a.vis[(uint64_t)r[u] * K + k] |= nk[u];
                         pc = (uint32_t)__popcll(nk[u]);
                         ++t_fwords;
                         if (an[u] != 0xFFFFFFFFu) or_relaxed(a.ans + (uint64_t)an[u] * K + k, nk[u]);
@@ -881,7 +915,7 @@ __device__ void phase_finalize(const BArgs& a, int p, uint32_t iter, uint64_t& t
         }                                                                            \
     } while (0)
 
-template <int K>
+template <int K, bool SEEN>
 __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
     uint64_t t_items = 0, t_descs = 0, t_wread = 0, t_wupd = 0, t_frows = 0, t_fwords = 0;
     // iterations continue the numbering of earlier launches on the same state (open form); every
@@ -902,7 +936,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_batch(BArgs a) {
         // has no frontier, so its rows are not the ones these phases touch)
         const uint32_t* drain = a.drain + (uint64_t)((iter - 1) & 1) * a.G;
         const uint32_t n_dr = (uint32_t)ld(&a.ctl->n_drain[(iter - 1) & 1]);
-        phase_expand<K>(a, p, t_items, t_descs, t_wread, t_wupd);
+        phase_expand<K, SEEN>(a, p, t_items, t_descs, t_wread, t_wupd);
         if (n_dr) phase_retire_extract<K, false>(a, drain, n_dr);
         BAR(0);
         phase_compact(a, p, iter);
@@ -1005,6 +1039,7 @@ struct HostQuery {
 
 struct Layout {
     uint32_t K, W, G, Qmax, H, nchunks, n_units;
+    uint32_t seen_or;   // visit scheme of the expansion (1 = seen OR, 0 = two reads)
     uint64_t slot_stride, summ_words, list_cap, desc_cap, log_cap, stage_keys;
     uint64_t off_ctl, off_nfas, off_queries, off_qout, off_units, off_slots, off_vis, off_next, off_touch, off_ever,
         off_ans,
@@ -1138,6 +1173,11 @@ int plan(rpq_batch* b) {
         rpq::set_error("chunk_edges must be <= 65535");
         return RPQ_EINVAL;
     }
+    if (b->opts.visit > RPQ_VISIT_SEEN_OR) {
+        rpq::set_error("visit must be 0, RPQ_VISIT_TWO_READS or RPQ_VISIT_SEEN_OR");
+        return RPQ_EINVAL;
+    }
+    x.seen_or = b->opts.visit ? b->opts.visit == RPQ_VISIT_SEEN_OR : g->V >= kSeenOrFrom;
     x.Qmax = 1;
     for (auto& q : b->queries) x.Qmax = std::max(x.Qmax, q.nfa.n_states);
     // units
@@ -1195,6 +1235,7 @@ BArgs args_for(const rpq_graph* g, const Layout& x, char* ws, unsigned n_blocks,
                uint32_t n_queries) {
     BArgs a;
     std::memset(&a, 0, sizeof a);
+    a.seen_or = x.seen_or;
     a.row_ptr = g->out.row_ptr;
     a.dst = g->out.dst;
     a.lmask = g->out.lmask;
@@ -1253,7 +1294,7 @@ BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
                     (uint32_t)b->queries.size());
 }
 
-#define RPQ_BDISPATCH(K, CALL)                                   \
+#define RPQ_BDISPATCH_K(K, CALL)                                 \
     switch (K) {                                                 \
         case 1: { constexpr int KK = 1; CALL; } break;           \
         case 2: { constexpr int KK = 2; CALL; } break;           \
@@ -1264,13 +1305,30 @@ BArgs make_bargs(const rpq_batch* b, char* ws, unsigned n_blocks) {
         case 64: { constexpr int KK = 64; CALL; } break;         \
         default: rpq::set_error("bad width"); return RPQ_EINVAL; \
     }
+// width K and visit scheme SS (seen OR) of the persistent kernel's instantiation
+#define RPQ_BDISPATCH(K, SEEN_OR, CALL)                                                       \
+    do {                                                                                      \
+        if (SEEN_OR) {                                                                        \
+            constexpr bool SS = true;                                                         \
+            RPQ_BDISPATCH_K(K, CALL);                                                         \
+        } else {                                                                              \
+            constexpr bool SS = false;                                                        \
+            RPQ_BDISPATCH_K(K, CALL);                                                         \
+        }                                                                                     \
+    } while (0)
 
-template <int K>
+template <int K, bool SEEN>
+int launch_batch_kernel(unsigned n_blocks, const BArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_batch<K, SEEN>), dim3(n_blocks), dim3(kBlock), 0, s, a);
+    return RPQ_OK;
+}
+
+template <int K, bool SEEN>
 int co_resident_blocks(unsigned* out, int max_per_cu = 4) {
     int per_cu = 0, dev = 0, n_cu = 0;
     RPQ_HIP(hipGetDevice(&dev));
     RPQ_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    RPQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch<K>), kBlock, 0));
+    RPQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch<K, SEEN>), kBlock, 0));
     if (per_cu <= 0) {
         rpq::set_error("persistent kernel does not fit on a compute unit");
         return RPQ_EUNSUPPORTED;
@@ -1282,7 +1340,7 @@ int co_resident_blocks(unsigned* out, int max_per_cu = 4) {
     return RPQ_OK;
 }
 
-template <int K>
+template <int K, bool SEEN>
 int enqueue_run(rpq_batch* b, char* ws, hipStream_t s) {
     const Layout& x = b->lay;
     const unsigned nb = b->n_blocks;   // co-resident grid, sized before capture began
@@ -1301,7 +1359,7 @@ int enqueue_run(rpq_batch* b, char* ws, hipStream_t s) {
     RPQ_TRY(rpq::fill_u64(a.unit_total, std::max<uint32_t>(1, x.n_units), 0, s));
     for (auto& q : b->queries)
         if (q.per_source) RPQ_TRY(rpq::fill_u64(q.per_source, q.n_sources * 2, 0, s));
-    hipLaunchKernelGGL(k_batch<K>, dim3(nb), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_batch<K, SEEN>), dim3(nb), dim3(kBlock), 0, s, a);
     RPQ_LAUNCH_CHECK();
     bool any_pairs = false;
     for (auto& q : b->queries) any_pairs |= q.pairs != nullptr;
@@ -1530,10 +1588,10 @@ int rpq_batch_run(rpq_batch_t b, void* workspace, uint64_t workspace_bytes, hipS
     }
     if (!b->cap_stream) RPQ_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     if (!b->exec) {
-        RPQ_BDISPATCH(x.K, RPQ_TRY(co_resident_blocks<KK>(&b->n_blocks)));
+        RPQ_BDISPATCH(x.K, x.seen_or, RPQ_TRY((co_resident_blocks<KK, SS>(&b->n_blocks))));
         RPQ_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         int rc = RPQ_OK;
-        RPQ_BDISPATCH(x.K, rc = enqueue_run<KK>(b, ws, b->cap_stream));
+        RPQ_BDISPATCH(x.K, x.seen_or, (rc = enqueue_run<KK, SS>(b, ws, b->cap_stream)));
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(b->cap_stream, &graph);
         if (rc != RPQ_OK) {
@@ -1614,6 +1672,7 @@ int rpq_batch_stats(rpq_batch_t b, rpq_batch_info* out) {
     out->slots = b->lay.G;
     out->batch_width = b->lay.W;
     out->blocks = b->n_blocks;
+    out->visit = b->lay.seen_or ? RPQ_VISIT_SEEN_OR : RPQ_VISIT_TWO_READS;
     out->workspace_bytes = b->lay.total;
     out->last_run_ms = b->last_ms;
     out->last_kernel_ms = b->last_kernel_ms;
@@ -1663,6 +1722,7 @@ int rpq_batch_autotune(rpq_batch_t b, const rpq_batch_opts* candidates, uint32_t
     rpq_batch_opts best_opts = saved;
     for (const rpq_batch_opts& c : cands) {
         b->opts = c;
+        if (!b->opts.visit) b->opts.visit = saved.visit;   // the scheme is the batch's, not tuned
         b->frozen = false;
         if (plan(b) != RPQ_OK || b->lay.total > workspace_bytes) continue;
         // time a bounded prefix of the unit queue: enough units for a few refills of every slot
@@ -1807,6 +1867,7 @@ int res_layout(const rpq_graph* g, uint32_t W, uint32_t G, uint32_t Qmax, uint32
     x.K = W / 64;
     x.H = 16;
     x.Qmax = Qmax;
+    x.seen_or = g->V >= kSeenOrFrom;
     x.G = G;
     uint64_t desc_per_slot = 0, per_slot = 0;
     size_slots(g, max_succ, true, kResShare, &x, &desc_per_slot, &per_slot);
@@ -1886,7 +1947,7 @@ int resident_create(rpq_graph* g, uint32_t W, uint32_t G, uint32_t Qmax, uint32_
     r->table.resize(kResQueries);
     for (uint32_t q = kResQueries; q-- > 0;) r->free_q.push_back(q);
     // half the co-resident occupancy: requests outside the engine keep room on every compute unit
-    RPQ_BDISPATCH(x.K, RPQ_TRY(co_resident_blocks<KK>(&r->n_blocks, 2)));
+    RPQ_BDISPATCH(x.K, x.seen_or, RPQ_TRY((co_resident_blocks<KK, SS>(&r->n_blocks, 2))));
     RPQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&r->h_recs), sizeof(ResRecord) * kResMaxStaged));
     RPQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&r->h_units), sizeof(BUnit) * kResMaxStagedUnits));
     RPQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&r->h_out), sizeof(BQueryOut) * kResQueries));
@@ -2046,7 +2107,7 @@ int step_body(Resident* r, uint32_t max_iters, hipStream_t stream, std::vector<R
                        stream, a, r->d_recs, n_rec, (unsigned long long)r->units_tail);
     RPQ_LAUNCH_CHECK();
     // 4. one bounded launch, then the control block and the query outputs
-    RPQ_BDISPATCH(x.K, hipLaunchKernelGGL(k_batch<KK>, dim3(r->n_blocks), dim3(kBlock), 0, stream, a));
+    RPQ_BDISPATCH(x.K, x.seen_or, RPQ_TRY((launch_batch_kernel<KK, SS>(r->n_blocks, a, stream))));
     RPQ_LAUNCH_CHECK();
     RPQ_HIP(hipMemcpyAsync(r->h_ctl, r->ws + x.off_ctl, sizeof(BCtl), hipMemcpyDeviceToHost, stream));
     RPQ_HIP(hipMemcpyAsync(r->h_out, r->ws + x.off_qout, sizeof(BQueryOut) * r->q_hi, hipMemcpyDeviceToHost, stream));

@@ -66,6 +66,8 @@ def check_batch(rpq, g, el, mix, opts, og=None, runs=2):
         b.run()
         st = b.stats()
         assert st["n_queries"] == len(mix)
+        if opts and opts.get("visit"):
+            assert st["visit"] == opts["visit"]
         for qi, (rx, src, want_pairs, per_source), ref in zip(qids, mix, expect):
             got = b.result(qi)
             assert (got.count, got.hash, got.product_edges) == (ref.count, ref.hash, ref.product_edges), rx
@@ -89,7 +91,9 @@ def test_batch_uniform_mix_matches_plain(rpq):
     rng = np.random.default_rng(5)
     mix = build_mix(rng, el.names, el.n_vertices, 24)
     for opts in (dict(batch_width=64, slots=3), dict(batch_width=128, slots=7, chunk_edges=5),
-                 dict(batch_width=512, slots=2), dict(batch_width=64, slots=40)):
+                 dict(batch_width=512, slots=2), dict(batch_width=64, slots=40),
+                 dict(batch_width=128, slots=5, visit=rpq.RPQ_VISIT_SEEN_OR),
+                 dict(batch_width=64, slots=40, chunk_edges=3, visit=rpq.RPQ_VISIT_SEEN_OR)):
         check_batch(rpq, g, el, mix, opts, og=og, runs=3)
     g.close()
 
@@ -107,7 +111,8 @@ def test_batch_against_oracle_random_graphs(rpq):
         g = rpq.rpq_graph_create(src, lab, dst, n, L, names=names[:L])
         og = oracle.OracleGraph(n, src, lab, dst, L, names[:L])
         b = rpq.rpq_batch_create(g, dict(batch_width=int(rng.choice([64, 128, 256])),
-                                          slots=int(rng.integers(1, 6)), chunk_edges=int(rng.integers(1, 70))))
+                                          slots=int(rng.integers(1, 6)), chunk_edges=int(rng.integers(1, 70)),
+                                          visit=1 + trial % 2))
         qs = []
         for i in range(int(rng.integers(1, 8))):
             rx = synth.random_regex(rng, names[:L])
@@ -144,6 +149,10 @@ def test_batch_rmat18_mixed_sizes(rpq):
     # one slot reused by every unit in turn: a retired unit's visited rows must be cleared
     # completely before the next unit seeds (regression: the clear raced with the slot reset)
     check_batch(rpq, g, el, mix, dict(batch_width=512, slots=1), runs=3)
+    # the seen-OR scheme (expansion ORs new bits into the visited rows), against the plain two-read
+    # results, with slots reused: a retired unit's visited rows are cleared from its first-visit log
+    check_batch(rpq, g, el, mix, dict(batch_width=512, slots=8, visit=rpq.RPQ_VISIT_SEEN_OR), runs=2)
+    check_batch(rpq, g, el, mix, dict(batch_width=512, slots=1, visit=rpq.RPQ_VISIT_SEEN_OR), runs=2)
     g.close()
 
 
@@ -219,6 +228,7 @@ def test_batch_tiny_lists_defer_rows_without_changing_results(rpq):
             lo = int(rng.integers(0, el.n_vertices - 1024))
             mix.append((rx, np.arange(lo, lo + 1024, dtype=np.uint32), False, True))
     check_batch(rpq, g, el, mix, dict(batch_width=256, slots=6, list_share=64), runs=2)
+    check_batch(rpq, g, el, mix, dict(batch_width=256, slots=6, list_share=64, visit=rpq.RPQ_VISIT_SEEN_OR), runs=2)
     b = rpq.rpq_batch_create(g, dict(batch_width=64, slots=2, list_share=64))
     b.add(rpq.rpq_nfa_compile("a*", el.names), np.array([1, 2], np.uint32), max_length=3)
     with pytest.raises(rpq.RpqError) as e:

@@ -123,9 +123,9 @@ def test_bounded_batched_matches_plain_and_oracle(rpq):
         s = np.arange(lo, lo + int(rng.integers(1, 300)), dtype=np.uint32)
         k = [0, 1, 2, 3, 6, None][i % 6]
         qs.append((rx, s, k))
-    for width in (64, 256):
-        say("case: bounded batch width %d" % width)
-        b = rpq.rpq_batch_create(g, opts=dict(batch_width=width, slots=3))
+    for width, visit in ((64, 0), (256, 0), (128, rpq.RPQ_VISIT_SEEN_OR)):
+        say("case: bounded batch width %d visit %d" % (width, visit))
+        b = rpq.rpq_batch_create(g, opts=dict(batch_width=width, slots=3, visit=visit))
         for rx, s, k in qs:
             b.add(rpq.rpq_nfa_compile(rx, names), s, pairs_capacity=1 << 20, per_source=True, max_length=k)
         b.run()
