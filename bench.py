@@ -83,6 +83,9 @@ def parse_args():
     ap.add_argument("--mix", action="store_true",
                     help="the 256-query batch on R-MAT scale 22 (generated regexes, half single-source, half "
                          "4,096-source slices): autotuned batched run vs the plain launches")
+    ap.add_argument("--plans", action="store_true",
+                    help="split plans (loop-cache, start-in-the-middle) of a.b.c* against the one-automaton plan, "
+                         "from --sources sampled sources of --workload")
     ap.add_argument("--no-serve-leg", action="store_true", help="skip the serving leg of the default line")
     ap.add_argument("--serve-leg", default="burst,10",
                     help="serving leg of the default line: arrival rates ('burst' = all at once)")
@@ -495,6 +498,55 @@ def mixes(g, el, seed, kinds=("single_source_256", "mixed_128_single_128_slices"
     return out
 
 
+def plans_main(args):
+    """The paper's Q5 shape a.b.c* three ways (Section 2.3; Section 8's plan comparison): the one-automaton
+    plan, start in the middle (a, then b.c* from a's targets, materialized and joined) and loop cache
+    (a.b, then c* from its targets).  Same sources, same keys; time per plan over the timed runs."""
+    import numpy as np
+    import torch
+
+    import paper_2602_20748_amd as rpq
+    import synth
+
+    name = args.workload
+    spec = synth.WORKLOADS[name]
+    print("bench: generating %s" % name, file=sys.stderr, flush=True)
+    el = synth.workload_graph(name)
+    g = rpq.rpq_graph_create(el.src, el.label, el.dst, el.n_vertices, el.n_labels, names=el.names)
+    n_src = 4096 if args.sources < 0 else args.sources
+    src = synth.sample_sources(el.n_vertices, n_src, seed=spec["seed"] + 2000)
+    src_dev = torch.from_numpy(src.astype(np.int64)).to(torch.int32).cuda()
+    comp = lambda rx: rpq.rpq_nfa_compile(rx, el.names)
+    plans = {
+        "one automaton a.b.c*": lambda: (rpq.rpq_eval(g, comp("a.b.c*"), src_dev), None),
+        "start in the middle a | b.c*": lambda: rpq.rpq_eval_split(g, comp("a"), comp("b.c*"), src_dev),
+        "loop cache a.b | c*": lambda: rpq.rpq_eval_split(g, comp("a.b"), comp("c*"), src_dev),
+    }
+    runs = max(1, min(args.steps, 5))
+    out = {}
+    for pname, fn in plans.items():
+        print("bench: plan %s" % pname, file=sys.stderr, flush=True)
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(runs):
+            res, info = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / runs
+        out[pname] = dict(ms=round(ms, 3), count=res.count, hash="%016x" % res.hash, info=info)
+    base = out["one automaton a.b.c*"]
+    identical = all((v["count"], v["hash"]) == (base["count"], base["hash"]) for v in out.values())
+    best = min(v["ms"] for k, v in out.items() if k != "one automaton a.b.c*")
+    line = {"metric": "split plan vs one-automaton plan (a.b.c*)", "value": round(base["ms"] / best, 3), "unit": "x",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "u64", "data": "synthetic (seeded R-MAT; no dataset)",
+            "config": {"workload": "%s: %d vertices, %d distinct edges, %d labels; %d seeded sampled sources; "
+                                   "%d timed runs per plan" % (name, el.n_vertices, g.info()["n_edges"], el.n_labels,
+                                                               n_src, runs)},
+            "plans": out, "results_identical": identical}
+    print(json.dumps(line), flush=True)
+    g.close()
+
+
 def mix_main(args):
     """The 256-query batch on R-MAT scale 22 (half single-source queries, half all-pairs over
     4,096-source slices; generated regexes, 2-12 automaton states): the batched persistent launch,
@@ -549,6 +601,9 @@ def main():
         return
     if args.mix:
         mix_main(args)
+        return
+    if args.plans:
+        plans_main(args)
         return
     spec = synth.WORKLOADS[args.workload]
     queries = spec.get("queries", [])

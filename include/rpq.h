@@ -346,6 +346,47 @@ int rpq_eval_stream(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, 
                     const rpq_pair_stream* out, rpq_result* result, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Split plans: a materialized sub-result joined with the rest of the expression              */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * WavePlan's loop-cache and start-in-the-middle plans (Section 2.3), executed as Section 6
+ * describes: one sub-RPQ's result is materialized in one direction and then joined with the rest
+ * of the expression.  For rho = head . tail (concatenation), walks split at the boundary, so
+ * R(rho) = { (x, y) : (x, m) in R(head) and (m, y) in R(tail) for some m }.  rpq_eval_split runs
+ *   1. head from the sources; the distinct targets are the middle vertices M;
+ *   2. tail from M (exploration starts in the middle of the expression), its pairs materialized
+ *      as edges m -lambda-> y of a new label lambda = n_labels of the graph;
+ *   3. head . lambda (rpq_nfa_append_label) over the graph with lambda added, from the sources.
+ * A split after a closure's prefix (head = a.b, tail = c*) is the loop-cache plan: the closure is
+ * explored once per middle vertex instead of once per unit of sources reaching it.
+ *
+ * The keys, count, checksum and per-source tallies equal rpq_eval's on the concatenated
+ * expression; product_edges, levels and max_depth describe step 3's product graph.
+ * flags: RPQ_PAIRS, RPQ_PER_SOURCE, RPQ_ALL_SOURCES only (RPQ_EUNSUPPORTED otherwise); result as
+ * for rpq_eval (its buffers are the caller's; RPQ_EOVERFLOW with pair_offset resumes, each call
+ * running the whole plan).  The graph needs fewer than RPQ_MAX_LABELS labels and head fewer than
+ * RPQ_MAX_STATES states.  Unlike rpq_eval the call allocates device memory for the steps'
+ * workspaces, the materialized relation and the derived graph, frees it before returning, and
+ * synchronises the stream.  info (host, nullable) receives the sizes of the steps.
+ */
+typedef struct {
+    uint64_t head_pairs;        /* pairs of step 1 */
+    uint64_t middle_vertices;   /* |M| */
+    uint64_t tail_pairs;        /* pairs of step 2: the lambda edges */
+    uint64_t derived_edges;     /* distinct edges of the derived graph */
+} rpq_split_info;
+
+int rpq_eval_split(rpq_graph_t g, const rpq_nfa* head, const rpq_nfa* tail, const uint32_t* sources,
+                   uint64_t n_sources, uint32_t flags, const rpq_eval_opts* opts, rpq_result* result,
+                   rpq_split_info* info, hipStream_t stream);
+
+/* The automaton of L(in) . label: one new state, entered on `label` from every final state of
+ * `in`, and the only final state.  Host.  Errors: RPQ_EINVAL for n_states >= RPQ_MAX_STATES or a
+ * label id >= RPQ_MAX_LABELS. */
+int rpq_nfa_append_label(const rpq_nfa* in, uint32_t label, rpq_nfa* out);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Batched evaluation: many queries in one persistent, graph-captured launch                  */
 /* ------------------------------------------------------------------------------------------ */
 

@@ -21,7 +21,8 @@ from typing import List, Optional, Sequence
 __all__ = [
     "RpqError", "library_path", "load_library", "rpq_abi_version", "rpq_last_error", "rpq_nfa_compile",
     "rpq_nfa_reverse", "rpq_graph_create", "rpq_graph_destroy", "rpq_graph_info_get",
-    "rpq_graph_export_csr", "rpq_eval_workspace_size", "rpq_eval", "rpq_eval_noalloc", "rpq_eval_stream",
+    "rpq_graph_export_csr", "rpq_eval_workspace_size", "rpq_eval", "rpq_eval_noalloc", "rpq_eval_stream", "rpq_eval_split",
+    "rpq_nfa_append_label", "SplitInfo",
     "EvalResult", "Graph",
     "Nfa", "EvalOpts", "RPQ_NOALLOC_SCRATCH_BYTES",
     "RPQ_OK", "RPQ_EINVAL", "RPQ_ENOMEM", "RPQ_EOVERFLOW", "RPQ_EDEVICE", "RPQ_EUNSUPPORTED", "RPQ_ECANCELED",
@@ -94,6 +95,11 @@ class Profile(ctypes.Structure):
 class BatchOpts(ctypes.Structure):
     _fields_ = [("batch_width", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("chunk_edges", ctypes.c_uint32),
                 ("list_share", ctypes.c_uint32), ("visit", ctypes.c_uint32)]
+
+
+class SplitInfo(ctypes.Structure):
+    _fields_ = [("head_pairs", ctypes.c_uint64), ("middle_vertices", ctypes.c_uint64),
+                ("tail_pairs", ctypes.c_uint64), ("derived_edges", ctypes.c_uint64)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -182,7 +188,8 @@ class ServerStats(ctypes.Structure):
 EXPORTED_SYMBOLS = [
     "rpq_last_error", "rpq_abi_version", "rpq_graph_create", "rpq_graph_destroy", "rpq_graph_info_get",
     "rpq_graph_export_csr", "rpq_nfa_compile", "rpq_nfa_reverse", "rpq_eval_workspace_size", "rpq_eval",
-    "rpq_eval_noalloc", "rpq_eval_stream", "rpq_profile_enable", "rpq_profile_read",
+    "rpq_eval_noalloc", "rpq_eval_stream", "rpq_eval_split", "rpq_nfa_append_label", "rpq_profile_enable",
+    "rpq_profile_read",
     "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size", "rpq_batch_run",
     "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune", "rpq_batch_bound_length",
     "crpq_eval", "rpq_serve_start", "rpq_serve_submit", "rpq_serve_poll", "rpq_serve_wait", "rpq_serve_clock_ms",
@@ -224,6 +231,9 @@ def load_library():
                                              ctypes.POINTER(_Result), vp]),
         "rpq_eval_stream": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), vp, u64, u32, ctypes.POINTER(EvalOpts), vp, u64,
                                             ctypes.POINTER(_PairStream), ctypes.POINTER(_Result), vp]),
+        "rpq_eval_split": (ctypes.c_int, [vp, ctypes.POINTER(Nfa), ctypes.POINTER(Nfa), vp, u64, u32,
+                                          ctypes.POINTER(EvalOpts), vp, ctypes.POINTER(SplitInfo), vp]),
+        "rpq_nfa_append_label": (ctypes.c_int, [ctypes.POINTER(Nfa), u32, ctypes.POINTER(Nfa)]),
         "rpq_profile_enable": (ctypes.c_int, [ctypes.c_int]),
         "rpq_batch_create": (ctypes.c_int, [vp, ctypes.POINTER(BatchOpts), ctypes.POINTER(vp)]),
         "rpq_batch_destroy": (ctypes.c_int, [vp]),
@@ -564,6 +574,55 @@ def rpq_eval_stream(g: Graph, nfa: Nfa, sink, sources=None, flags: int = 0, opts
     _check(rc)
     return EvalResult(int(res.count), int(res.hash), int(res.product_edges), int(res.levels), int(res.max_depth),
                       int(res.written), None, per_source, rc)
+
+
+def rpq_nfa_append_label(nfa: Nfa, label: int) -> Nfa:
+    out = Nfa()
+    _check(load_library().rpq_nfa_append_label(ctypes.byref(nfa), int(label), ctypes.byref(out)))
+    return out
+
+
+def rpq_eval_split(g: Graph, head: Nfa, tail: Nfa, sources=None, opts=None, pairs=None, per_source=None,
+                   stream=None, allow_overflow: bool = False):
+    """R(head . tail) through the materialized R(tail) from the middle vertices (rpq_eval_split).
+
+    pairs: a CUDA int64 tensor (capacity = its length), or True for one of exactly the needed
+    size (the plan runs twice), or None.  per_source: a CUDA int64 tensor [n, 2], or True.
+    Returns (EvalResult, info dict)."""
+    torch = _torch()
+    lib = load_library()
+    flags = 0
+    if sources is None:
+        flags |= RPQ_ALL_SOURCES
+        src_t = None
+        n = rpq_graph_info_get(g)["n_vertices"]
+    else:
+        src_t = _dev_u32(sources, torch)
+        n = src_t.numel()
+    o = _opts(opts)
+    if per_source is True:
+        per_source = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+    if per_source is not None:
+        flags |= RPQ_PER_SOURCE
+    if pairs is True:
+        first, _ = rpq_eval_split(g, head, tail, src_t, opts, None, per_source, stream)
+        pairs = torch.empty(max(first.count, 1), dtype=torch.int64, device="cuda")
+    if pairs is not None:
+        flags |= RPQ_PAIRS
+    res = _Result()
+    res.pairs = pairs.data_ptr() if pairs is not None else None
+    res.capacity = int(pairs.numel()) if pairs is not None else 0
+    res.per_source = per_source.data_ptr() if per_source is not None else None
+    info = SplitInfo()
+    rc = lib.rpq_eval_split(g.handle, ctypes.byref(head), ctypes.byref(tail),
+                            src_t.data_ptr() if (src_t is not None and n) else None, n, flags,
+                            ctypes.byref(o) if o is not None else None, ctypes.byref(res), ctypes.byref(info),
+                            _stream(stream))
+    _check(rc, allow=(RPQ_EOVERFLOW,) if allow_overflow else ())
+    out_pairs = pairs[: res.written] if pairs is not None else None
+    return (EvalResult(int(res.count), int(res.hash), int(res.product_edges), int(res.levels), int(res.max_depth),
+                       int(res.written), out_pairs, per_source, rc),
+            {name: int(getattr(info, name)) for name, _ in SplitInfo._fields_})
 
 
 def rpq_eval_noalloc(g: Graph, nfa: Nfa, sources=None, flags: int = 0, opts=None, pairs=None,

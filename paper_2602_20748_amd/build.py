@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "librpq.so")
-SOURCES = ["prims.hip", "graph.hip", "nfa.cpp", "eval.hip", "batch.hip", "crpq.hip", "serve.cpp"]
+SOURCES = ["prims.hip", "graph.hip", "nfa.cpp", "eval.hip", "batch.hip", "crpq.hip", "plan.hip", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

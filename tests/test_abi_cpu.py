@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import paper_2602_20748_amd as rpq
-from oracle.automata import glushkov, parse
+from oracle.automata import glushkov, parse, thompson
 import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -152,3 +152,33 @@ def test_workspace_size_rejects_null_graph(lib):
     n = ctypes.c_uint64()
     rc = lib.rpq_eval_workspace_size(None, ctypes.byref(nfa), 10, 0, None, ctypes.byref(n))
     assert rc == rpq.RPQ_EINVAL
+
+
+def _table_accepts(nfa, word):
+    cur = nfa.initial_mask
+    for a in word:
+        nxt = 0
+        for q in range(nfa.n_states):
+            if (cur >> q) & 1:
+                nxt |= nfa.successors(q, a)
+        cur = nxt
+    return bool(cur & nfa.final_mask)
+
+
+@pytest.mark.parametrize("regex", ["a", "a.b*", "(a|b).c*", "a?", "(a.b)*", "c*.a+"])
+def test_append_label_accepts_the_language_then_the_label(lib, regex):
+    # L(append(rho, lambda)) = L(rho) . lambda for a label lambda outside rho's alphabet: checked
+    # word by word against the oracle's Thompson automaton for rho, over every word of length <= 5
+    names = ["a", "b", "c"]
+    nfa = rpq.rpq_nfa_compile(regex, names)
+    ap = rpq.rpq_nfa_append_label(nfa, 3)
+    assert ap.n_states == nfa.n_states + 1 and ap.n_labels == 4
+    ref = thompson(parse(regex, names))
+    words = [[]]
+    for _ in range(5):
+        words += [w + [a] for w in words if len(w) == _ for a in range(4)]
+    for w in words:
+        want = len(w) >= 1 and w[-1] == 3 and 3 not in w[:-1] and ref.accepts(w[:-1])
+        assert _table_accepts(ap, w) == want, (regex, w)
+    with pytest.raises(rpq.RpqError):
+        rpq.rpq_nfa_append_label(nfa, 64)
