@@ -142,7 +142,12 @@ def crpq_main():
              ("3-cycle of knows.knows*, 128 persons, sorted tuples",
               lambda: rpq.crpq_eval(g, cyc, 3, domain=[s128] * 3, vertex_label=[0] * 3, tuples=True)),
              ("3-cycle of knows.knows*, 1,024 persons, count + checksum",
-              lambda: rpq.crpq_eval(g, cyc, 3, domain=[s1024] * 3, vertex_label=[0] * 3))]
+              lambda: rpq.crpq_eval(g, cyc, 3, domain=[s1024] * 3, vertex_label=[0] * 3)),
+             ("3-cycle, 128 persons, sorted tuples, atoms in the batched form",
+              lambda: rpq.crpq_eval(g, cyc, 3, domain=[s128] * 3, vertex_label=[0] * 3, tuples=True,
+                                    flags=rpq.CRPQ_BATCH_ATOMS)),
+             ("3-cycle, 1,024 persons, count + checksum, atoms in the batched form",
+              lambda: rpq.crpq_eval(g, cyc, 3, domain=[s1024] * 3, vertex_label=[0] * 3, flags=rpq.CRPQ_BATCH_ATOMS))]
     out = []
     for name, f in cases:
         print("bench: crpq %s" % name, file=sys.stderr, flush=True)

@@ -529,12 +529,21 @@ typedef struct {
 #define CRPQ_FORCE_SPARSE  2u   /* every multi-step atom by the per-source hash-set search */
 #define CRPQ_NO_EDGE_SCAN  4u   /* single-label atoms are traversed like the others */
 #define CRPQ_NO_REVERSE    8u   /* never traverse an atom backwards */
+#define CRPQ_BATCH_ATOMS  16u   /* the atoms that run bit-parallel and forward from their source
+                                   variable's domain run together in the batched persistent form
+                                   (rpq_batch_*): one run counts their pairs, a second writes them.
+                                   They then start from the domains as the constraints fix them,
+                                   before the semi-join reductions of the other atoms narrow them;
+                                   when the join reaches such an atom its pairs are restricted to the
+                                   reduced domains, so the result is the same.  Creates a batch and
+                                   its capture stream for the call; device memory from the workspace. */
 
 /* Per-atom strategy codes reported in crpq_result.atom_strategy */
 #define CRPQ_STRATEGY_EDGE_SCAN 1u
 #define CRPQ_STRATEGY_DENSE     2u
 #define CRPQ_STRATEGY_SPARSE    3u
 #define CRPQ_STRATEGY_REVERSED  0x100u   /* or-ed in when the atom ran backwards from dst_var */
+#define CRPQ_STRATEGY_BATCHED   0x200u   /* or-ed in when the atom ran in the batched form */
 
 /* Result of crpq_eval (host struct).
  *   tuples, capacity: device buffer of capacity rows of n_free uint32 (row-major), or NULL

@@ -32,7 +32,8 @@ __all__ = [
     "Batch", "rpq_batch_create", "rpq_batch_destroy", "rpq_batch_add", "rpq_batch_workspace_size",
     "rpq_batch_run", "rpq_batch_result", "rpq_batch_stats", "rpq_batch_autotune",
     "crpq_eval", "CrpqOutput", "CrpqAtom", "CrpqVars", "CrpqResult", "CRPQ_FORCE_DENSE", "CRPQ_FORCE_SPARSE",
-    "CRPQ_NO_EDGE_SCAN", "CRPQ_NO_REVERSE", "CRPQ_STRATEGY_EDGE_SCAN", "CRPQ_STRATEGY_DENSE",
+    "CRPQ_NO_EDGE_SCAN", "CRPQ_NO_REVERSE", "CRPQ_BATCH_ATOMS", "CRPQ_STRATEGY_EDGE_SCAN", "CRPQ_STRATEGY_DENSE",
+    "CRPQ_STRATEGY_BATCHED",
     "CRPQ_STRATEGY_SPARSE", "CRPQ_STRATEGY_REVERSED", "Server", "Request", "Ticket", "ServerOpts", "ServerStats",
     "RPQ_REQ_RPQ", "RPQ_REQ_CRPQ",
 ]
@@ -130,8 +131,9 @@ class _Result(ctypes.Structure):
 
 CRPQ_MAX_VARS = 16
 CRPQ_MAX_ATOMS = 16
-CRPQ_FORCE_DENSE, CRPQ_FORCE_SPARSE, CRPQ_NO_EDGE_SCAN, CRPQ_NO_REVERSE = 1, 2, 4, 8
+CRPQ_FORCE_DENSE, CRPQ_FORCE_SPARSE, CRPQ_NO_EDGE_SCAN, CRPQ_NO_REVERSE, CRPQ_BATCH_ATOMS = 1, 2, 4, 8, 16
 CRPQ_STRATEGY_EDGE_SCAN, CRPQ_STRATEGY_DENSE, CRPQ_STRATEGY_SPARSE, CRPQ_STRATEGY_REVERSED = 1, 2, 3, 0x100
+CRPQ_STRATEGY_BATCHED = 0x200
 
 
 class CrpqAtom(ctypes.Structure):

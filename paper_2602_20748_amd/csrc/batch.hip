@@ -69,6 +69,8 @@ struct BQuery {
     uint32_t first_unit, n_units;
     uint32_t flags;
     uint32_t max_len;          // length bound: the deepest depth recorded (0xFFFFFFFF = none)
+    const uint64_t* target;    // device bitmap of V bits, or null: only result vertices with their bit
+                               // set are counted, hashed and written
 };
 
 struct BQueryOut {
@@ -487,8 +489,9 @@ __device__ void phase_retire_extract(const BArgs& a, const uint32_t* list, uint3
         while (any) {
             const int wl = __ffsll((long long)any) - 1;
             any &= any - 1;
-            const uint64_t bits = __shfl(sw, wl, 64);
+            uint64_t bits = __shfl(sw, wl, 64);
             const uint32_t vg = vbeg + (uint32_t)wl * 64;
+            if (Qy.target) bits &= Qy.target[vg >> 6];   // vg is a multiple of 64
             const uint64_t mine = ((bits >> lane) & 1) ? xld(a.ans + ((uint64_t)slot * a.V + vg + lane) * K + k) : 0;
             uint64_t nz = __ballot(mine != 0);
             while (nz) {
@@ -1035,6 +1038,7 @@ struct HostQuery {
     uint64_t* pairs;
     uint64_t capacity;
     uint64_t* per_source;
+    const uint64_t* target = nullptr;
 };
 
 struct Layout {
@@ -1496,6 +1500,27 @@ int rpq_batch_bound_length(rpq_batch_t b, uint32_t query_id, uint32_t max_length
     return RPQ_OK;
 }
 
+}  // extern "C"
+
+namespace rpq {
+
+int batch_filter_targets(rpq_batch_t b, uint32_t query_id, const uint64_t* target) {
+    if (!b || query_id >= b->queries.size()) {
+        rpq::set_error("unknown batch or query");
+        return RPQ_EINVAL;
+    }
+    if (b->frozen) {
+        rpq::set_error("batch already ran; create a new batch to filter a query's results");
+        return RPQ_EINVAL;
+    }
+    b->queries[query_id].target = target;
+    return RPQ_OK;
+}
+
+}  // namespace rpq
+
+extern "C" {
+
 int rpq_batch_workspace_size(rpq_batch_t b, uint64_t* bytes) {
     rpq::clear_error();
     if (!b || !bytes) {
@@ -1570,6 +1595,7 @@ int rpq_batch_run(rpq_batch_t b, void* workspace, uint64_t workspace_bytes, hipS
             ufirst += d.n_units;
             d.flags = h.flags;
             d.max_len = h.max_len;
+            d.target = h.target;
         }
         RPQ_HIP(hipMemcpy(ws + x.off_nfas, nf.data(), sizeof(BNfa) * nq, hipMemcpyHostToDevice));
         RPQ_HIP(hipMemcpy(ws + x.off_queries, qs.data(), sizeof(BQuery) * nq, hipMemcpyHostToDevice));

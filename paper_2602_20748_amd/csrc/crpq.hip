@@ -160,23 +160,30 @@ __global__ void k_swap_halves(const uint64_t* __restrict__ in, uint64_t* __restr
 
 // ------------------------------------------------------------------------------------------------
 // order-preserving compaction of sorted keys: mode 0 keeps the first of each run of equal keys,
-// mode 1 additionally keeps only keys with equal halves (pairs (v, v))
+// mode 1 additionally keeps only keys with equal halves (pairs (v, v)); with domain bitmaps (or
+// null) only keys whose high half is in dhi and whose low half is in dlo
 // ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ bool keep_key(const uint64_t* keys, uint64_t i, int mode) {
+__device__ __forceinline__ bool keep_key(const uint64_t* keys, uint64_t i, int mode, const uint64_t* dhi,
+                                         const uint64_t* dlo) {
     const uint64_t k = keys[i];
     if (i > 0 && keys[i - 1] == k) return false;
-    if (mode == 1 && (k >> 32) != (k & 0xFFFFFFFFull)) return false;
+    const uint32_t hi = (uint32_t)(k >> 32), lo = (uint32_t)k;
+    if (mode == 1 && hi != lo) return false;
+    if (dhi && !((dhi[hi >> 6] >> (hi & 63)) & 1)) return false;
+    if (dlo && !((dlo[lo >> 6] >> (lo & 63)) & 1)) return false;
     return true;
 }
 
 __global__ __launch_bounds__(kBlock) void k_tile_count(const uint64_t* __restrict__ keys, uint64_t n, int mode,
+                                                       const uint64_t* __restrict__ dhi,
+                                                       const uint64_t* __restrict__ dlo,
                                                        uint64_t* __restrict__ counts) {
     __shared__ uint32_t s_sum[kWaves];
     const uint64_t base = (uint64_t)blockIdx.x * kTile;
     uint32_t c = 0;
     for (int j = threadIdx.x; j < kTile; j += kBlock) {
         const uint64_t i = base + j;
-        if (i < n && keep_key(keys, i, mode)) ++c;
+        if (i < n && keep_key(keys, i, mode, dhi, dlo)) ++c;
     }
     c = (uint32_t)rpqd::wave_sum_u64(c);
     if (__lane_id() == 0) s_sum[threadIdx.x >> 6] = c;
@@ -189,6 +196,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint64_t* __restric
 }
 
 __global__ __launch_bounds__(kBlock) void k_tile_write(const uint64_t* __restrict__ keys, uint64_t n, int mode,
+                                                       const uint64_t* __restrict__ dhi,
+                                                       const uint64_t* __restrict__ dlo,
                                                        const uint64_t* __restrict__ offs, uint64_t* __restrict__ out) {
     __shared__ uint32_t s_sum[kWaves];
     __shared__ uint64_t s_run;
@@ -198,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_write(const uint64_t* __restric
     const int lane = __lane_id(), wv = threadIdx.x >> 6;
     for (int j0 = 0; j0 < kTile; j0 += kBlock) {
         const uint64_t i = base + j0 + threadIdx.x;
-        const bool keep = i < n && keep_key(keys, i, mode);
+        const bool keep = i < n && keep_key(keys, i, mode, dhi, dlo);
         const uint64_t m = __ballot(keep);
         if (lane == 0) s_sum[wv] = (uint32_t)__popcll(m);
         __syncthreads();
@@ -688,7 +697,8 @@ int bits_to_list(Ctx& c, const uint64_t* bits, uint32_t** list, uint64_t* n) {
 
 // sort keys (both halves are vertex ids) and keep distinct ones (mode 1: only (v, v)); result
 // replaces *keys (same allocation), *n updated
-int sort_unique(Ctx& c, uint64_t* keys, uint64_t* n, bool sorted_already, int mode) {
+int sort_unique(Ctx& c, uint64_t* keys, uint64_t* n, bool sorted_already, int mode, const uint64_t* dhi = nullptr,
+                const uint64_t* dlo = nullptr) {
     if (*n == 0) return RPQ_OK;
     const uint64_t mark = c.ar.top;
     const int vb = rpq::bits_for(c.g->V ? c.g->V - 1 : 0);
@@ -707,10 +717,10 @@ int sort_unique(Ctx& c, uint64_t* keys, uint64_t* n, bool sorted_already, int mo
     CRPQ_TAKE(stmp, uint64_t, rpq::scan_temp_elems(tiles));
     uint64_t* out = keys;
     if (src == keys) CRPQ_TAKE(out, uint64_t, *n);   // compaction needs distinct in/out buffers
-    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)tiles), dim3(kBlock), 0, c.s, src, *n, mode, offs);
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)tiles), dim3(kBlock), 0, c.s, src, *n, mode, dhi, dlo, offs);
     RPQ_LAUNCH_CHECK();
     RPQ_TRY(rpq::exclusive_scan_u64(offs, offs, tiles, stmp, offs + tiles, c.s));
-    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)tiles), dim3(kBlock), 0, c.s, src, *n, mode, offs, out);
+    hipLaunchKernelGGL(k_tile_write, dim3((unsigned)tiles), dim3(kBlock), 0, c.s, src, *n, mode, dhi, dlo, offs, out);
     RPQ_LAUNCH_CHECK();
     RPQ_HIP(hipMemcpyAsync(c.stage, offs + tiles, 8, hipMemcpyDeviceToHost, c.s));
     RPQ_HIP(hipStreamSynchronize(c.s));
@@ -847,6 +857,91 @@ int eval_dense(Ctx& c, const rpq_nfa& nfa, bool reverse, const uint32_t* srcs, u
     c.ar.top = mark + align256(std::max<uint64_t>(1, r.count) * 8);   // keep the pairs, drop the traversal state
     *keys = pairs;
     *n = r.count;
+    return RPQ_OK;
+}
+
+// CRPQ_BATCH_ATOMS: the query's forward bit-parallel atoms run together in the batched persistent
+// form (Section 4.2's traversal queue feeding one exploration kernel, here across atoms), each from
+// its source variable's domain as the constraints fix it.  One run counts their pairs, a second
+// writes them into the workspace, where they stay for the join.
+struct BatchGuard {
+    rpq_batch_t b = nullptr;
+    ~BatchGuard() {
+        if (b) (void)rpq_batch_destroy(b);
+    }
+};
+
+int batch_run(Ctx& c, const crpq_atom* atoms, const std::vector<uint32_t>& ids, const std::vector<uint32_t*>& srcs,
+              const std::vector<uint64_t>& ns, const std::vector<const uint64_t*>& targets, uint32_t width,
+              uint64_t* const* pairs, std::vector<uint64_t>& counts) {
+    BatchGuard bg;
+    rpq_batch_opts o;
+    std::memset(&o, 0, sizeof o);
+    o.batch_width = width;
+    RPQ_TRY(rpq_batch_create(c.g, &o, &bg.b));
+    std::vector<uint32_t> qid(ids.size());
+    for (size_t j = 0; j < ids.size(); ++j) {
+        RPQ_TRY(rpq_batch_add(bg.b, &atoms[ids[j]].nfa, srcs[j], ns[j], pairs ? RPQ_PAIRS : 0u,
+                              pairs ? pairs[j] : nullptr, pairs ? counts[j] : 0, nullptr, &qid[j]));
+        // only destinations in the atom's destination domain, as the sequential plan's filter
+        RPQ_TRY(rpq::batch_filter_targets(bg.b, qid[j], targets[j]));
+    }
+    uint64_t ws = 0;
+    RPQ_TRY(rpq_batch_workspace_size(bg.b, &ws));
+    const uint64_t mark = c.ar.top;
+    char* w;
+    CRPQ_TAKE(w, char, ws);
+    RPQ_TRY(rpq_batch_run(bg.b, w, ws, c.s));
+    for (size_t j = 0; j < ids.size(); ++j) {
+        rpq_result r;
+        RPQ_TRY(rpq_batch_result(bg.b, qid[j], &r));
+        if (pairs && r.count != counts[j]) {
+            rpq::set_error("batched atom %u: %llu pairs on the second run, %llu on the first", ids[j],
+                           (unsigned long long)r.count, (unsigned long long)counts[j]);
+            return RPQ_EDEVICE;
+        }
+        counts[j] = r.count;
+    }
+    c.ar.top = mark;   // the traversal state goes; the pairs were taken below it
+    return RPQ_OK;
+}
+
+int batch_atoms(Ctx& c, const crpq_atom* atoms, uint32_t n_atoms, uint32_t flags, const std::vector<uint64_t*>& dom,
+                const std::vector<uint64_t>& dom_n, std::vector<bool>& pre, std::vector<uint64_t*>& keys,
+                std::vector<uint64_t>& nk) {
+    std::vector<uint32_t> ids;
+    uint64_t widest = 1;
+    for (uint32_t i = 0; i < n_atoms; ++i) {
+        const uint32_t x = atoms[i].src_var, y = atoms[i].dst_var;
+        uint64_t lang = 0;
+        const bool scan = !(flags & CRPQ_NO_EDGE_SCAN) && single_step_language(atoms[i].nfa, &lang);
+        const bool reverse = !(flags & CRPQ_NO_REVERSE) && c.g->has_in && x != y && dom_n[y] < dom_n[x];
+        const bool dense = (flags & CRPQ_FORCE_DENSE) || (!(flags & CRPQ_FORCE_SPARSE) && dom_n[x] <= kDenseMaxSources);
+        if (!scan && !reverse && dense) {
+            ids.push_back(i);
+            widest = std::max(widest, dom_n[x]);
+        }
+    }
+    if (ids.empty()) return RPQ_OK;
+    // units as wide as the largest source set needs, 64 .. 2048
+    uint32_t width = 64;
+    while (width < 2048 && width < widest) width *= 2;
+    std::vector<uint32_t*> srcs(ids.size());
+    std::vector<uint64_t> ns(ids.size()), counts(ids.size(), 0);
+    std::vector<const uint64_t*> targets(ids.size());
+    for (size_t j = 0; j < ids.size(); ++j) {
+        RPQ_TRY(bits_to_list(c, dom[atoms[ids[j]].src_var], &srcs[j], &ns[j]));
+        targets[j] = dom[atoms[ids[j]].dst_var];
+    }
+    RPQ_TRY(batch_run(c, atoms, ids, srcs, ns, targets, width, nullptr, counts));
+    std::vector<uint64_t*> bufs(ids.size());
+    for (size_t j = 0; j < ids.size(); ++j) CRPQ_TAKE(bufs[j], uint64_t, counts[j]);
+    RPQ_TRY(batch_run(c, atoms, ids, srcs, ns, targets, width, bufs.data(), counts));
+    for (size_t j = 0; j < ids.size(); ++j) {
+        pre[ids[j]] = true;
+        keys[ids[j]] = bufs[j];
+        nk[ids[j]] = counts[j];
+    }
     return RPQ_OK;
 }
 
@@ -1145,7 +1240,7 @@ int crpq_eval_body(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, cons
         rpq::set_error("n_vars must be 1..%d and n_atoms at most %d", CRPQ_MAX_VARS, CRPQ_MAX_ATOMS);
         return RPQ_EINVAL;
     }
-    if (flags & ~(CRPQ_FORCE_DENSE | CRPQ_FORCE_SPARSE | CRPQ_NO_EDGE_SCAN | CRPQ_NO_REVERSE)) {
+    if (flags & ~(CRPQ_FORCE_DENSE | CRPQ_FORCE_SPARSE | CRPQ_NO_EDGE_SCAN | CRPQ_NO_REVERSE | CRPQ_BATCH_ATOMS)) {
         rpq::set_error("unknown flags 0x%x", flags);
         return RPQ_EINVAL;
     }
@@ -1283,6 +1378,10 @@ int crpq_eval_body(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, cons
         if (dom_n[i] == 0) return empty_result();
 
     // ---- 2. atoms, smallest source domain first, with semi-join reduction of the domains
+    std::vector<bool> pre(n_atoms, false);
+    std::vector<uint64_t*> pre_keys(n_atoms, nullptr);
+    std::vector<uint64_t> pre_n(n_atoms, 0);
+    if (flags & CRPQ_BATCH_ATOMS) CRPQ_STEP(batch_atoms(c, atoms, n_atoms, flags, dom, dom_n, pre, pre_keys, pre_n));
     std::vector<Rel> rel(n_atoms);
     std::vector<bool> done(n_atoms, false);
     for (uint32_t it = 0; it < n_atoms; ++it) {
@@ -1299,28 +1398,36 @@ int crpq_eval_body(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, cons
         const crpq_atom& at = atoms[pick];
         done[pick] = true;
         const uint32_t x = at.src_var, y = at.dst_var;
-        const bool reverse = !(flags & CRPQ_NO_REVERSE) && g->has_in && x != y && dom_n[y] < dom_n[x];
+        const bool batched = pre[pick];
+        const bool reverse = !batched && !(flags & CRPQ_NO_REVERSE) && g->has_in && x != y && dom_n[y] < dom_n[x];
         const uint32_t sv = reverse ? y : x, dv = reverse ? x : y;
         uint64_t lang = 0;
-        const bool scan = !(flags & CRPQ_NO_EDGE_SCAN) && single_step_language(at.nfa, &lang);
+        const bool scan = !batched && !(flags & CRPQ_NO_EDGE_SCAN) && single_step_language(at.nfa, &lang);
         uint32_t strategy;
-        if (scan) strategy = CRPQ_STRATEGY_EDGE_SCAN;
+        if (batched) strategy = CRPQ_STRATEGY_DENSE;
+        else if (scan) strategy = CRPQ_STRATEGY_EDGE_SCAN;
         else if (flags & CRPQ_FORCE_DENSE) strategy = CRPQ_STRATEGY_DENSE;
         else if (flags & CRPQ_FORCE_SPARSE) strategy = CRPQ_STRATEGY_SPARSE;
         else strategy = dom_n[sv] <= kDenseMaxSources ? CRPQ_STRATEGY_DENSE : CRPQ_STRATEGY_SPARSE;
-        res->atom_strategy[pick] = strategy | (reverse ? CRPQ_STRATEGY_REVERSED : 0u);
+        res->atom_strategy[pick] = strategy | (reverse ? CRPQ_STRATEGY_REVERSED : 0u) |
+                                   (batched ? CRPQ_STRATEGY_BATCHED : 0u);
         Rel& R = rel[pick];
         R.x = x;
         R.y = y;
         CRPQ_STEP([&]() -> int {
             const uint64_t mark = c.ar.top;
-            uint32_t* srcs;
+            uint32_t* srcs = nullptr;
             uint64_t n_src = 0;
-            RPQ_TRY(bits_to_list(c, dom[sv], &srcs, &n_src));
+            if (!batched) RPQ_TRY(bits_to_list(c, dom[sv], &srcs, &n_src));
             uint64_t* keys = nullptr;
             uint64_t nk = 0;
             bool sorted = false;
-            if (strategy == CRPQ_STRATEGY_EDGE_SCAN) {
+            if (batched) {
+                // evaluated from the domains before any reduction: restricted to the current ones below
+                keys = pre_keys[pick];
+                nk = pre_n[pick];
+                sorted = true;
+            } else if (strategy == CRPQ_STRATEGY_EDGE_SCAN) {
                 RPQ_TRY(eval_edge_scan(c, reverse ? g->in : g->out, lang, srcs, n_src, dom[dv], &keys, &nk));
             } else if (strategy == CRPQ_STRATEGY_DENSE) {
                 RPQ_TRY(eval_dense(c, at.nfa, reverse, srcs, n_src, dom[dv], &keys, &nk));
@@ -1351,7 +1458,8 @@ int crpq_eval_body(rpq_graph_t g, const crpq_atom* atoms, uint32_t n_atoms, cons
                 RPQ_LAUNCH_CHECK();
                 sorted = false;
             }
-            RPQ_TRY(sort_unique(c, keys, &nk, sorted, x == y ? 1 : 0));
+            RPQ_TRY(sort_unique(c, keys, &nk, sorted, x == y ? 1 : 0, batched ? dom[x] : nullptr,
+                                batched ? dom[y] : nullptr));
             (void)mark;   // the source list below the relation stays allocated (the arena is a stack)
             R.fwd = keys;
             R.n = nk;

@@ -81,6 +81,10 @@ int radix_sort_u64(uint64_t* keys, uint64_t* alt, uint64_t n, int lo_bits, int h
 // rpq_eval with an optional result-vertex filter (device bitmap of V bits, or null): the
 // traversal is unchanged and only result pairs whose non-source vertex has its bit set are
 // counted, hashed and written.
+// Batched form: only result pairs whose destination has its bit set in `target` (device bitmap of
+// V bits) count, as eval_impl's filter; before the batch's first run.
+int batch_filter_targets(rpq_batch_t b, uint32_t query_id, const uint64_t* target);
+
 int eval_impl(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64_t n_sources, uint32_t flags,
               const rpq_eval_opts* opts, const uint64_t* target, void* workspace, uint64_t workspace_bytes,
               rpq_result* res, hipStream_t stream);

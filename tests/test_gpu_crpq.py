@@ -30,7 +30,9 @@ def rpq():
 
 def strategies(rpq):
     return [0, rpq.CRPQ_FORCE_DENSE, rpq.CRPQ_FORCE_SPARSE, rpq.CRPQ_NO_EDGE_SCAN | rpq.CRPQ_NO_REVERSE,
-            rpq.CRPQ_FORCE_SPARSE | rpq.CRPQ_NO_EDGE_SCAN]
+            rpq.CRPQ_FORCE_SPARSE | rpq.CRPQ_NO_EDGE_SCAN,
+            # atoms in the batched persistent form (those that run forward, bit-parallel)
+            rpq.CRPQ_BATCH_ATOMS, rpq.CRPQ_BATCH_ATOMS | rpq.CRPQ_FORCE_DENSE | rpq.CRPQ_NO_REVERSE | rpq.CRPQ_NO_EDGE_SCAN]
 
 
 def rows(r):
@@ -321,6 +323,12 @@ def test_social_full_size_cycle(rpq, social_full):
     assert r.count == len(want)
     assert np.array_equal(r.tuples.cpu().numpy().view(np.uint32).astype(np.int64), want)
     assert r.hash == chain_hash(want)
+    say("case: social full 3-cycle, 128 persons, atoms in the batched form")
+    rb = rpq.crpq_eval(g, cyc, 3, domain=[s128] * 3, vertex_label=[PERSON] * 3, tuples=True,
+                       flags=rpq.CRPQ_BATCH_ATOMS)
+    assert all(st & rpq.CRPQ_STRATEGY_BATCHED for st in rb.atom_strategy[:3])
+    assert rb.count == len(want) and rb.hash == r.hash
+    assert np.array_equal(rb.tuples.cpu().numpy().view(np.uint32).astype(np.int64), want)
     s1024 = np.sort(rng.choice(P, size=1024, replace=False)).astype(np.uint32)
     say("case: social full 3-cycle, 1,024 persons, count only")
     r = rpq.crpq_eval(g, cyc, 3, domain=[s1024] * 3, vertex_label=[PERSON] * 3)
