@@ -240,7 +240,12 @@ def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib,
         del srv
         torch.cuda.empty_cache()   # the pool goes back before the FIFO replay allocates its workspaces
         warm = t0 if burst else t0 + warmup_seconds * 1e3
-        meas = [d for d in done if d["arrival_ms"] >= warm] or done
+        # requests the server could not run (e.g. a workspace beyond the pool: RPQ_ENOMEM) are reported
+        # and left out of the latencies and of the one-at-a-time replay
+        ok_status = (0, rpq.RPQ_EOVERFLOW)
+        failed = [(reqs[i][0], int(d["status"])) for i, d in enumerate(done) if d["status"] not in ok_status]
+        served = [d for d in done if d["status"] in ok_status]
+        meas = [d for d in served if d["arrival_ms"] >= warm] or served
         lat = np.array([d["end_ms"] - d["arrival_ms"] for d in meas])
         span = (max(d["end_ms"] for d in meas) - min(d["arrival_ms"] for d in meas)) / 1e3
         ep = sum(d["product_edges"] for d in meas)
@@ -254,6 +259,9 @@ def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib,
             if time.time() - last_note > 10:
                 last_note = time.time()
                 print("bench: FIFO %d / %d" % (i + 1, n), file=sys.stderr, flush=True)
+            if d["status"] not in ok_status:
+                fifo_times.append(float("nan"))
+                continue
             t = time.perf_counter()
             if r[0] == "crpq":
                 a = rpq.crpq_eval(g, r[1], r[2], binding=r[3])
@@ -267,16 +275,17 @@ def serve_points(g, el, seed, rates, seconds, warmup_seconds, workers, pool_gib,
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
             fifo_times.append(dt)
-            identical &= ok and d["status"] in (0, rpq.RPQ_EOVERFLOW)
-            if d["arrival_ms"] >= warm or len(meas) == len(done):
+            identical &= ok
+            if d["arrival_ms"] >= warm or len(meas) == len(served):
                 fifo_s += dt
                 fifo_ep += e
         kinds = {k: sum(1 for r in reqs if r[0] == k) for k in ("rpq_single", "rpq_slice", "crpq")}
-        service = {k: round(float(np.mean([d["end_ms"] - d["start_ms"] for r, d in zip(reqs, done) if r[0] == k]
-                                          or [0.0])), 3) for k in kinds}
-        fifo_kind = {k: round(1e3 * float(np.mean([t for r, t in zip(reqs, fifo_times) if r[0] == k] or [0.0])), 3)
-                     for k in kinds}
+        service = {k: round(float(np.mean([d["end_ms"] - d["start_ms"] for r, d in zip(reqs, done)
+                                           if r[0] == k and d["status"] in ok_status] or [0.0])), 3) for k in kinds}
+        fifo_kind = {k: round(1e3 * float(np.mean([t for r, t in zip(reqs, fifo_times) if r[0] == k and t == t]
+                                                  or [0.0])), 3) for k in kinds}
         points.append(dict(qps="burst" if burst else qps, requests=n, measured=len(meas), mix=kinds, workers=workers,
+                           failed=len(failed), failed_kind_status=failed,
                            resident=dict(slots=resident_slots, completed=sst["resident_completed"],
                                          launches=sst["resident_launches"],
                                          gib=round(sst["resident_bytes"] / 2 ** 30, 2)),
