@@ -389,8 +389,8 @@ def expand_roofline(prof):
       frontier word read, one 8 B read of the target's visited word per item-word, and 8 B per OR
       into the next frontier.
     impl: what this kernel moves on purpose -- the same plus 8 B per access beyond the method's: the
-      next-frontier word read beside each visited word (two-read scheme), or the second OR of each
-      new word, into the visited bitmap (seen-OR scheme)."""
+      next-frontier word read beside each visited word (two-read scheme); the seen-OR scheme makes
+      the method's accesses only."""
     launches = max(1, prof["expand_launches"])
     method = (4 * prof["edge_items"] + 16 * prof["descriptors"] + 8 * prof["row_words"] + 8 * prof["word_reads"]
               + 8 * prof["word_updates"]) / launches
@@ -403,9 +403,10 @@ def other_rooflines(prof):
     """Method bytes and HBM fraction of the two other level-step kernels, from their exact tallies.
 
     finalize (timed with the compaction that feeds it, one pair per level): 8 B per row id (written by
-      compaction, read by finalize); per row word 16 B (Next read, frontier write); per non-zero word
-      8 B more to clear it, and 16 B to read and write the visited word where finalize does that
-      (two-read scheme; with seen OR the expansion has set the bits); per non-zero word of a
+      compaction, read by finalize); per row word 16 B (Next or, with seen OR, the previous level's
+      visited copy read, frontier write); per non-zero word 8 B more to clear Next or advance the
+      copy; 8 B per finalize access to the visited bitmap (two reads: a read and a write of each
+      non-zero word; seen OR: a read of each row word); per non-zero word of a
       final-state row 16 B for the answer word.  The touch bitmap compaction scans (one bit per row) is left out;
       the tallies include the seeding finalize of each group (one row per source), which is not timed.
     extract (count passes, timed on the extraction stream): 8 B per answer word read."""
@@ -413,7 +414,7 @@ def other_rooflines(prof):
     fl = prof["finalize_launches"]
     if fl and prof["finalize_ms"] / fl > 1e-6:
         b = (8 * prof["finalize_rows"] + 16 * prof["finalize_row_words"] + 8 * prof["finalize_words"]
-             + 16 * prof["finalize_vis_words"] + 16 * prof["finalize_ans_words"]) / fl
+             + 8 * prof["finalize_vis_words"] + 16 * prof["finalize_ans_words"]) / fl
         ms = prof["finalize_ms"] / fl
         a = b / (ms / 1e3) / 1e9
         out["finalize"] = dict(bound="hbm", achieved=round(a, 2), peak=HBM_PEAK_GBPS, unit="GB/s",

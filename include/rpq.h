@@ -220,9 +220,10 @@ typedef struct {
                                 visited check before the update); same results either way.
                                 RPQ_VISIT_TWO_READS: read the visited and the Next word, OR the
                                 rest into Next; finalize adds each level's Next to the visited
-                                bitmap.  RPQ_VISIT_SEEN_OR: read only the visited word, OR the rest
-                                into it and into Next.  0 = seen OR on graphs of 2^22 vertices or
-                                more (where the reads come from HBM), two reads below. */
+                                bitmap.  RPQ_VISIT_SEEN_OR: read only the visited word and OR the
+                                rest into it; finalize takes a row's new bits as the visited word
+                                minus a copy of it kept from the previous level.  0 = seen OR
+                                (faster on every graph measured). */
 } rpq_eval_opts;
 
 #define RPQ_VISIT_TWO_READS 1u
@@ -412,8 +413,10 @@ typedef struct {
                                the worst case (every row of every slot in one level); rows beyond wait
                                for the next iteration, which changes no result (0 = 4, or 1 when a
                                query is length-bounded: such queries need exact depths and require 1) */
-    uint32_t visit;         /* the expansion's visit scheme, as rpq_eval_opts.visit (0 = seen OR on graphs of
-                               2^22 vertices or more, two reads below) */
+    uint32_t visit;         /* the expansion's visit scheme, RPQ_VISIT_TWO_READS or RPQ_VISIT_SEEN_OR
+                               (0 = seen OR on graphs of 2^22 vertices or more, two reads below).
+                               The batched kernel's seen OR ORs each new word into the visited word
+                               and into Next */
 } rpq_batch_opts;
 
 typedef struct {
@@ -738,15 +741,16 @@ typedef struct {
     uint64_t finalize_rows;      /* rows moved from Next to the frontier by finalize */
     uint64_t finalize_row_words; /* their 8-byte words (each read from Next, written to the frontier) */
     uint64_t finalize_words;     /* their non-zero 8-byte Next words (each cleared) */
-    uint64_t finalize_vis_words; /* of those, the ones finalize ORed into Vis (all with two reads,
-                                    none with seen OR, where the expansion set them) */
+    uint64_t finalize_vis_words; /* 8-byte accesses of finalize to Vis: with two reads a read and a
+                                    write of each non-zero word; with seen OR a read of each row
+                                    word (its new bits are Vis minus the previous level's copy) */
     uint64_t finalize_ans_words; /* those of final-state rows (each also ORed into Ans) */
     uint64_t extract_launches;   /* extraction count passes, timed on the extraction stream */
     double extract_ms;
     uint64_t extract_words;      /* 8-byte answer words those passes read */
     uint64_t expand_extra_words; /* 8-byte accesses of the expansion beyond the method's: the Next
-                                    word read beside each visited word (two reads), or the second
-                                    OR of each new word (seen OR) */
+                                    word read beside each visited word (two reads); none with
+                                    seen OR */
 } rpq_profile;
 
 /* Turn event timing of the level kernels on (1) or off (0).  Process-wide. */

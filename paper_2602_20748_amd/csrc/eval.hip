@@ -87,8 +87,8 @@ struct Args {
     const uint64_t* lmask;
     const DevNfa* nfa;
     uint64_t* vis;          // visited bits (with seen_or: also those found at the current level)
-    uint64_t* next;
-    uint64_t* touch;        // one bit per (slot, q, v) row: row has bits in Next
+    uint64_t* next;         // two reads: bits found at this level; seen_or: Vis as of the last finalize
+    uint64_t* touch;        // one bit per (slot, q, v) row: row has bits new at this level
     uint64_t* ans;
     uint64_t* rows0;
     uint64_t* rows1;
@@ -135,15 +135,18 @@ __device__ __forceinline__ void load_nfa(const Args& a, uint32_t* s_delta, uint6
 // kUnroll items per group are loaded before any of them is updated (memory-level parallelism).
 //
 // New bits of a target word (Section 4, the visited check before the atomic update) are found in
-// one of two ways, both giving the same Next:
+// one of two ways, both giving the same frontier:
 //   two reads  the visited word and the Next word are read; bits in neither are ORed into Next,
-//              and finalize ORs each level's Next into the visited bitmap;
-//   seen OR    only the visited word is read; bits not in it are ORed into both it and Next.  The
-//              visited bitmap then also holds the bits found so far at this level (so it filters
-//              as well as the two reads together), and finalize leaves it alone.  One read and two
-//              ORs per new word instead of two reads and one OR: better where the reads come from
-//              HBM (R-MAT scale 23: 3.41 -> 3.17 s a step), worse where they hit in cache and the
-//              atomics bound the kernel (scale 18: 606 -> 634 ms).
+//              and finalize ORs each level's Next into the visited bitmap and clears Next;
+//   seen OR    only the visited word is read; bits not in it are ORed into it alone.  The visited
+//              bitmap then also holds the bits found so far at this level, so it filters as well as
+//              the two reads together.  The second bitmap holds the visited bits as of the last
+//              finalize, and finalize takes a listed row's new bits as Vis & ~that, then advances
+//              it.  One read and one OR per new word, the method's own accesses; finalize reads one
+//              more word per row word, and the second bitmap is cleared with Vis for every group.
+//              Faster at both scales measured: R-MAT 23, 3.41 -> 2.91 s a step (expansion 2.11 ms
+//              a launch when each new word was also ORed into a Next bitmap, 1.53 ms now); R-MAT
+//              18, 603 -> 541 ms (expansion 1.43 -> 1.15 ms).
 // ------------------------------------------------------------------------------------------------
 constexpr int kUnroll = 8;
 
@@ -218,7 +221,6 @@ __device__ __forceinline__ void expand_segments(const Args& a, const uint32_t* s
                     nb[u] = f[u] & ~sw[u];
                     if (nb[u]) {
                         or_relaxed(&a.vis[(uint64_t)r[u] * K + k], nb[u]);
-                        or_relaxed(&a.next[(uint64_t)r[u] * K + k], nb[u]);
                     }
                 }
             } else {
@@ -412,13 +414,25 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_wo
         // word phase
         for (uint32_t j = 0; j < n_here; j += GS * kUnroll) {
             uint32_t r[kUnroll], an[kUnroll];
-            uint64_t nk[kUnroll];
+            uint64_t nk[kUnroll], ov[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t idx = j + u * GS + grp;
                 r[u] = __shfl(my_row, idx & 63, 64);
                 an[u] = __shfl(my_ans, idx & 63, 64);
-                nk[u] = idx < n_here ? a.next[(uint64_t)r[u] * K + k] : 0;
+                nk[u] = ov[u] = 0;
+                if (idx < n_here) {
+                    if (a.seen_or) {
+                        ov[u] = a.next[(uint64_t)r[u] * K + k];
+                        nk[u] = a.vis[(uint64_t)r[u] * K + k];
+                    } else {
+                        nk[u] = a.next[(uint64_t)r[u] * K + k];
+                    }
+                }
+            }
+            if (a.seen_or) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) nk[u] &= ~ov[u];
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -427,7 +441,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Args a, int p, int count_wo
                 if (idx < n_here) {
                     rows[(e0 + idx) * K + k] = nk[u];
                     if (nk[u]) {
-                        a.next[(uint64_t)r[u] * K + k] = 0;
+                        // seen OR: the snapshot catches up with Vis.  Two reads: Next is cleared.
+                        a.next[(uint64_t)r[u] * K + k] = a.seen_or ? (ov[u] | nk[u]) : 0;
                         // a row is on the list once, and nothing else writes its Vis word in this
                         // kernel: a plain read-modify-write (an atomic OR cost 0.82 vs 0.69 ms a
                         // launch).  With seen OR the expansion has already set these bits.
@@ -523,8 +538,10 @@ __global__ __launch_bounds__(kBlock) void k_seed(Args a, const uint32_t* __restr
         const uint32_t q = __ffs(init) - 1;
         init &= init - 1;
         const uint64_t row = ((uint64_t)slot * a.Q + q) * a.V + s;
-        or_relaxed(&a.next[row * K + k], bit);
-        if (a.seen_or) or_relaxed(&a.vis[row * K + k], bit);
+        if (a.seen_or)
+            or_relaxed(&a.vis[row * K + k], bit);
+        else
+            or_relaxed(&a.next[row * K + k], bit);
         or_relaxed(&a.touch[row >> 6], 1ull << (row & 63));
     }
 }
@@ -782,9 +799,6 @@ constexpr uint64_t kTargetInFlight = 65536;
 constexpr uint64_t kWorkspaceBudget = 64ull << 30;
 constexpr uint64_t kUnitBudget = 96ull << 30;
 constexpr uint32_t kDefaultChunk = 16;
-// Graphs from this many vertices on take the seen-OR visit scheme by default (the expansion's
-// comment has the measurements at scales 18 and 23).
-constexpr uint32_t kSeenOrFrom = 1u << 22;
 
 uint32_t max_default_width(uint32_t V) { return V >= (1u << 22) ? 4096 : 2048; }
 
@@ -814,7 +828,9 @@ int make_layout(const rpq_graph* g, const DevNfa& dn, uint64_t n_sources, uint32
     }
     x.K = x.W / 64;
     x.H = (o && o->chunk_edges) ? o->chunk_edges : kDefaultChunk;
-    x.seen_or = (o && o->visit) ? o->visit == RPQ_VISIT_SEEN_OR : g->V >= kSeenOrFrom;
+    // seen OR unless asked otherwise: the faster scheme on both R-MAT 18 and R-MAT 23 (the
+    // expansion's comment has the figures)
+    x.seen_or = (o && o->visit) ? o->visit == RPQ_VISIT_SEEN_OR : 1u;
     if (x.H > 65535) {
         rpq::set_error("chunk_edges must be <= 65535");
         return RPQ_EINVAL;
@@ -1491,6 +1507,7 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
         // the bitmap's previous group must be extracted before it is cleared for this one
         if (side.stream && grp >= 2) RPQ_HIP(hipStreamWaitEvent(stream, side.extracted[buf], 0));
         RPQ_TRY(rpq::fill_u64(a.vis, (uint64_t)G_eff * x.Q * x.V * x.K, 0, stream));
+        if (x.seen_or) RPQ_TRY(rpq::fill_u64(a.next, (uint64_t)G_eff * x.Q * x.V * x.K, 0, stream));
         RPQ_TRY(rpq::fill_u64(a.ans, (uint64_t)G_eff * x.V * x.K, 0, stream));
         hipLaunchKernelGGL(k_seed, dim3((unsigned)(((uint64_t)G_eff * x.W + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                            stream, a, sources, n_sources, gbase, G_eff, x.W, x.K);
@@ -1596,10 +1613,12 @@ int eval_core(rpq_graph_t g, const rpq_nfa* nfa, const uint32_t* sources, uint64
             pr.acc.finalize_rows += stage[C_FROWS];
             pr.acc.finalize_row_words += stage[C_FROWS] * x.K;
             pr.acc.finalize_words += stage[C_FWORDS];
-            pr.acc.finalize_vis_words += x.seen_or ? 0 : stage[C_FWORDS];
-            // beyond the method's bytes: the Next word read beside each visited word (two reads),
-            // or the second OR of each new word (seen OR)
-            pr.acc.expand_extra_words += x.seen_or ? stage[C_WUPD] : stage[C_WREAD];
+            // 8-byte accesses of finalize to Vis: a read of every row word (seen OR), or a read and
+            // a write of every non-zero word (two reads)
+            pr.acc.finalize_vis_words += x.seen_or ? stage[C_FROWS] * x.K : 2 * stage[C_FWORDS];
+            // beyond the method's bytes: the Next word read beside each visited word (two reads);
+            // seen OR makes the method's accesses only
+            pr.acc.expand_extra_words += x.seen_or ? 0 : stage[C_WREAD];
             pr.acc.finalize_ans_words += stage[C_FANS];
             pr.acc.edge_items += stage[C_ITEMS];
             pr.acc.descriptors += stage[C_DESCS];

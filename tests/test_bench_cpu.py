@@ -53,9 +53,9 @@ def test_expand_roofline_counts_one_visited_word_read_per_item_word():
     method, impl, avg_ms = bench.expand_roofline(prof)
     assert method == 4 * 13_070_000 + 16 * 1_414_000 + 8 * 45_260_000 + 8 * 275_400_000 + 8 * 56_380_000
     assert impl - method == 8 * 275_400_000
-    # seen OR: the extra accesses are the second OR of each new word
-    method2, impl2, _ = bench.expand_roofline(dict(prof, expand_extra_words=2 * 56_380_000))
-    assert method2 == method and impl2 - method2 == 8 * 56_380_000
+    # seen OR: the kernel makes the method's accesses only
+    method2, impl2, _ = bench.expand_roofline(dict(prof, expand_extra_words=0))
+    assert method2 == method and impl2 == method2
     assert abs(avg_ms - 1.4714) < 1e-12
     assert abs(method / (avg_ms / 1e3) / 8e12 - 0.2626) < 5e-4
 
@@ -64,7 +64,7 @@ def test_finalize_and_extract_rooflines_from_their_tallies():
     # two finalize launches over 1,000 rows of 64 words, 30,000 of them non-zero and 5,000 of those in
     # final-state rows; one extraction count pass over 1,000,000 answer words
     prof = dict(finalize_launches=2, finalize_ms=2 * 0.5, finalize_rows=2000, finalize_row_words=128_000,
-                finalize_words=60_000, finalize_vis_words=60_000, finalize_ans_words=10_000, extract_launches=1,
+                finalize_words=60_000, finalize_vis_words=2 * 60_000, finalize_ans_words=10_000, extract_launches=1,
                 extract_ms=0.25, extract_words=1_000_000)
     out = bench.other_rooflines(prof)
     fin_bytes = (8 * 2000 + 16 * 128_000 + 24 * 60_000 + 16 * 10_000) / 2
@@ -72,8 +72,8 @@ def test_finalize_and_extract_rooflines_from_their_tallies():
     assert abs(out["finalize"]["achieved"] - round(fin_bytes / 0.5e-3 / 1e9, 2)) < 1e-9
     assert abs(out["extract"]["achieved"] - 8e6 / 0.25e-3 / 1e9) < 1e-6
     assert abs(out["extract"]["frac"] - round(8e6 / 0.25e-3 / 1e9 / 8000, 5)) < 1e-9
-    # seen OR: finalize leaves the visited words alone
-    fin2 = (8 * 2000 + 16 * 128_000 + 8 * 60_000 + 16 * 10_000) / 2
-    assert bench.other_rooflines(dict(prof, finalize_vis_words=0))["finalize"]["alg_bytes_per_launch"] == round(fin2, 1)
+    # seen OR: finalize reads the visited word of every row word and writes none
+    fin2 = (8 * 2000 + 16 * 128_000 + 8 * 60_000 + 8 * 128_000 + 16 * 10_000) / 2
+    assert bench.other_rooflines(dict(prof, finalize_vis_words=128_000))["finalize"]["alg_bytes_per_launch"] == round(fin2, 1)
     # no launches, no entry
     assert bench.other_rooflines(dict(prof, finalize_launches=0, extract_launches=0)) == {}
